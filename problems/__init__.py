@@ -1,0 +1,19 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This package builds the linear systems ``A u = f`` that the solver is run on
+(sparse matrices in CSR form and right-hand sides).  It holds none of the
+multigrid method's arithmetic: no strength test, aggregation, smoothing,
+transfer operator or Krylov step lives here, so both the oracle and the
+device path can take their inputs from it without sharing any of the method.
+"""
+
+from .grids import (  # noqa: F401
+    CSR,
+    poisson3d,
+    poisson3d_nnz,
+    gaussian_field,
+    diffusion3d,
+    rhs_ones,
+    rhs_uniform,
+    tridiag1d,
+)

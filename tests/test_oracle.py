@@ -1,0 +1,368 @@
+"""Pins for the oracle (CPU only).
+
+Each test checks the oracle against something other than itself: the
+hand-derived worked example, closed forms, invariants the mathematics fixes,
+special cases that reduce to a dense solve, and brute force on tiny grids.
+"""
+
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import problems
+
+
+def load_golden(path):
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *vals = line.split()
+            out[key] = [Fraction(v) for v in vals]
+    return out
+
+
+@pytest.fixture(scope="module")
+def pw(golden_dir):
+    return load_golden(os.path.join(golden_dir, "pw_1d_laplacian.txt"))
+
+
+def _f(vals):
+    return np.array([float(v) for v in vals])
+
+
+def pw_hierarchy():
+    A = problems.tridiag1d(9)
+    return oracle.setup(A, oracle.Params(coarse_enough=3))
+
+
+# ---------------------------------------------------------------- worked example
+
+
+def test_worked_example_setup(pw):
+    h = pw_hierarchy()
+    assert h.nlevels == 2
+    lv = h.levels[0]
+    assert lv.agg.tolist() == [int(a) for a in pw["agg"]]
+    assert lv.omega == pytest.approx(float(pw["omega"][0]), abs=1e-16)
+    P = _f(pw["P"]).reshape(9, 3)
+    assert np.max(np.abs(lv.P.toarray() - P)) <= 1e-15
+    assert np.array_equal(lv.R.toarray(), lv.P.toarray().T)
+    Ac = _f(pw["Ac"]).reshape(3, 3)
+    assert np.max(np.abs(h.levels[1].A.toarray() - Ac)) <= 1e-15
+    assert np.max(np.abs(lv.m - _f(pw["m"]))) <= 1e-16
+
+
+def test_worked_example_vcycle(pw):
+    h = pw_hierarchy()
+    lv = h.levels[0]
+    r = np.ones(9)
+    z0 = lv.m * r
+    f_c = lv.R @ (r - lv.A @ z0)
+    assert np.max(np.abs(f_c - _f(pw["f_c"]))) <= 4e-15
+    z_c = oracle.vcycle(h, f_c, 1)
+    assert np.max(np.abs(z_c - _f(pw["z_c"]))) / 10.2 <= 1e-15
+    V = oracle.vcycle(h, r)
+    ref = _f(pw["V"])
+    assert np.max(np.abs(V - ref)) / np.max(np.abs(ref)) <= 1e-15
+
+
+# ---------------------------------------------------------------- closed forms
+
+
+def test_spai0_closed_form_poisson():
+    N = 6
+    A = problems.poisson3d(N).to_scipy()
+    m = oracle.spai0_diagonal(A)
+    idx = np.arange(N**3)
+    c = [idx % N, (idx // N) % N, idx // (N * N)]
+    nb = sum(((ci > 0).astype(int) + (ci < N - 1).astype(int)) for ci in c)
+    # a_ii = 6, sum_j a_ij^2 = 36 + (number of neighbours)
+    expect = 6.0 / (36.0 + nb)
+    assert np.array_equal(m, expect)
+    assert m[idx[(nb == 6)][0]] == 6.0 / 42.0  # interior 1/7
+    assert set(np.round(1.0 / m * 6).astype(int).tolist()) == {39, 40, 41, 42}
+
+
+def test_jacobi_diagonal_closed_form():
+    A = problems.poisson3d(4).to_scipy()
+    m = oracle.jacobi_diagonal(A, 0.72)
+    assert np.allclose(m, 0.12, rtol=0, atol=1e-17)
+
+
+def test_level1_poisson_all_strong_and_filter_identity():
+    A = problems.poisson3d(6).to_scipy()
+    S = oracle.strength_graph(A, 0.08)
+    off = A - sp.diags(A.diagonal())
+    off.eliminate_zeros()
+    assert (S != (off != 0)).nnz == 0
+    A_F, d_F = oracle.filtered_matrix(A, S)
+    assert abs(A_F - A).max() == 0
+    isolated = np.diff(S.indptr) == 0
+    assert oracle.prolongator_damping(A_F, d_F, isolated) == pytest.approx(2.0 / 3.0, abs=1e-16)
+
+
+def test_strength_threshold_is_strict_and_squared():
+    # 2x2 with a_01^2 exactly eps^2 a_00 a_11 is weak; slightly above is strong.
+    eps = 0.25
+    a00, a11 = 4.0, 1.0
+    a01 = -eps * np.sqrt(a00 * a11)  # = -0.5, exact in binary
+    for val, expect in ((a01, 0), (a01 * 1.0000001, 1)):
+        A = sp.csr_matrix(np.array([[a00, val], [val, a11]]))
+        S = oracle.strength_graph(A, eps)
+        assert S.nnz == 2 * expect
+
+
+def test_strength_symmetrised_for_nonsymmetric():
+    A = sp.csr_matrix(np.array([[1.0, -0.5, 0.0], [-0.01, 1.0, -0.5], [0.0, -0.5, 1.0]]))
+    S = oracle.strength_graph(A, 0.08).toarray()
+    assert np.array_equal(S, S.T)
+    assert S[0, 1] == 1 and S[1, 0] == 1  # 1->0 weak, but 0->1 strong
+
+
+def test_filtered_matrix_lumps_weak_entries():
+    A = sp.csr_matrix(np.array([[4.0, -1.0, -0.01], [-1.0, 4.0, -1.0], [-0.01, -1.0, 4.0]]))
+    S = oracle.strength_graph(A, 0.08)
+    A_F, d_F = oracle.filtered_matrix(A, S)
+    D = A_F.toarray()
+    assert D[0, 2] == 0 and D[2, 0] == 0
+    assert D[0, 0] == pytest.approx(3.99) and D[1, 1] == 4.0
+    assert np.allclose(D.sum(axis=1), A.toarray().sum(axis=1))
+
+
+# ---------------------------------------------------------------- invariants
+
+
+def _check_partition(S, agg):
+    n = S.shape[0]
+    isolated = np.diff(S.indptr) == 0
+    assert np.all(agg[isolated] == -1)
+    assert np.all(agg[~isolated] >= 0)
+    nc = agg.max() + 1
+    assert set(np.unique(agg[agg >= 0]).tolist()) == set(range(nc))
+    # each aggregate is connected in the strong graph
+    for a in range(nc):
+        members = np.nonzero(agg == a)[0]
+        sub = S[members][:, members]
+        ncomp, _ = sp.csgraph.connected_components(sub, directed=False)
+        assert ncomp == 1
+    return nc
+
+
+@pytest.mark.parametrize("case", ["poisson", "diffusion", "convection"])
+def test_aggregation_invariants(case):
+    N = 10
+    if case == "poisson":
+        A = problems.poisson3d(N).to_scipy()
+    elif case == "diffusion":
+        A = problems.diffusion3d(N, problems.gaussian_field(N, 2.0, 8.0, 1)).to_scipy()
+    else:
+        A = problems.diffusion3d(N, problems.gaussian_field(N, 2.0, 8.0, 1),
+                                 velocity=(50.0, 25.0, 12.5)).to_scipy()
+    S = oracle.strength_graph(A, 0.08)
+    agg = oracle.aggregate(S)
+    nc = _check_partition(S, agg)
+    assert 0 < nc < A.shape[0]
+    assert np.array_equal(agg, oracle.aggregate(S))
+
+
+def _graph(n, edges):
+    r = [a for a, b in edges] + [b for a, b in edges]
+    c = [b for a, b in edges] + [a for a, b in edges]
+    return sp.csr_matrix((np.ones(len(r)), (r, c)), shape=(n, n))
+
+
+def test_aggregation_phase1_natural_order():
+    # path 0-...-6 plus isolated node 7: node 0 -> {0,1}; node 2 touches the
+    # aggregated 1 -> skipped; node 3 -> {2,3,4}; node 5 skipped; node 6 -> {5,6}
+    S = _graph(8, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (5, 6)])
+    assert oracle.aggregate(S).tolist() == [0, 0, 1, 1, 1, 2, 2, -1]
+
+
+def test_aggregation_phase2_joins_lowest_index_neighbour():
+    # node 4 touches node 1 (aggregate 0) and node 3 (aggregate 1): it joins the
+    # aggregate of the lower-index neighbour, node 1
+    S = _graph(5, [(0, 1), (2, 3), (1, 4), (3, 4)])
+    assert oracle.aggregate(S).tolist() == [0, 0, 1, 1, 0]
+    # and with the indices of the two aggregates' members swapped it follows them
+    S = _graph(5, [(0, 3), (1, 2), (3, 4), (1, 4)])
+    # phase 1: node 0 -> {0,3}; node 1 -> {1,2}; node 4 touches 1 and 3 -> lowest is 1
+    assert oracle.aggregate(S).tolist() == [0, 1, 1, 0, 1]
+
+
+def test_aggregation_partition_random_graphs():
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        n = 60
+        M = sp.random(n, n, density=0.05, random_state=rng, format="csr")
+        S = ((M + M.T) > 0).astype(np.int8).tocsr()
+        S.setdiag(0)
+        S.eliminate_zeros()
+        S.sort_indices()
+        agg = oracle.aggregate(S)
+        _check_partition(S, agg)
+
+
+def test_prolongator_rowsum_invariant():
+    N = 8
+    A = problems.poisson3d(N).to_scipy()
+    h = oracle.setup(A, oracle.Params(coarse_enough=50))
+    P = h.levels[0].P
+    rowsum = np.asarray(P.sum(axis=1)).ravel()
+    zero_rows = np.abs(np.asarray(A.sum(axis=1)).ravel()) == 0
+    assert zero_rows.sum() > 0
+    assert np.max(np.abs(rowsum[zero_rows] - 1.0)) <= 1e-15
+    # boundary rows lose mass (A row sum > 0) -> P row sums < 1
+    assert np.all(rowsum[~zero_rows] < 1.0)
+
+
+@pytest.mark.parametrize("case", ["poisson", "diffusion"])
+def test_galerkin_symmetric_spd(case):
+    N = 12
+    if case == "poisson":
+        A = problems.poisson3d(N).to_scipy()
+    else:
+        A = problems.diffusion3d(N, problems.gaussian_field(N, 2.0, 8.0, 1)).to_scipy()
+    h = oracle.setup(A, oracle.Params(coarse_enough=30))
+    assert h.nlevels >= 3
+    for l in range(1, h.nlevels):
+        Ac = h.levels[l].A.toarray()
+        assert np.max(np.abs(Ac - Ac.T)) <= 1e-14 * np.max(np.abs(Ac))
+        np.linalg.cholesky(Ac)
+        # Galerkin identity against the dense triple product
+        prev = h.levels[l - 1]
+        dense = prev.P.toarray().T @ prev.A.toarray() @ prev.P.toarray()
+        assert np.max(np.abs(Ac - dense)) <= 1e-13 * np.max(np.abs(dense))
+
+
+def test_two_grid_closed_form():
+    # npre = npost = 0, two levels: V(r) = P A_c^-1 R r
+    A = problems.poisson3d(6).to_scipy()
+    prm = oracle.Params(coarse_enough=100, npre=0, npost=0)
+    h = oracle.setup(A, prm)
+    assert h.nlevels == 2
+    P = h.levels[0].P.toarray()
+    Ac = h.levels[1].A.toarray()
+    r = np.random.default_rng(1).standard_normal(A.shape[0])
+    expect = P @ np.linalg.solve(Ac, P.T @ r)
+    got = oracle.vcycle(h, r)
+    assert np.max(np.abs(got - expect)) <= 1e-13 * np.max(np.abs(expect))
+
+
+def _vcycle_matrix(h, n):
+    return np.column_stack([oracle.vcycle(h, e) for e in np.eye(n)])
+
+
+@pytest.mark.parametrize("relax", ["spai0", "jacobi"])
+def test_vcycle_operator_symmetric_spd_linear(relax):
+    N = 7
+    A = problems.poisson3d(N).to_scipy()
+    h = oracle.setup(A, oracle.Params(coarse_enough=10, relax=relax))
+    assert h.nlevels >= 3
+    B = _vcycle_matrix(h, A.shape[0])
+    assert np.max(np.abs(B - B.T)) <= 1e-13 * np.max(np.abs(B))
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+    rng = np.random.default_rng(2)
+    x, y = rng.standard_normal((2, A.shape[0]))
+    lhs = oracle.vcycle(h, 2.5 * x - 0.75 * y)
+    rhs = 2.5 * oracle.vcycle(h, x) - 0.75 * oracle.vcycle(h, y)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-14 * np.max(np.abs(rhs))
+
+
+def test_single_level_is_exact():
+    A = problems.poisson3d(10)  # 1000 unknowns <= 3000: one level, V = A^-1
+    f = problems.rhs_ones(A.n)
+    h = oracle.setup(A)
+    assert h.nlevels == 1
+    x, info, _ = oracle.solve(A, f, h=h)
+    assert info.iters == 1
+    xd = np.linalg.solve(A.to_scipy().toarray(), f)
+    assert np.max(np.abs(x - xd)) / np.max(np.abs(xd)) < 1e-13
+    x, info, _ = oracle.solve(A, f, oracle.Params(solver="bicgstab"), h=h)
+    assert info.iters == 1
+
+
+def _tiny_cases():
+    out = []
+    for N in (3, 5, 8):
+        out.append(("poisson", N, problems.poisson3d(N), "cg", "spai0"))
+    g = problems.gaussian_field(8, 2.0, 8.0, 1)
+    out.append(("diffusion", 8, problems.diffusion3d(8, g), "cg", "spai0"))
+    out.append(("diffusion-bicg", 8, problems.diffusion3d(8, g), "bicgstab", "jacobi"))
+    out.append(("convection", 8, problems.diffusion3d(8, g, velocity=(50.0, 25.0, 12.5)),
+                "bicgstab", "jacobi"))
+    return out
+
+
+@pytest.mark.parametrize("name,N,A,solver,relax", _tiny_cases(), ids=lambda v: str(v) if isinstance(v, (str, int)) else "")
+def test_whole_solve_vs_dense(name, N, A, solver, relax):
+    f = problems.rhs_uniform(A.n, seed=0)
+    prm = oracle.Params(solver=solver, relax=relax, coarse_enough=20)
+    x, info, h = oracle.solve(A, f, prm)
+    D = A.to_scipy().toarray()
+    xd = np.linalg.solve(D, f)
+    kappa = np.linalg.cond(D)
+    assert info.converged
+    assert info.true_rel_resid <= 1e-8
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= kappa * 1e-8
+
+
+def test_mesh_independent_iterations():
+    its = []
+    for N in (16, 24, 32, 40, 48):
+        A = problems.poisson3d(N)
+        _, info, h = oracle.solve(A, problems.rhs_uniform(A.n, 0), oracle.Params())
+        assert info.converged
+        its.append(info.iters)
+    assert max(its) / min(its) <= 1.5, its
+
+
+def test_mixed_vcycle_is_fp32_close_but_not_fp64():
+    A = problems.poisson3d(16)
+    h = oracle.setup(A)
+    r = problems.rhs_uniform(A.n, 0)
+    z64 = oracle.vcycle(h, r)
+    z32 = oracle.vcycle_fp32(h, r)
+    rel = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
+    assert 1e-9 < rel < 1e-5
+
+
+def test_fp32_csr_product_accumulates_in_fp32():
+    # The mixed oracle relies on SciPy's FP32 CSR product accumulating in FP32.
+    n = 4000
+    rng = np.random.default_rng(0)
+    row = np.zeros(n, dtype=np.int64)
+    col = np.arange(n)
+    val = rng.random(n).astype(np.float32)
+    x = rng.random(n).astype(np.float32)
+    A = sp.csr_matrix((val, (row, col)), shape=(1, n))
+    y = (A @ x)[0]
+    assert y.dtype == np.float32
+    acc = np.float32(0)
+    for v, xx in zip(val, x):
+        acc = np.float32(acc + np.float32(v * xx))
+    assert y == acc
+
+
+def test_pcg_and_bicgstab_report_iterations_and_zero_rhs():
+    A = problems.poisson3d(16)
+    f0 = np.zeros(A.n)
+    x, info, _ = oracle.solve(A, f0)
+    assert info.iters == 0 and not x.any()
+    x, info, _ = oracle.solve(A, problems.rhs_ones(A.n), oracle.Params(max_iter=1))
+    assert info.iters == 1 and not info.converged
+
+
+def test_coarse_lu_solves_coarsest_system():
+    A = problems.poisson3d(16)
+    h = oracle.setup(A)
+    Ac = h.levels[-1].A.toarray()
+    b = np.random.default_rng(3).standard_normal(Ac.shape[0])
+    z = oracle.vcycle(h, b, h.nlevels - 1)
+    assert np.linalg.norm(Ac @ z - b) / np.linalg.norm(b) < 1e-13

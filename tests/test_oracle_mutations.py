@@ -1,0 +1,135 @@
+"""Planted mistakes in the oracle must be caught by its pins (CPU only).
+
+Each case swaps one oracle step for a plausible wrong version (a dropped term,
+a wrong sign, index or exponent, a missing transpose or symmetrisation) and
+checks that at least one pin in ``test_oracle`` then fails.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import oracle.sa_amg as sa
+import problems
+from tests import test_oracle as pins
+
+
+def _pins_fail(golden):
+    """True when the worked-example or dense-solve pins reject the oracle."""
+    pw = pins.load_golden(golden)
+    checks = [
+        lambda: pins.test_worked_example_setup(pw),
+        lambda: pins.test_worked_example_vcycle(pw),
+        lambda: pins.test_galerkin_symmetric_spd("diffusion"),
+        lambda: pins.test_spai0_closed_form_poisson(),
+        lambda: pins.test_aggregation_phase2_joins_lowest_index_neighbour(),
+        lambda: pins.test_strength_symmetrised_for_nonsymmetric(),
+        lambda: pins.test_filtered_matrix_lumps_weak_entries(),
+        lambda: pins.test_whole_solve_vs_dense(*pins._tiny_cases()[-1]),
+        lambda: pins.test_vcycle_operator_symmetric_spd_linear("spai0"),
+    ]
+    for chk in checks:
+        try:
+            chk()
+        except (AssertionError, ValueError, np.linalg.LinAlgError, sa.Breakdown):
+            return True
+    return False
+
+
+def _spai0_wrong_numerator(A):
+    A = sa._as_csr(A)
+    return A.diagonal() ** 2 / np.asarray(A.multiply(A).sum(axis=1)).ravel()
+
+
+def _aggregate_highest_neighbour(S):
+    n = S.shape[0]
+    ptr, nbr = S.indptr.tolist(), S.indices.tolist()
+    agg = [sa.UNAGGREGATED] * n
+    cnt = 0
+    for i in range(n):
+        if ptr[i] == ptr[i + 1]:
+            agg[i] = sa.ISOLATED
+    for i in range(n):
+        if agg[i] == sa.UNAGGREGATED and all(agg[j] == sa.UNAGGREGATED for j in nbr[ptr[i]:ptr[i + 1]]):
+            agg[i] = cnt
+            for j in nbr[ptr[i]:ptr[i + 1]]:
+                agg[j] = cnt
+            cnt += 1
+    snap = list(agg)
+    for i in range(n):
+        if agg[i] == sa.UNAGGREGATED:
+            for j in reversed(nbr[ptr[i]:ptr[i + 1]]):  # wrong: highest index
+                if snap[j] >= 0:
+                    agg[i] = snap[j]
+                    break
+    return np.array(agg, dtype=np.int64)
+
+
+def _strength_not_symmetrised(A, eps):
+    A = sa._as_csr(A)
+    d = A.diagonal()
+    rows = sa._row_of_entry(A)
+    strong = (A.indices != rows) & (A.data ** 2 > eps * eps * np.abs(d[rows] * d[A.indices]))
+    n = A.shape[0]
+    S = sp.csr_matrix((np.ones(int(strong.sum()), dtype=np.int8), (rows[strong], A.indices[strong])),
+                      shape=(n, n))
+    S.sort_indices()
+    return S
+
+
+def _filter_drops_weak(A, S):
+    A_F, d_F = _orig["filtered_matrix"](A, S)
+    d = sa._as_csr(A).diagonal()
+    return (A_F - sp.diags(d_F) + sp.diags(d)).tocsr(), d
+
+
+def _vcycle_wrong_sign(h, f, level=0):
+    lv = h.levels[level]
+    if level == h.nlevels - 1:
+        return sa.sla.lu_solve(h.lu, f)
+    z = lv.m * f
+    r = f - lv.A @ z
+    z = z + lv.P @ _vcycle_wrong_sign(h, lv.R @ r, level + 1)
+    return z - lv.m * (f - lv.A @ z)  # wrong sign in the post-sweep
+
+
+def _vcycle_restrict_tentative(h, f, level=0):
+    lv = h.levels[level]
+    if level == h.nlevels - 1:
+        return sa.sla.lu_solve(h.lu, f)
+    z = lv.m * f
+    r = f - lv.A @ z
+    fc = sa.tentative_prolongator(lv.agg).T @ r  # wrong: restricts with P_hat^T
+    z = z + lv.P @ _vcycle_restrict_tentative(h, fc, level + 1)
+    return z + lv.m * (f - lv.A @ z)
+
+
+_orig = {"filtered_matrix": sa.filtered_matrix, "prolongator_damping": sa.prolongator_damping}
+
+
+MUTATIONS = {
+    "spai0_numerator": ("spai0_diagonal", _spai0_wrong_numerator),
+    "damping_constant": ("prolongator_damping", lambda A_F, d_F, iso: 0.5 * _orig["prolongator_damping"](A_F, d_F, iso)),
+    "phase2_highest": ("aggregate", _aggregate_highest_neighbour),
+    "strength_unsymmetrised": ("strength_graph", _strength_not_symmetrised),
+    "filter_drops_weak": ("filtered_matrix", _filter_drops_weak),
+    "post_sweep_sign": ("vcycle", _vcycle_wrong_sign),
+    "restriction_tentative": ("vcycle", _vcycle_restrict_tentative),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, monkeypatch, golden_dir):
+    import os
+
+    attr, fn = MUTATIONS[name]
+    monkeypatch.setattr(sa, attr, fn)
+    monkeypatch.setattr(oracle, attr, fn)
+    assert _pins_fail(os.path.join(golden_dir, "pw_1d_laplacian.txt")), name
+
+
+def test_pins_pass_unmutated(golden_dir):
+    import os
+
+    assert not _pins_fail(os.path.join(golden_dir, "pw_1d_laplacian.txt"))

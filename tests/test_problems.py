@@ -1,0 +1,112 @@
+"""Pins for the seeded input generators (CPU)."""
+
+import numpy as np
+import pytest
+
+import problems
+
+
+def test_poisson_sizes_match_paper_150():
+    # Section 4.1 quotes 3,375,000 unknowns and 23,490,000 nonzeros at 150^3.
+    A = problems.poisson3d(150)
+    assert A.n == 3_375_000
+    assert A.nnz == 23_490_000
+    assert problems.poisson3d_nnz(150) == 23_490_000
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 7, 16, 32])
+def test_poisson_nnz_closed_form(N):
+    A = problems.poisson3d(N)
+    assert A.nnz == 7 * N**3 - 6 * N**2
+    assert A.row_ptr.dtype == np.int64 and A.col.dtype == np.int32
+
+
+def test_other_sizes_closed_form():
+    assert problems.poisson3d_nnz(32) == 223_232
+    assert problems.poisson3d_nnz(128) == 14_581_760
+    assert problems.poisson3d_nnz(200) == 55_760_000
+
+
+def test_poisson_structure():
+    N = 5
+    A = problems.poisson3d(N)
+    S = A.to_scipy()
+    D = S.toarray()
+    assert np.array_equal(D, D.T)
+    assert np.all(np.diag(D) == 6.0)
+    # columns strictly ascending per row and diagonal present
+    for i in range(A.n):
+        c = A.col[A.row_ptr[i]:A.row_ptr[i + 1]]
+        assert np.all(np.diff(c) > 0)
+        assert i in c
+    # 7-point coupling: only unit-distance lexicographic neighbours
+    i, j = np.nonzero(D)
+    off = np.abs(i - j)
+    assert set(off.tolist()) <= {0, 1, N, N * N}
+
+
+def test_diffusion_unit_coefficient_is_poisson():
+    N = 9
+    P = problems.poisson3d(N)
+    Dz = problems.diffusion3d(N, np.zeros(N**3))
+    assert np.array_equal(P.row_ptr, Dz.row_ptr)
+    assert np.array_equal(P.col, Dz.col)
+    assert np.array_equal(P.val, Dz.val)
+
+
+def test_diffusion_symmetric_and_m_matrix():
+    N = 8
+    g = problems.gaussian_field(N, sigma=2.0, ell=8.0, seed=1)
+    A = problems.diffusion3d(N, g).to_scipy().toarray()
+    assert np.allclose(A, A.T, rtol=0, atol=1e-12 * np.abs(A).max())
+    off = A - np.diag(np.diag(A))
+    assert np.all(off <= 0)
+    # weak diagonal dominance with strict dominance on boundary rows
+    assert np.all(np.diag(A) + off.sum(axis=1) >= -1e-12)
+    np.linalg.cholesky(A)
+
+
+def test_convection_m_matrix_zero_interior_rowsums():
+    N = 7
+    Pe = 50.0
+    v = (1.0 * Pe, 0.5 * Pe, 0.25 * Pe)
+    A = problems.diffusion3d(N, None, velocity=v).to_scipy().toarray()
+    off = A - np.diag(np.diag(A))
+    assert np.all(off <= 0)
+    assert not np.allclose(A, A.T)
+    idx = np.arange(N**3)
+    i, j, k = idx % N, (idx // N) % N, idx // (N * N)
+    interior = (i > 0) & (i < N - 1) & (j > 0) & (j < N - 1) & (k > 0) & (k < N - 1)
+    rs = A.sum(axis=1)
+    assert np.allclose(rs[interior], 0.0, atol=1e-12)
+    assert np.all(rs[~interior] > 0)
+    # upwind coefficient -v_x h on the -x neighbour of an interior node
+    h = 1.0 / (N + 1)
+    c = int(np.nonzero(interior)[0][0])
+    assert A[c, c - 1] == pytest.approx(-1.0 - v[0] * h, rel=1e-14)
+    assert A[c, c + 1] == pytest.approx(-1.0, rel=1e-14)
+
+
+def test_gaussian_field_statistics_and_seed():
+    N = 48
+    g1 = problems.gaussian_field(N, sigma=1.0, ell=8.0, seed=3)
+    g2 = problems.gaussian_field(N, sigma=1.0, ell=8.0, seed=3)
+    g3 = problems.gaussian_field(N, sigma=1.0, ell=8.0, seed=4)
+    assert np.array_equal(g1, g2)
+    assert not np.array_equal(g1, g3)
+    # variance is sigma^2 by construction (unit-norm kernel); sample estimate
+    # over a correlated field is loose
+    assert 0.3 < g1.var() < 2.0
+    # correlation at lag ell along x is exp(-1/2) for the squared exponential
+    G = g1.reshape(N, N, N)
+    lag = 8
+    a, b = G[:, :, :-lag].ravel(), G[:, :, lag:].ravel()
+    rho = np.corrcoef(a, b)[0, 1]
+    assert abs(rho - np.exp(-0.5)) < 0.15
+
+
+def test_rhs_generators():
+    assert np.array_equal(problems.rhs_ones(5), np.ones(5))
+    u = problems.rhs_uniform(1000, seed=0)
+    assert np.array_equal(u, np.random.default_rng(0).random(1000))
+    assert u.min() >= 0.0 and u.max() < 1.0
