@@ -233,7 +233,7 @@ def prolongator_damping(A_F: sp.csr_matrix, d_F: np.ndarray, isolated: np.ndarra
 
     rho is the Gershgorin bound on the spectral radius of D_F^-1 A_F.
     """
-    absrow = np.asarray(abs(A_F).sum(axis=1)).ravel()
+    absrow = abs(A_F) @ np.ones(A_F.shape[0])  # row sums, entries in column order
     ratio = absrow / np.abs(d_F)
     live = ~isolated
     rho = float(ratio[live].max()) if live.any() else 1.0
@@ -251,7 +251,7 @@ def smoothed_prolongator(A_F, d_F, P_hat, omega) -> sp.csr_matrix:
 def spai0_diagonal(A: sp.csr_matrix) -> np.ndarray:
     """SPAI-0: m_i = a_ii / sum_j a_ij^2, the diagonal M minimising ||I - M A||_F."""
     A = _as_csr(A)
-    rowsq = np.asarray(A.multiply(A).sum(axis=1)).ravel()
+    rowsq = A.multiply(A) @ np.ones(A.shape[0])  # row sums, entries in column order
     return A.diagonal() / rowsq
 
 
