@@ -1,0 +1,206 @@
+/*
+ * amg.h -- C ABI of an MI355X (gfx950) smoothed-aggregation AMG solver.
+ *
+ * The library solves A u = f for a square sparse matrix A given in CSR form
+ * (the problem statement of section 2, eq. 1).  Following section 3, the
+ * hierarchy is built once on the host (the paper's "AMG setup" algorithm of
+ * section 2, with smoothed aggregation as the coarsening strategy) and moved
+ * to the device; each solve then runs a Krylov method (CG or BiCGStab,
+ * section 3 "Iterative solvers") preconditioned by one V-cycle (section 2,
+ * "AMG solve" and the closing remark of section 2) entirely in HIP kernels.
+ * The hierarchy is reused across right-hand sides (section 3).
+ *
+ * Conventions for every entry point:
+ *  - No C++ exception crosses this boundary; every failure is a negative
+ *    amg_status, and amg_last_error() returns a thread-local message.
+ *  - "host" pointers are ordinary CPU memory owned by the caller, read only
+ *    during the call (the library copies what it keeps).  "device" pointers
+ *    are caller-owned device memory of the current HIP device.
+ *  - hip_stream is a hipStream_t (NULL = the legacy default stream).  Work is
+ *    enqueued on it; calls that report results (amg_solve, amg_vcycle's
+ *    status) synchronise that stream before returning.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef AMG_H
+#define AMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AMG_OK = 0,
+  AMG_NOT_CONVERGED = 1,        /* warning: outputs are valid, tol not met   */
+  AMG_ERR_INVALID_ARG = -1,     /* NULL pointer, bad enum, bad size          */
+  AMG_ERR_BAD_CSR = -2,         /* row_ptr/col malformed or columns unsorted */
+  AMG_ERR_ZERO_DIAG = -3,       /* missing or non-positive diagonal entry    */
+  AMG_ERR_SINGULAR_COARSE = -4, /* zero pivot in the coarsest dense LU       */
+  AMG_ERR_OOM = -5,             /* device or host allocation failed          */
+  AMG_ERR_HIP = -6,             /* a HIP runtime call failed                 */
+  AMG_ERR_BREAKDOWN = -7,       /* BiCGStab rho = 0 or omega = 0             */
+  AMG_ERR_TOO_LARGE = -8,       /* nnz >= 2^31, or coarsest level > 20000    */
+  AMG_ERR_NAN = -9              /* non-finite value in the iteration         */
+} amg_status;
+
+enum { AMG_CG = 0, AMG_BICGSTAB = 1 };         /* Krylov method (section 3) */
+enum { AMG_SPAI0 = 0, AMG_JACOBI = 1 };        /* relaxation (section 3)    */
+enum { AMG_FP64 = 0, AMG_MIXED = 1 };          /* value type of the V-cycle */
+
+/*
+ * Method parameters: the paper's nested params structs (section 3.1) and its
+ * runtime keys (section 3.2: solver.type, solver.tol,
+ * precond.coarsening.type, precond.relax.type), flattened.
+ * amg_params_default() fills: CG, SPAI-0, FP64, eps_strong 0.08 (halved on
+ * every coarser level), jacobi_omega 0.72, npre = npost = 1, coarse_enough
+ * 3000, max_levels 30, max_iter 500, tol 1e-8 (relative to ||f||_2),
+ * use_graph 1, check_every 4.
+ */
+typedef struct {
+  int32_t solver;        /* AMG_CG | AMG_BICGSTAB                               */
+  int32_t relax;         /* AMG_SPAI0 | AMG_JACOBI                              */
+  int32_t precision;     /* AMG_FP64 | AMG_MIXED (FP32 V-cycle, FP64 Krylov)    */
+  int32_t npre;          /* pre-relaxation sweeps per level (>= 0)              */
+  int32_t npost;         /* post-relaxation sweeps per level (>= 0)             */
+  int32_t coarse_enough; /* a level with at most this many rows is the coarsest */
+  int32_t max_levels;    /* hierarchy depth limit (>= 1)                        */
+  int32_t max_iter;      /* Krylov iteration limit (>= 1)                       */
+  double eps_strong;     /* strength threshold on level 1                      */
+  double jacobi_omega;   /* damping of the Jacobi smoother                     */
+  double tol;            /* stop when ||r||_2 <= tol * ||f||_2                 */
+  int32_t use_graph;     /* 1: replay the V-cycle as a captured hipGraph        */
+  int32_t check_every;   /* iterations enqueued between host convergence polls  */
+} amg_params;
+
+/* Optional device allocator; NULL everywhere means hipMalloc / hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* hip_stream, void* ctx);
+  void (*free)(void* ptr, void* hip_stream, void* ctx);
+  void* ctx;
+} amg_allocator;
+
+typedef struct {
+  int32_t iters;          /* PCG: products q = A p; BiCGStab: loop passes      */
+  int32_t levels;         /* L, including the coarsest                         */
+  int32_t restarts;       /* 0 or 1 (restart when the true residual misses tol) */
+  int32_t status;         /* same as the return value of amg_solve             */
+  double rel_resid;       /* recursive ||r|| / ||f|| at exit                   */
+  double true_rel_resid;  /* ||f - A u|| / ||f|| recomputed at exit            */
+  double setup_s;         /* wall seconds of amg_setup                         */
+  double solve_s;         /* wall seconds of this amg_solve                    */
+  double op_complexity;   /* sum of nnz(A_l) / nnz(A_1)                        */
+} amg_info;
+
+typedef struct amg_solver* amg_handle;
+
+/* Fill *p with the defaults listed above.  p must not be NULL. */
+void amg_params_default(amg_params* p);
+
+/*
+ * Build the hierarchy for the n x n CSR matrix (row_ptr int64[n+1], col
+ * int32[nnz], val double[nnz]; host, caller-owned, copied) and upload it to
+ * the current device.  Requirements: row_ptr[0] = 0, non-decreasing row_ptr,
+ * 0 <= col < n, strictly ascending columns within a row, a stored diagonal
+ * entry a_ii > 0 in every row, nnz < 2^31.  p = NULL means defaults.  On
+ * success *out receives a handle owning all device memory; on error *out is
+ * set to NULL.
+ */
+amg_status amg_setup(int64_t n, const int64_t* row_ptr, const int32_t* col,
+                     const double* val, const amg_params* p,
+                     const amg_allocator* alloc, void* hip_stream,
+                     amg_handle* out);
+
+/*
+ * Same hierarchy construction, host only: nothing is allocated on or sent to
+ * a device.  The handle answers the query functions below; amg_solve and
+ * amg_vcycle reject it with AMG_ERR_INVALID_ARG.
+ */
+amg_status amg_setup_host(int64_t n, const int64_t* row_ptr, const int32_t* col,
+                          const double* val, const amg_params* p, amg_handle* out);
+
+/*
+ * Solve A u = f.  f_dev, u_dev: device double[n]; u holds the initial guess
+ * on entry and the solution on exit.  info may be NULL.  Returns AMG_OK,
+ * AMG_NOT_CONVERGED (u is the last iterate), or a negative error.  A zero f
+ * gives u = 0 and 0 iterations.
+ */
+amg_status amg_solve(amg_handle h, const double* f_dev, double* u_dev,
+                     void* hip_stream, amg_info* info);
+
+/* Free everything the handle owns.  NULL-safe. */
+void amg_release(amg_handle h);
+
+/* Message of the last error on this thread ("" if none). */
+const char* amg_last_error(void);
+
+/* --- test and measurement exports ----------------------------------------- */
+
+/*
+ * One V-cycle (section 2, "AMG solve", with zero initial guess on every
+ * level) applied to r: z = M^-1 r.  r_dev, z_dev: device double[n], must not
+ * alias.  Runs in the handle's precision.
+ */
+amg_status amg_vcycle(amg_handle h, const double* r_dev, double* z_dev, void* hip_stream);
+
+/* Number of levels L of the hierarchy (0 on a NULL handle). */
+int32_t amg_num_levels(amg_handle h);
+
+/*
+ * Sizes of level `level` (0-based).  n: rows of A_l; nnz_A: stored entries of
+ * A_l; nnz_P: stored entries of P_l (0 on the coarsest level).  Any output
+ * pointer may be NULL.
+ */
+amg_status amg_level_info(amg_handle h, int32_t level, int64_t* n, int64_t* nnz_A,
+                          int64_t* nnz_P);
+
+/* Aggregate id of every node of level `level` (< L-1); -1 = isolated. Host int32[n]. */
+amg_status amg_get_aggregates(amg_handle h, int32_t level, int32_t* agg_host);
+
+/*
+ * Copy a level matrix to host arrays sized from amg_level_info: which = 0 for
+ * A_l (n x n), 1 for P_l (n x n_{l+1}), 2 for R_l = P_l^T (n_{l+1} x n).
+ * row_ptr int64[rows+1], col int32[nnz], val double[nnz].
+ */
+amg_status amg_get_level_csr(amg_handle h, int32_t level, int32_t which,
+                             int64_t* row_ptr, int32_t* col, double* val);
+
+/* Smoother diagonal m_l (host double[n]) and prolongator damping omega_l. */
+amg_status amg_get_smoother(amg_handle h, int32_t level, double* m_host, double* omega);
+
+/*
+ * Device SpMV y = A x for a standalone CSR matrix, using the same kernel
+ * selection as the solver (by row length).  precision AMG_FP64: x, y double;
+ * AMG_MIXED: FP32 copies of the values, x and y float.  rows x cols matrix;
+ * empty rows give y_i = 0.
+ */
+typedef struct amg_matrix_s* amg_matrix;
+amg_status amg_csr_upload(int64_t rows, int64_t cols, const int64_t* row_ptr,
+                          const int32_t* col, const double* val, int32_t precision,
+                          void* hip_stream, amg_matrix* out);
+amg_status amg_csr_spmv(amg_matrix m, const void* x_dev, void* y_dev, void* hip_stream);
+/* kind: 0 = LDS-staged stream kernel (short rows), 1 = sub-wavefront per row. */
+amg_status amg_csr_kernel_info(amg_matrix m, int32_t* kind, int32_t* lanes_per_row,
+                               int32_t* blocks);
+void amg_csr_release(amg_matrix m);
+
+/*
+ * Measurement: launch one hot kernel of the solve `reps` times back to back
+ * on hip_stream between two HIP events and report the mean duration per
+ * launch (microseconds) and the kernel's algorithmic HBM bytes per launch
+ * (CSR arrays read once, int32 indices, each vector read or written once).
+ * which: 0 outer SpMV q = A p with p.q (FP64), 1 level-1 pre-sweep +
+ * residual, 2 level-1 post-sweep (with r.z), 3 level-1 restriction,
+ * 4 level-1 prolongation + correction, 5 one whole V-cycle (all levels,
+ * bytes summed over the hierarchy); 1-5 run in the handle's precision on its
+ * internal work vectors (contents are overwritten).
+ */
+amg_status amg_time_kernel(amg_handle h, int32_t which, int32_t reps, void* hip_stream,
+                           double* avg_us, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMG_H */

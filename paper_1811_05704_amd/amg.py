@@ -1,0 +1,364 @@
+"""Python binding of the C ABI in ``include/amg.h`` (ctypes; marshalling only).
+
+Every step of the solve runs in the library's HIP kernels; this module only
+converts arguments.  PyTorch supplies device memory (through the caching
+allocator, handed to the library as its allocator hook) and the current HIP
+stream.  The shared library is built in-tree by ``paper_1811_05704_amd.build``;
+if it is missing, loading raises instead of falling back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamg.so")
+
+AMG_OK = 0
+AMG_NOT_CONVERGED = 1
+AMG_ERR = {
+    -1: "AMG_ERR_INVALID_ARG", -2: "AMG_ERR_BAD_CSR", -3: "AMG_ERR_ZERO_DIAG",
+    -4: "AMG_ERR_SINGULAR_COARSE", -5: "AMG_ERR_OOM", -6: "AMG_ERR_HIP",
+    -7: "AMG_ERR_BREAKDOWN", -8: "AMG_ERR_TOO_LARGE", -9: "AMG_ERR_NAN",
+}
+SOLVERS = {"cg": 0, "bicgstab": 1}
+RELAX = {"spai0": 0, "jacobi": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
+
+
+class AmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{AMG_ERR.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("solver", C.c_int32), ("relax", C.c_int32), ("precision", C.c_int32),
+        ("npre", C.c_int32), ("npost", C.c_int32), ("coarse_enough", C.c_int32),
+        ("max_levels", C.c_int32), ("max_iter", C.c_int32),
+        ("eps_strong", C.c_double), ("jacobi_omega", C.c_double), ("tol", C.c_double),
+        ("use_graph", C.c_int32), ("check_every", C.c_int32),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int32), ("levels", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32),
+        ("rel_resid", C.c_double), ("true_rel_resid", C.c_double), ("setup_s", C.c_double),
+        ("solve_s", C.c_double), ("op_complexity", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libamg.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_1811_05704_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P64, P32, PD = C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double)
+    sig = {
+        "amg_params_default": (None, [C.POINTER(Params)]),
+        "amg_setup": (i32, [i64, P64, P32, PD, C.POINTER(Params), C.POINTER(Allocator), vp, C.POINTER(vp)]),
+        "amg_setup_host": (i32, [i64, P64, P32, PD, C.POINTER(Params), C.POINTER(vp)]),
+        "amg_solve": (i32, [vp, vp, vp, vp, C.POINTER(Info)]),
+        "amg_release": (None, [vp]),
+        "amg_last_error": (C.c_char_p, []),
+        "amg_vcycle": (i32, [vp, vp, vp, vp]),
+        "amg_num_levels": (i32, [vp]),
+        "amg_level_info": (i32, [vp, i32, P64, P64, P64]),
+        "amg_get_aggregates": (i32, [vp, i32, P32]),
+        "amg_get_level_csr": (i32, [vp, i32, i32, P64, P32, PD]),
+        "amg_get_smoother": (i32, [vp, i32, PD, PD]),
+        "amg_csr_upload": (i32, [i64, i64, P64, P32, PD, i32, vp, C.POINTER(vp)]),
+        "amg_csr_spmv": (i32, [vp, vp, vp, vp]),
+        "amg_csr_kernel_info": (i32, [vp, P32, P32, P32]),
+        "amg_csr_release": (None, [vp]),
+        "amg_time_kernel": (i32, [vp, i32, i32, vp, PD, PD]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return [
+        "amg_params_default", "amg_setup", "amg_setup_host", "amg_solve", "amg_release",
+        "amg_last_error", "amg_vcycle", "amg_num_levels", "amg_level_info", "amg_get_aggregates",
+        "amg_get_level_csr", "amg_get_smoother", "amg_csr_upload", "amg_csr_spmv",
+        "amg_csr_kernel_info", "amg_csr_release", "amg_time_kernel",
+    ]
+
+
+def _check(code):
+    if code < 0:
+        raise AmgError(code, lib().amg_last_error().decode())
+    return code
+
+
+def make_params(**kw) -> Params:
+    """Defaults of ``amg_params_default`` overridden by keyword arguments.
+
+    Accepts the names of the struct fields and string values for ``solver``
+    ("cg" | "bicgstab"), ``relax`` ("spai0" | "jacobi") and ``precision``
+    ("fp64" | "mixed").
+    """
+    p = Params()
+    lib().amg_params_default(C.byref(p))
+    for k, v in kw.items():
+        if k == "solver" and isinstance(v, str):
+            v = SOLVERS[v]
+        elif k == "relax" and isinstance(v, str):
+            v = RELAX[v]
+        elif k == "precision" and isinstance(v, str):
+            v = PRECISION[v]
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _csr_arrays(A):
+    row_ptr = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(A.col, dtype=np.int32)
+    val = np.ascontiguousarray(A.val, dtype=np.float64)
+    return row_ptr, col, val
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class _Handle:
+    """Queries shared by device and host-only handles."""
+
+    _h = None
+
+    @property
+    def nlevels(self) -> int:
+        return int(lib().amg_num_levels(self._h))
+
+    def level_info(self, level):
+        n, na, npp = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().amg_level_info(self._h, level, C.byref(n), C.byref(na), C.byref(npp)))
+        return n.value, na.value, npp.value
+
+    def aggregates(self, level) -> np.ndarray:
+        n, _, _ = self.level_info(level)
+        out = np.empty(n, dtype=np.int32)
+        _check(lib().amg_get_aggregates(self._h, level, _ptr(out, C.c_int32)))
+        return out
+
+    def level_csr(self, level, which="A"):
+        """(rows, cols, row_ptr, col, val) of A_l, P_l or R_l."""
+        w = {"A": 0, "P": 1, "R": 2}[which]
+        n, na, npp = self.level_info(level)
+        if w == 0:
+            rows, nnz = n, na
+            cols = n
+        else:
+            nc = self.level_info(level + 1)[0]
+            rows, cols = (n, nc) if w == 1 else (nc, n)
+            nnz = npp
+        rp = np.empty(rows + 1, dtype=np.int64)
+        c = np.empty(nnz, dtype=np.int32)
+        v = np.empty(nnz, dtype=np.float64)
+        _check(lib().amg_get_level_csr(self._h, level, w, _ptr(rp, C.c_int64), _ptr(c, C.c_int32),
+                                       _ptr(v, C.c_double)))
+        return rows, cols, rp, c, v
+
+    def level_scipy(self, level, which="A"):
+        import scipy.sparse as sp
+
+        rows, cols, rp, c, v = self.level_csr(level, which)
+        return sp.csr_matrix((v, c, rp), shape=(rows, cols))
+
+    def smoother(self, level):
+        n, _, _ = self.level_info(level)
+        m = np.empty(n, dtype=np.float64)
+        om = C.c_double()
+        _check(lib().amg_get_smoother(self._h, level, _ptr(m, C.c_double), C.byref(om)))
+        return m, om.value
+
+    def release(self):
+        if self._h:
+            lib().amg_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class HostHierarchy(_Handle):
+    """Hierarchy built on the host only (``amg_setup_host``); no device needed."""
+
+    def __init__(self, A, **params):
+        self.params = make_params(**params)
+        rp, c, v = _csr_arrays(A)
+        h = C.c_void_p()
+        _check(lib().amg_setup_host(int(A.n), _ptr(rp, C.c_int64), _ptr(c, C.c_int32), _ptr(v, C.c_double),
+                                    C.byref(self.params), C.byref(h)))
+        self._h = h
+
+
+def _torch_stream():
+    import torch
+
+    return torch.cuda.current_stream()
+
+
+class Solver(_Handle):
+    """AMG-preconditioned Krylov solver resident on the current HIP device.
+
+    ``A`` has ``n``, ``row_ptr``, ``col``, ``val`` (host arrays); keyword
+    arguments are :class:`Params` fields.  With ``torch_alloc`` (default) the
+    library's device memory comes from PyTorch's caching allocator.
+    """
+
+    def __init__(self, A, torch_alloc: bool = True, **params):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("amg.Solver needs a HIP device")
+        self.params = make_params(**params)
+        self.n = int(A.n)
+        self.device = torch.cuda.current_device()
+        stream = _torch_stream()
+        self._alloc = None
+        alloc_p = None
+        if torch_alloc:
+            dev = self.device
+            self._live = {}
+
+            def _a(size, strm, ctx):
+                try:
+                    ptr = torch.cuda.caching_allocator_alloc(int(size), dev, stream)
+                except Exception:
+                    return None
+                self._live[ptr] = True
+                return ptr
+
+            def _f(ptr, strm, ctx):
+                if ptr in self._live:
+                    del self._live[ptr]
+                    torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc = Allocator(ALLOC_FN(_a), FREE_FN(_f), None)
+            alloc_p = C.byref(self._alloc)
+        rp, c, v = _csr_arrays(A)
+        h = C.c_void_p()
+        _check(lib().amg_setup(self.n, _ptr(rp, C.c_int64), _ptr(c, C.c_int32), _ptr(v, C.c_double),
+                               C.byref(self.params), alloc_p, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def solve(self, f, x0=None, raise_on_error: bool = True):
+        """Solve A x = f; f (and x0) are float64 device tensors of length n.
+
+        Returns (x, info dict).  info["status"] is AMG_OK (0) or
+        AMG_NOT_CONVERGED (1); errors raise.
+        """
+        import torch
+
+        assert f.dtype == torch.float64 and f.is_cuda and f.numel() == self.n
+        f = f.contiguous()
+        x = torch.zeros_like(f) if x0 is None else x0.clone().contiguous()
+        info = Info()
+        code = lib().amg_solve(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(x.data_ptr()),
+                               C.c_void_p(_torch_stream().cuda_stream), C.byref(info))
+        if raise_on_error:
+            _check(code)
+        d = info.as_dict()
+        d["status"] = code
+        return x, d
+
+    KERNELS = ("outer_spmv_dot", "pre_smooth_residual", "post_smooth_dot", "restrict", "prolong", "vcycle")
+
+    def time_kernel(self, which, reps=50):
+        """(mean microseconds per launch, algorithmic bytes per launch) of one hot kernel."""
+        k = self.KERNELS.index(which) if isinstance(which, str) else int(which)
+        us, by = C.c_double(), C.c_double()
+        _check(lib().amg_time_kernel(self._h, k, reps, C.c_void_p(_torch_stream().cuda_stream),
+                                     C.byref(us), C.byref(by)))
+        return us.value, by.value
+
+    def vcycle(self, r):
+        """z = V(r): one V-cycle on a float64 device tensor."""
+        import torch
+
+        assert r.dtype == torch.float64 and r.is_cuda and r.numel() == self.n
+        r = r.contiguous()
+        z = torch.empty_like(r)
+        _check(lib().amg_vcycle(self._h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()),
+                                C.c_void_p(_torch_stream().cuda_stream)))
+        return z
+
+
+class DeviceMatrix:
+    """Standalone device CSR matrix for y = A x (kernel tests and measurement)."""
+
+    def __init__(self, rows, cols, row_ptr, col, val, precision="fp64"):
+        self.rows, self.cols = int(rows), int(cols)
+        self.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().amg_csr_upload(self.rows, self.cols, _ptr(rp, C.c_int64), _ptr(c, C.c_int32),
+                                    _ptr(v, C.c_double), self.precision,
+                                    C.c_void_p(_torch_stream().cuda_stream), C.byref(h)))
+        self._h = h
+
+    def kernel_info(self):
+        k, l, b = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().amg_csr_kernel_info(self._h, C.byref(k), C.byref(l), C.byref(b)))
+        return {"kind": ("stream", "vector")[k.value], "lanes": l.value, "blocks": b.value}
+
+    def spmv(self, x, y=None):
+        import torch
+
+        dt = torch.float64 if self.precision == 0 else torch.float32
+        assert x.dtype == dt and x.is_cuda and x.numel() == self.cols
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty(self.rows, dtype=dt, device=x.device)
+        _check(lib().amg_csr_spmv(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                  C.c_void_p(_torch_stream().cuda_stream)))
+        return y
+
+    def release(self):
+        if self._h:
+            lib().amg_csr_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass

@@ -1,0 +1,210 @@
+// Device-side data of the solver: level matrices and vectors in HBM, the
+// per-matrix SpMV schedule (variant chosen by row length), and launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/amg.h"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+namespace amg {
+
+struct DevError {
+  int code;
+  std::string msg;
+};
+
+#define AMG_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::amg::DevError{-6, std::string(#call) + ": " + hipGetErrorString(e_)};     \
+  } while (0)
+
+#define AMG_LAUNCHED()                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = hipGetLastError();                                                  \
+    if (e_ != hipSuccess)                                                               \
+      throw ::amg::DevError{-6, std::string("kernel launch: ") + hipGetErrorString(e_)}; \
+  } while (0)
+
+// Device memory from the caller's allocator (or hipMalloc), freed together.
+class DevArena {
+ public:
+  DevArena(const amg_allocator* a, hipStream_t s) : stream_(s) {
+    if (a && a->alloc && a->free) {
+      alloc_ = *a;
+      custom_ = true;
+    }
+  }
+  ~DevArena() { release(); }
+  DevArena(const DevArena&) = delete;
+  DevArena& operator=(const DevArena&) = delete;
+
+  void* raw(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~size_t(255);
+    void* p = nullptr;
+    if (custom_) {
+      p = alloc_.alloc(bytes, stream_, alloc_.ctx);
+      if (!p) throw DevError{-5, "device allocator returned NULL for " + std::to_string(bytes) + " bytes"};
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        throw DevError{-5, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+      }
+    }
+    blocks_.push_back(p);
+    bytes_ += bytes;
+    return p;
+  }
+  template <class T>
+  T* get(size_t count) {
+    return static_cast<T*>(raw(count * sizeof(T)));
+  }
+  template <class T>
+  T* upload(const T* host, size_t count) {
+    T* d = get<T>(count);
+    if (count) AMG_HIP(hipMemcpyAsync(d, host, count * sizeof(T), hipMemcpyHostToDevice, stream_));
+    return d;
+  }
+  size_t bytes() const { return bytes_; }
+  hipStream_t stream() const { return stream_; }
+  void release() {
+    if (!blocks_.empty()) (void)hipStreamSynchronize(stream_);
+    for (void* p : blocks_) {
+      if (custom_) alloc_.free(p, stream_, alloc_.ctx);
+      else (void)hipFree(p);
+    }
+    blocks_.clear();
+    bytes_ = 0;
+  }
+
+ private:
+  amg_allocator alloc_{};
+  bool custom_ = false;
+  hipStream_t stream_;
+  std::vector<void*> blocks_;
+  size_t bytes_ = 0;
+};
+
+// SpMV schedule selection by row length.
+constexpr double kStreamMaxMean = 12.0;  // mean row length up to which the stream variant is used
+
+template <class T>
+struct DevCsr {
+  int32_t rows = 0, cols = 0;
+  int64_t nnz = 0;
+  int32_t* ptr = nullptr;
+  int32_t* col = nullptr;
+  T* val = nullptr;
+  int kind = 0;   // 0 stream, 1 vector
+  int lanes = 1;  // vector variant: lanes per row
+  int32_t nblocks = 0;
+  int32_t* blk = nullptr;
+  CsrView<T> view() const { return CsrView<T>{ptr, col, val, blk, rows, nblocks}; }
+};
+
+struct Schedule {
+  int kind = 0, lanes = 1;
+  std::vector<int32_t> blk;
+  int32_t nblocks = 0;
+};
+
+inline Schedule make_schedule(const Csr& M, int force_kind = -1) {
+  Schedule s;
+  const int64_t rows = M.rows;
+  const double mean = rows ? double(M.nnz()) / double(rows) : 0.0;
+  s.kind = force_kind >= 0 ? force_kind : (mean <= kStreamMaxMean ? 0 : 1);
+  if (s.kind == 0) {
+    s.blk.push_back(0);
+    int64_t r = 0;
+    while (r < rows) {
+      const int64_t start = r;
+      if (M.ptr[r + 1] - M.ptr[r] > kStreamNnz) {
+        ++r;
+      } else {
+        int64_t nnz = 0;
+        while (r < rows && r - start < kStreamRows) {
+          const int64_t len = M.ptr[r + 1] - M.ptr[r];
+          if (nnz + len > kStreamNnz) break;
+          nnz += len;
+          ++r;
+        }
+      }
+      s.blk.push_back(static_cast<int32_t>(r));
+    }
+    s.nblocks = static_cast<int32_t>(s.blk.size()) - 1;
+  } else {
+    int lanes = 2;
+    while (lanes < 64 && lanes < mean) lanes *= 2;
+    s.lanes = lanes;
+    const int rpb = kBS / lanes;
+    s.nblocks = static_cast<int32_t>((rows + rpb - 1) / rpb);
+  }
+  return s;
+}
+
+template <class T>
+DevCsr<T> upload_csr(DevArena& ar, const Csr& M, int force_kind = -1) {
+  DevCsr<T> d;
+  d.rows = static_cast<int32_t>(M.rows);
+  d.cols = static_cast<int32_t>(M.cols);
+  d.nnz = M.nnz();
+  std::vector<int32_t> p32(M.ptr.begin(), M.ptr.end());
+  if (p32.empty()) p32.assign(1, 0);
+  d.ptr = ar.upload(p32.data(), p32.size());
+  d.col = ar.upload(M.col.data(), M.col.size());
+  if constexpr (std::is_same<T, double>::value) {
+    d.val = ar.upload(M.val.data(), M.val.size());
+  } else {
+    std::vector<T> v(M.val.size());
+    for (size_t k = 0; k < v.size(); ++k) v[k] = static_cast<T>(M.val[k]);  // round to nearest
+    d.val = ar.upload(v.data(), v.size());
+  }
+  Schedule s = make_schedule(M, force_kind);
+  d.kind = s.kind;
+  d.lanes = s.lanes;
+  d.nblocks = s.nblocks;
+  if (s.kind == 0) d.blk = ar.upload(s.blk.data(), s.blk.size());
+  // upload uses pageable host buffers: finish before they go out of scope
+  AMG_HIP(hipStreamSynchronize(ar.stream()));
+  return d;
+}
+
+// Launch y-epilogue SpMV with the matrix's schedule; returns the grid size
+// (= number of partials written when E::K > 0).
+template <class T, class G, class E>
+int launch_spmv(const DevCsr<T>& M, G g, E e, double* partials, const int* skip, hipStream_t s) {
+  if (M.rows == 0) return 0;
+  if (M.kind == 0) {
+    csr_stream_kernel<T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip);
+  } else {
+    switch (M.lanes) {
+      case 2: csr_vector_kernel<2, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
+      case 4: csr_vector_kernel<4, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
+      case 8: csr_vector_kernel<8, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
+      case 16: csr_vector_kernel<16, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
+      case 32: csr_vector_kernel<32, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
+      default: csr_vector_kernel<64, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
+    }
+  }
+  AMG_LAUNCHED();
+  return M.nblocks;
+}
+
+inline int vec_blocks(int64_t n) {
+  int64_t b = (n + kVecBS - 1) / kVecBS;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, 65536)));
+}
+
+}  // namespace amg

@@ -1,0 +1,64 @@
+// Host-side smoothed-aggregation setup (section 2, "AMG setup"; section 3,
+// "Coarsening strategies": smoothed aggregation after Vanek, Mandel and
+// Brezina 1996).  Builds A_l, P_l, R_l = P_l^T and the smoother diagonals on
+// the CPU; the device layer uploads the result.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace amg {
+
+struct Csr {
+  int64_t rows = 0, cols = 0;
+  std::vector<int64_t> ptr;  // rows + 1
+  std::vector<int32_t> col;  // ascending within each row
+  std::vector<double> val;
+  int64_t nnz() const { return ptr.empty() ? 0 : ptr.back(); }
+};
+
+struct SetupParams {
+  int relax = 0;  // 0 SPAI-0, 1 damped Jacobi
+  double eps_strong = 0.08;
+  double jacobi_omega = 0.72;
+  int coarse_enough = 3000;
+  int max_levels = 30;
+  int max_coarse = 20000;
+};
+
+struct HostLevel {
+  Csr A, P, R;                // P, R empty on the coarsest level
+  std::vector<int32_t> agg;   // aggregate per node, -1 isolated
+  std::vector<double> m;      // smoother diagonal
+  double omega = 0.0;         // prolongator damping
+  double eps = 0.0;           // strength threshold used on this level
+};
+
+struct HostHierarchy {
+  std::vector<HostLevel> levels;  // the last one is the coarsest (A only)
+};
+
+// Error raised by the setup; code is an amg_status value.
+struct SetupError {
+  int code;
+  std::string msg;
+};
+
+// Validate a CSR input as the C ABI requires; throws SetupError.
+void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val);
+
+// Full hierarchy; throws SetupError.
+HostHierarchy build_hierarchy(Csr A, const SetupParams& prm);
+
+// Steps, exposed for tests of the host logic.
+struct Graph {
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> idx;
+};
+Graph strength_graph(const Csr& A, double eps);
+std::vector<int32_t> aggregate(const Graph& S, int32_t* count);
+Csr transpose(const Csr& M);
+Csr spgemm(const Csr& A, const Csr& B);
+
+}  // namespace amg

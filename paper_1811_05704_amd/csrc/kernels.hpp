@@ -1,0 +1,559 @@
+// gfx950 kernels of the AMG solve phase.
+//
+// The solve phase (section 2, "AMG solve", and section 3: "sparse
+// matrix-vector product or linear vector combinations") reduces to CSR
+// sparse matrix-vector products with fused element-wise epilogues, vector
+// updates and dot products.  Everything here is bandwidth bound (about 2
+// flops per 12 bytes of matrix in FP64), so no matrix cores are used: the
+// kernels are built around coalesced streaming of the CSR arrays, gathers of
+// x that hit in L2, LDS-staged row sums and wave64 reductions.
+//
+// Two SpMV variants, chosen per matrix from its row lengths:
+//  * stream: a workgroup takes a precomputed block of consecutive rows whose
+//    entries fit in LDS, streams val/col of the whole block with consecutive
+//    lanes on consecutive entries (perfectly coalesced), stores the products
+//    in LDS, then each lane sums one row from LDS (short rows: fine-level
+//    operators and prolongators).  A row longer than the LDS block gets a
+//    block of its own and is reduced by the whole workgroup.
+//  * vector: G lanes (a power of two up to the 64-lane wavefront) per row,
+//    strided loads within the row and a butterfly reduction with lane
+//    shuffles (longer rows: coarse operators and restrictions).
+// Workgroups are remapped so that each of the 8 XCDs (each with its own L2)
+// works on one contiguous range of rows, keeping x-gathers XCD-local.
+//
+// Reductions are deterministic: each workgroup writes one partial per dot
+// product, and a one-workgroup finalize kernel sums the partials in a fixed
+// order and updates the Krylov scalars on the device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amg {
+
+constexpr int kBS = 256;             // threads per workgroup for the sparse kernels
+constexpr int kStreamNnz = 2048;     // LDS entries per stream block (8 per thread)
+constexpr int kStreamRows = kBS;     // at most one row per thread
+constexpr int kFinBS = 1024;         // finalize workgroup
+constexpr int kNumXcd = 8;
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  // Blocks are dispatched round-robin over the XCDs; give XCD x the x-th
+  // contiguous slice of the virtual block range.
+  const int x = b % kNumXcd, local = b / kNumXcd;
+  const int per = nb / kNumXcd, rem = nb % kNumXcd;
+  return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int G, class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
+// Sum K per-thread values over the workgroup; thread 0 writes them to
+// partials[k * nparts + slot].
+template <int K, int BS>
+__device__ __forceinline__ void block_partials(const double* v, double* partials, int nparts,
+                                               int slot) {
+  if constexpr (K > 0) {
+    __shared__ double sh[K][BS / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = wave_sum(v[k]);
+      if (lane == 0) sh[k][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < BS / 64; ++w) s += sh[k][w];
+        partials[k * nparts + slot] = s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- CSR views
+
+template <class T>
+struct CsrView {
+  const int32_t* ptr;
+  const int32_t* col;
+  const T* val;
+  const int32_t* blk;  // stream variant: first row of each block, nblocks + 1
+  int32_t rows;
+  int32_t nblocks;
+};
+
+// x-gathers ---------------------------------------------------------------
+
+template <class T, class TX>
+struct GatherX {
+  const TX* x;
+  __device__ __forceinline__ T operator()(int j) const { return static_cast<T>(x[j]); }
+};
+
+// x_j = m_j f_j: the first relaxation sweep from a zero guess, recomputed on
+// the fly instead of stored.
+template <class T, class TF>
+struct GatherMF {
+  const T* m;
+  const TF* f;
+  __device__ __forceinline__ T operator()(int j) const { return m[j] * static_cast<T>(f[j]); }
+};
+
+// Epilogues: called once per row with the row sum s = (A x)_i; may add to K
+// dot-product partials.  ------------------------------------------------------
+
+template <class T, class TY>
+struct EpiStore {  // y = A x
+  static constexpr int K = 0;
+  TY* y;
+  __device__ __forceinline__ void operator()(int i, T s, double*) const { y[i] = static_cast<TY>(s); }
+};
+
+struct EpiStoreDot {  // y = A x, dot += w . y   (FP64 Krylov)
+  static constexpr int K = 1;
+  double* y;
+  const double* w;
+  __device__ __forceinline__ void operator()(int i, double s, double* d) const {
+    y[i] = s;
+    d[0] += w[i] * s;
+  }
+};
+
+struct EpiStoreDot2 {  // y = A x, dots += (w . y, y . y)
+  static constexpr int K = 2;
+  double* y;
+  const double* w;
+  __device__ __forceinline__ void operator()(int i, double s, double* d) const {
+    y[i] = s;
+    d[0] += w[i] * s;
+    d[1] += s * s;
+  }
+};
+
+// r = b - A x, with ||r||^2 and ||b||^2 (FP64 Krylov initial / true residual)
+struct EpiResidNorms {
+  static constexpr int K = 2;
+  double* r;
+  const double* b;
+  __device__ __forceinline__ void operator()(int i, double s, double* d) const {
+    const double bi = b[i];
+    const double ri = bi - s;
+    r[i] = ri;
+    d[0] += ri * ri;
+    d[1] += bi * bi;
+  }
+};
+
+// r = f - A x in the V-cycle's value type (f may be wider: level 1, mixed).
+template <class T, class TF>
+struct EpiResid {
+  static constexpr int K = 0;
+  T* r;
+  const TF* f;
+  __device__ __forceinline__ void operator()(int i, T s, double*) const {
+    r[i] = static_cast<T>(f[i]) - s;
+  }
+};
+
+// y = base + P z_c, base = m.*f (one pre-sweep), a stored vector, or zero.
+template <class T, class TF, int BASE>  // BASE: 0 none, 1 m.*f, 2 stored
+struct EpiProlong {
+  static constexpr int K = 0;
+  T* y;
+  const T* m;
+  const TF* f;
+  const T* base;
+  __device__ __forceinline__ void operator()(int i, T s, double*) const {
+    if constexpr (BASE == 1) {
+      y[i] = m[i] * static_cast<T>(f[i]) + s;
+    } else if constexpr (BASE == 2) {
+      y[i] = base[i] + s;
+    } else {
+      y[i] = s;
+    }
+  }
+};
+
+// One relaxation sweep z_out = z + m.*(f - A z); optionally dot += f . z_out
+// in FP64 (level 1 of PCG: rho = r . z).
+template <class T, class TF, class TZ, int DOT>
+struct EpiSmooth {
+  static constexpr int K = DOT;
+  TZ* zout;
+  const T* z;
+  const T* m;
+  const TF* f;
+  __device__ __forceinline__ void operator()(int i, T s, double* d) const {
+    const T v = z[i] + m[i] * (static_cast<T>(f[i]) - s);
+    const TZ o = static_cast<TZ>(v);
+    zout[i] = o;
+    if constexpr (DOT) d[0] += static_cast<double>(f[i]) * static_cast<double>(o);
+  }
+};
+
+// ---------------------------------------------------------------- SpMV kernels
+
+// Stream variant.  Block b covers rows [blk[b], blk[b+1]): either at most
+// kStreamRows rows with at most kStreamNnz entries, or a single longer row.
+template <class T, class G, class E>
+__global__ void __launch_bounds__(kBS) csr_stream_kernel(CsrView<T> A, G gather, E epi,
+                                                         double* partials, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ T prod[kStreamNnz];
+  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  const int r0 = A.blk[vb], r1 = A.blk[vb + 1];
+  const int e0 = A.ptr[r0], e1 = A.ptr[r1];
+  const int tid = threadIdx.x;
+  double d[E::K > 0 ? E::K : 1] = {};
+  if (e1 - e0 <= kStreamNnz) {
+#pragma unroll
+    for (int k = 0; k < kStreamNnz / kBS; ++k) {
+      const int e = e0 + k * kBS + tid;
+      if (e < e1) prod[k * kBS + tid] = A.val[e] * gather(A.col[e]);
+    }
+    __syncthreads();
+    const int i = r0 + tid;
+    if (i < r1) {
+      const int b = A.ptr[i] - e0, e = A.ptr[i + 1] - e0;
+      T s = T(0);
+      for (int k = b; k < e; ++k) s += prod[k];
+      epi(i, s, d);
+    }
+  } else {
+    // one long row: strided over the workgroup, then a fixed-order tree
+    T s = T(0);
+    for (int e = e0 + tid; e < e1; e += kBS) s += A.val[e] * gather(A.col[e]);
+    __shared__ T red[kBS / 64];
+    s = group_sum<64>(s);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) {
+      T t = T(0);
+      for (int w = 0; w < kBS / 64; ++w) t += red[w];
+      epi(r0, t, d);
+    }
+  }
+  if constexpr (E::K > 0) block_partials<E::K, kBS>(d, partials, gridDim.x, vb);
+}
+
+// Vector variant: L lanes per row, kBS / L rows per workgroup.
+template <int L, class T, class G, class E>
+__global__ void __launch_bounds__(kBS) csr_vector_kernel(CsrView<T> A, G gather, E epi,
+                                                         double* partials, const int* skip) {
+  if (skip && *skip) return;
+  constexpr int RPB = kBS / L;
+  const int vb = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = vb * RPB + threadIdx.x / L;
+  const int lane = threadIdx.x % L;
+  double d[E::K > 0 ? E::K : 1] = {};
+  T s = T(0);
+  if (i < A.rows) {
+    const int b = A.ptr[i], e = A.ptr[i + 1];
+    for (int k = b + lane; k < e; k += L) s += A.val[k] * gather(A.col[k]);
+  }
+  s = group_sum<L>(s);
+  if (i < A.rows && lane == 0) epi(i, s, d);
+  if constexpr (E::K > 0) block_partials<E::K, kBS>(d, partials, gridDim.x, vb);
+}
+
+// ---------------------------------------------------------------- Krylov scalars
+
+// Device-resident Krylov state; the host reads it only to poll convergence.
+enum : int32_t {
+  kRunning = 0,
+  kConverged = 1,
+  kMaxIter = 2,
+  kBreakdown = 3,
+  kNonFinite = 4,
+  kZeroRhs = 5,
+  kHalfStep = 6,  // BiCGStab met tol after the first half step
+};
+
+struct KState {
+  double rho, rho1, alpha, beta, omega;
+  double ff, tol2, rr, true_rr;
+  double tol;
+  int32_t iters, done, max_iter, first;
+};
+
+// Finalize operations (one workgroup): sums of the partials are in s[].
+enum FinOp : int {
+  kFinInit = 0,       // s = (r.r, f.f) of r = f - A x0
+  kFinTrue = 1,       // s = (r.r, f.f) of the true residual at exit
+  kFinAlpha = 2,      // PCG: s = p.q -> alpha = rho / p.q
+  kFinPcgRR = 3,      // PCG: s = r.r -> iteration done, test convergence
+  kFinPcgRho = 4,     // PCG: s = r.z -> beta, rho
+  kFinBiAlpha = 5,    // BiCGStab: s = rt.v -> alpha
+  kFinBiS = 6,        // BiCGStab: s = s.s -> iteration counted, half-step test
+  kFinBiOmega = 7,    // BiCGStab: s = (t.s, t.t) -> omega
+  kFinBiR = 8,        // BiCGStab: s = (r.r, rt.r) -> convergence, rho, beta
+  kFinBiHalfDone = 9, // BiCGStab: half-step exit completed
+};
+
+template <int K>
+__global__ void __launch_bounds__(kFinBS) finalize_kernel(const double* partials, int nparts,
+                                                          KState* st, int op) {
+  const bool always = (op == kFinInit || op == kFinTrue || op == kFinBiHalfDone);
+  if (!always && st->done != kRunning) return;
+  if (op == kFinBiHalfDone) {
+    if (threadIdx.x == 0 && st->done == kHalfStep) st->done = kConverged;
+    return;
+  }
+  __shared__ double sh[K][kFinBS / 64];
+  double s[2] = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kFinBS) a += partials[k * nparts + b];
+    a = wave_sum(a);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double a = 0.0;
+    for (int w = 0; w < kFinBS / 64; ++w) a += sh[k][w];
+    s[k] = a;
+  }
+  auto bad = [](double v) { return !isfinite(v); };
+  switch (op) {
+    case kFinInit: {
+      st->rr = s[0];
+      st->ff = s[1];
+      st->tol2 = st->tol * st->tol * s[1];
+      if (s[1] == 0.0) st->done = kZeroRhs;
+      else if (bad(s[0]) || bad(s[1])) st->done = kNonFinite;
+      else if (s[0] <= st->tol2) st->done = kConverged;
+      else st->done = kRunning;
+      st->first = 1;
+      st->rho = s[0];  // BiCGStab: rt = r, so rt . r = r . r
+      st->rho1 = st->alpha = st->omega = 1.0;
+      break;
+    }
+    case kFinTrue:
+      st->true_rr = s[0];
+      break;
+    case kFinAlpha:
+      if (bad(s[0]) || s[0] == 0.0) { st->done = bad(s[0]) ? kNonFinite : kBreakdown; break; }
+      st->alpha = st->rho / s[0];
+      st->first = 0;
+      break;
+    case kFinPcgRR:
+      st->rr = s[0];
+      st->iters += 1;
+      if (bad(s[0])) st->done = kNonFinite;
+      else if (s[0] <= st->tol2) st->done = kConverged;
+      else if (st->iters >= st->max_iter) st->done = kMaxIter;
+      break;
+    case kFinPcgRho:
+      if (bad(s[0])) { st->done = kNonFinite; break; }
+      st->beta = st->first ? 0.0 : s[0] / st->rho;
+      st->rho = s[0];
+      break;
+    case kFinBiAlpha:
+      if (bad(s[0]) || s[0] == 0.0) { st->done = bad(s[0]) ? kNonFinite : kBreakdown; break; }
+      st->alpha = st->rho / s[0];
+      break;
+    case kFinBiS:
+      st->iters += 1;
+      st->rr = s[0];
+      if (bad(s[0])) st->done = kNonFinite;
+      else if (s[0] <= st->tol2) st->done = kHalfStep;
+      break;
+    case kFinBiOmega:
+      if (bad(s[0]) || bad(s[1]) || s[1] == 0.0) { st->done = kBreakdown; break; }
+      st->omega = s[0] / s[1];
+      break;
+    case kFinBiR: {
+      st->rr = s[0];
+      if (bad(s[0]) || bad(s[1])) { st->done = kNonFinite; break; }
+      if (s[0] <= st->tol2) { st->done = kConverged; break; }
+      if (st->omega == 0.0) { st->done = kBreakdown; break; }
+      if (st->iters >= st->max_iter) { st->done = kMaxIter; break; }
+      st->rho1 = st->rho;
+      st->rho = s[1];
+      if (s[1] == 0.0) { st->done = kBreakdown; break; }
+      st->beta = (st->rho / st->rho1) * (st->alpha / st->omega);
+      st->first = 0;
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// ---------------------------------------------------------------- vector kernels (FP64)
+
+constexpr int kVecBS = 256;
+
+__device__ __forceinline__ int vec_grid_start() {
+  return xcd_remap(blockIdx.x, gridDim.x) * kVecBS + threadIdx.x;
+}
+
+// x += alpha p; r -= alpha q; partial r.r
+__global__ void __launch_bounds__(kVecBS) pcg_update_kernel(int n, double* x, double* r,
+                                                            const double* p, const double* q,
+                                                            const KState* st, double* partials) {
+  if (st->done != kRunning) return;
+  const double alpha = st->alpha;
+  double d[1] = {0.0};
+  const int stride = gridDim.x * kVecBS;
+  for (int i = vec_grid_start(); i < n; i += stride) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    d[0] += ri * ri;
+  }
+  block_partials<1, kVecBS>(d, partials, gridDim.x, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// p = z + beta p  (p = z on the first iteration)
+__global__ void __launch_bounds__(kVecBS) pcg_dir_kernel(int n, double* p, const double* z,
+                                                         const KState* st) {
+  if (st->done != kRunning) return;
+  const double beta = st->beta;
+  const bool first = st->first;
+  const int stride = gridDim.x * kVecBS;
+  for (int i = vec_grid_start(); i < n; i += stride) p[i] = first ? z[i] : z[i] + beta * p[i];
+}
+
+// BiCGStab: p = r (first) or p = r + beta (p - omega v)
+__global__ void __launch_bounds__(kVecBS) bicg_p_kernel(int n, double* p, const double* r,
+                                                        const double* v, const KState* st) {
+  if (st->done != kRunning) return;
+  const double beta = st->beta, omega = st->omega;
+  const bool first = st->first;
+  const int stride = gridDim.x * kVecBS;
+  for (int i = vec_grid_start(); i < n; i += stride)
+    p[i] = first ? r[i] : r[i] + beta * (p[i] - omega * v[i]);
+}
+
+// BiCGStab: s = r - alpha v; partial s.s
+__global__ void __launch_bounds__(kVecBS) bicg_s_kernel(int n, double* s, const double* r,
+                                                        const double* v, const KState* st,
+                                                        double* partials) {
+  if (st->done != kRunning) return;
+  const double alpha = st->alpha;
+  double d[1] = {0.0};
+  const int stride = gridDim.x * kVecBS;
+  for (int i = vec_grid_start(); i < n; i += stride) {
+    const double si = r[i] - alpha * v[i];
+    s[i] = si;
+    d[0] += si * si;
+  }
+  block_partials<1, kVecBS>(d, partials, gridDim.x, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// BiCGStab half-step exit: x += alpha p_hat (only when the s-test passed)
+__global__ void __launch_bounds__(kVecBS) bicg_half_kernel(int n, double* x, const double* phat,
+                                                           const KState* st) {
+  if (st->done != kHalfStep) return;
+  const double alpha = st->alpha;
+  const int stride = gridDim.x * kVecBS;
+  for (int i = vec_grid_start(); i < n; i += stride) x[i] += alpha * phat[i];
+}
+
+// BiCGStab: x += alpha p_hat + omega s_hat; r = s - omega t; partials r.r, rt.r
+__global__ void __launch_bounds__(kVecBS) bicg_xr_kernel(int n, double* x, double* r,
+                                                         const double* phat, const double* shat,
+                                                         const double* s, const double* t,
+                                                         const double* rt, const KState* st,
+                                                         double* partials) {
+  if (st->done != kRunning) return;
+  const double alpha = st->alpha, omega = st->omega;
+  double d[2] = {0.0, 0.0};
+  const int stride = gridDim.x * kVecBS;
+  for (int i = vec_grid_start(); i < n; i += stride) {
+    x[i] += alpha * phat[i] + omega * shat[i];
+    const double ri = s[i] - omega * t[i];
+    r[i] = ri;
+    d[0] += ri * ri;
+    d[1] += rt[i] * ri;
+  }
+  block_partials<2, kVecBS>(d, partials, gridDim.x, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <class TD, class TS>
+__global__ void __launch_bounds__(kVecBS) copy_kernel(int n, TD* dst, const TS* src) {
+  const int stride = gridDim.x * kVecBS;
+  for (int i = blockIdx.x * kVecBS + threadIdx.x; i < n; i += stride)
+    dst[i] = static_cast<TD>(src[i]);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kVecBS) fill_kernel(int n, T* dst, T v) {
+  const int stride = gridDim.x * kVecBS;
+  for (int i = blockIdx.x * kVecBS + threadIdx.x; i < n; i += stride) dst[i] = v;
+}
+
+// z = m .* f   (first pre-sweep from zero, materialised when npre > 1)
+template <class T, class TF>
+__global__ void __launch_bounds__(kVecBS) scale_kernel(int n, T* z, const T* m, const TF* f,
+                                                       const int* skip) {
+  if (skip && *skip) return;
+  const int stride = gridDim.x * kVecBS;
+  for (int i = blockIdx.x * kVecBS + threadIdx.x; i < n; i += stride)
+    z[i] = m[i] * static_cast<T>(f[i]);
+}
+
+// ---------------------------------------------------------------- coarse solve
+
+// z = Ainv f with the dense inverse of the coarsest operator (FP64, row-major),
+// one wavefront per row, FP64 accumulation; f and z in the V-cycle's types.
+template <class TF, class TZ>
+__global__ void __launch_bounds__(kBS) coarse_gemv_kernel(int n, const double* __restrict__ Ainv,
+                                                          const TF* __restrict__ f, TZ* __restrict__ z,
+                                                          const int* skip) {
+  if (skip && *skip) return;
+  const int row = blockIdx.x * (kBS / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double* a = Ainv + static_cast<int64_t>(row) * n;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += a[j] * static_cast<double>(f[j]);
+  s = wave_sum(s);
+  if (lane == 0) z[row] = static_cast<TZ>(s);
+}
+
+// partials of a . b (FP64)
+__global__ void __launch_bounds__(kVecBS) dot_kernel(int n, const double* a, const double* b,
+                                                     double* partials, const int* skip) {
+  if (skip && *skip) return;
+  double d[1] = {0.0};
+  const int stride = gridDim.x * kVecBS;
+  for (int i = vec_grid_start(); i < n; i += stride) d[0] += a[i] * b[i];
+  block_partials<1, kVecBS>(d, partials, gridDim.x, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// zout = y (no post-sweep); optionally partials of f . zout
+template <class T, class TF, class TZ, int DOT>
+__global__ void __launch_bounds__(kVecBS) copy_dot_kernel(int n, TZ* zout, const T* y, const TF* f,
+                                                          double* partials, const int* skip) {
+  if (skip && *skip) return;
+  double d[1] = {0.0};
+  const int stride = gridDim.x * kVecBS;
+  for (int i = vec_grid_start(); i < n; i += stride) {
+    const TZ o = static_cast<TZ>(y[i]);
+    zout[i] = o;
+    if constexpr (DOT) d[0] += static_cast<double>(f[i]) * static_cast<double>(o);
+  }
+  if constexpr (DOT) block_partials<1, kVecBS>(d, partials, gridDim.x, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+}  // namespace amg
