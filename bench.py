@@ -100,6 +100,31 @@ def cpu_baseline(A, f, x_gpu_by_prec):
     }, errs
 
 
+def pmc_probe(N, torch, amg, problems):
+    """Counter calibration and hot-kernel dispatches for rocprofv3 --pmc runs.
+
+    A device-to-device copy of exactly 1 GiB (read 1 GiB, write 1 GiB) gives
+    the scale between the counters and bytes; then each level-1 kernel and
+    the V-cycle are launched through amg_time_kernel (reps launches after one
+    warm-up) in FP64 and mixed precision.
+    """
+    torch.cuda.set_device(0)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    A = problems.poisson3d(N)
+    out = {"copy_bytes": src.numel() * 8}
+    for prec in ("fp64", "mixed"):
+        S = amg.Solver(A, precision=prec)
+        for k in S.KERNELS:
+            us, by = S.time_kernel(k, reps=3)
+            out[f"{prec}:{k}"] = {"us": us, "bytes": by}
+        S.release()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +134,9 @@ def main():
     ap.add_argument("--reps", type=int, default=50, help="launches per kernel / V-cycle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only launch a 1 GiB copy and a few launches of each hot kernel (run under "
+                         "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is "
@@ -122,6 +150,9 @@ def main():
     from paper_1811_05704_amd import amg
 
     N, rhs = WORKLOADS[args.workload]
+    if args.pmc_probe:
+        pmc_probe(N, torch, amg, problems)
+        return
     A = problems.poisson3d(N)
     f_host = problems.rhs_uniform(A.n, 0) if rhs == "uniform" else problems.rhs_ones(A.n)
     torch.cuda.set_device(0)

@@ -70,8 +70,10 @@ typedef struct {
   double eps_strong;     /* strength threshold on level 1                      */
   double jacobi_omega;   /* damping of the Jacobi smoother                     */
   double tol;            /* stop when ||r||_2 <= tol * ||f||_2                 */
-  int32_t use_graph;     /* 1: replay the V-cycle as a captured hipGraph        */
-  int32_t check_every;   /* iterations enqueued between host convergence polls  */
+  int32_t use_graph;     /* 1: replay check_every Krylov iterations as one
+                            captured hipGraph; 0: launch kernels directly     */
+  int32_t check_every;   /* iterations enqueued between host convergence polls
+                            (1..64)                                            */
 } amg_params;
 
 /* Optional device allocator; NULL everywhere means hipMalloc / hipFree. */

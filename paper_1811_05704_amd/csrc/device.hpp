@@ -97,8 +97,10 @@ class DevArena {
   size_t bytes_ = 0;
 };
 
-// SpMV schedule selection by row length.
-constexpr double kStreamMaxMean = 12.0;  // mean row length up to which the stream variant is used
+// SpMV schedule selection by row length: the LDS-staged stream kernel with
+// G = 1, 4, 16 or 64 lanes reducing each row, or (very long rows) G = 64 lanes
+// per row reading straight from memory.
+constexpr double kVectorMinMean = 512.0;
 
 template <class T>
 struct DevCsr {
@@ -108,7 +110,7 @@ struct DevCsr {
   int32_t* col = nullptr;
   T* val = nullptr;
   int kind = 0;   // 0 stream, 1 vector
-  int lanes = 1;  // vector variant: lanes per row
+  int lanes = 1;  // lanes per row (stream: in the LDS reduction phase)
   int32_t nblocks = 0;
   int32_t* blk = nullptr;
   CsrView<T> view() const { return CsrView<T>{ptr, col, val, blk, rows, nblocks}; }
@@ -120,23 +122,33 @@ struct Schedule {
   int32_t nblocks = 0;
 };
 
-inline Schedule make_schedule(const Csr& M, int force_kind = -1) {
+inline int stream_lanes(double mean) {
+  if (mean <= 12.0) return 1;
+  if (mean <= 48.0) return 4;
+  if (mean <= 192.0) return 16;
+  return 64;
+}
+
+template <class T>
+Schedule make_schedule(const Csr& M, int force_kind = -1) {
   Schedule s;
   const int64_t rows = M.rows;
   const double mean = rows ? double(M.nnz()) / double(rows) : 0.0;
-  s.kind = force_kind >= 0 ? force_kind : (mean <= kStreamMaxMean ? 0 : 1);
+  s.kind = force_kind >= 0 ? force_kind : (mean <= kVectorMinMean ? 0 : 1);
   if (s.kind == 0) {
+    constexpr int64_t cap = stream_nnz<T>();
+    s.lanes = stream_lanes(mean);
     s.blk.push_back(0);
     int64_t r = 0;
     while (r < rows) {
       const int64_t start = r;
-      if (M.ptr[r + 1] - M.ptr[r] > kStreamNnz) {
+      if (M.ptr[r + 1] - M.ptr[r] > cap) {
         ++r;
       } else {
         int64_t nnz = 0;
-        while (r < rows && r - start < kStreamRows) {
+        while (r < rows && r - start < kStreamMaxRows) {
           const int64_t len = M.ptr[r + 1] - M.ptr[r];
-          if (nnz + len > kStreamNnz) break;
+          if (nnz + len > cap) break;
           nnz += len;
           ++r;
         }
@@ -145,10 +157,8 @@ inline Schedule make_schedule(const Csr& M, int force_kind = -1) {
     }
     s.nblocks = static_cast<int32_t>(s.blk.size()) - 1;
   } else {
-    int lanes = 2;
-    while (lanes < 64 && lanes < mean) lanes *= 2;
-    s.lanes = lanes;
-    const int rpb = kBS / lanes;
+    s.lanes = 64;
+    const int rpb = kBS / s.lanes;
     s.nblocks = static_cast<int32_t>((rows + rpb - 1) / rpb);
   }
   return s;
@@ -171,7 +181,7 @@ DevCsr<T> upload_csr(DevArena& ar, const Csr& M, int force_kind = -1) {
     for (size_t k = 0; k < v.size(); ++k) v[k] = static_cast<T>(M.val[k]);  // round to nearest
     d.val = ar.upload(v.data(), v.size());
   }
-  Schedule s = make_schedule(M, force_kind);
+  Schedule s = make_schedule<T>(M, force_kind);
   d.kind = s.kind;
   d.lanes = s.lanes;
   d.nblocks = s.nblocks;
@@ -187,16 +197,14 @@ template <class T, class G, class E>
 int launch_spmv(const DevCsr<T>& M, G g, E e, double* partials, const int* skip, hipStream_t s) {
   if (M.rows == 0) return 0;
   if (M.kind == 0) {
-    csr_stream_kernel<T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip);
-  } else {
     switch (M.lanes) {
-      case 2: csr_vector_kernel<2, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
-      case 4: csr_vector_kernel<4, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
-      case 8: csr_vector_kernel<8, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
-      case 16: csr_vector_kernel<16, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
-      case 32: csr_vector_kernel<32, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
-      default: csr_vector_kernel<64, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
+      case 1: csr_stream_kernel<1, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
+      case 4: csr_stream_kernel<4, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
+      case 16: csr_stream_kernel<16, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
+      default: csr_stream_kernel<64, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
     }
+  } else {
+    csr_vector_kernel<64, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip);
   }
   AMG_LAUNCHED();
   return M.nblocks;

@@ -32,8 +32,6 @@
 namespace amg {
 
 constexpr int kBS = 256;             // threads per workgroup for the sparse kernels
-constexpr int kStreamNnz = 2048;     // LDS entries per stream block (8 per thread)
-constexpr int kStreamRows = kBS;     // at most one row per thread
 constexpr int kFinBS = 1024;         // finalize workgroup
 constexpr int kNumXcd = 8;
 
@@ -145,6 +143,20 @@ struct EpiStoreDot2 {  // y = A x, dots += (w . y, y . y)
   }
 };
 
+// f_c = R r, plus m_c .* f_c: the next level's first relaxation sweep from a
+// zero guess, gathered by its fused pre-sweep + residual kernel.
+template <class T>
+struct EpiRestrict {
+  static constexpr int K = 0;
+  T* f;
+  T* mf;
+  const T* m;
+  __device__ __forceinline__ void operator()(int i, T s, double*) const {
+    f[i] = s;
+    mf[i] = m[i] * s;
+  }
+};
+
 // r = b - A x, with ||r||^2 and ||b||^2 (FP64 Krylov initial / true residual)
 struct EpiResidNorms {
   static constexpr int K = 2;
@@ -208,31 +220,63 @@ struct EpiSmooth {
 
 // ---------------------------------------------------------------- SpMV kernels
 
+// Entries staged in LDS per stream block: 16 KB of products (2048 FP64 or
+// 4096 FP32 values, 8 or 16 per thread).
+template <class T>
+constexpr int stream_nnz() {
+  return 16384 / static_cast<int>(sizeof(T));
+}
+constexpr int kStreamMaxRows = 1024;  // rows per stream block
+
 // Stream variant.  Block b covers rows [blk[b], blk[b+1]): either at most
-// kStreamRows rows with at most kStreamNnz entries, or a single longer row.
-template <class T, class G, class E>
-__global__ void __launch_bounds__(kBS) csr_stream_kernel(CsrView<T> A, G gather, E epi,
+// kStreamMaxRows rows with at most stream_nnz<T>() entries, or a single longer
+// row.  Phase 1: every lane loads its share of the block's val/col (all loads
+// issued before any use; streamed with non-temporal hints so that L2 keeps x),
+// gathers x and stores the products in LDS.  Phase 2: G lanes per row sum the
+// row's products (strided, then a butterfly) and apply the epilogue.
+template <int G, class T, class Gth, class E>
+__global__ void __launch_bounds__(kBS) csr_stream_kernel(CsrView<T> A, Gth gather, E epi,
                                                          double* partials, const int* skip) {
   if (skip && *skip) return;
-  __shared__ T prod[kStreamNnz];
+  constexpr int NNZ = stream_nnz<T>();
+  constexpr int PER = NNZ / kBS;
+  __shared__ T prod[NNZ + kBS];  // the last kBS slots take surplus lanes' products
   const int vb = xcd_remap(blockIdx.x, gridDim.x);
   const int r0 = A.blk[vb], r1 = A.blk[vb + 1];
   const int e0 = A.ptr[r0], e1 = A.ptr[r1];
+  const int cnt = e1 - e0;
   const int tid = threadIdx.x;
   double d[E::K > 0 ? E::K : 1] = {};
-  if (e1 - e0 <= kStreamNnz) {
+  if (cnt <= NNZ) {
+    if (cnt > 0) {
+      // All loads of a lane are issued before any is used, and nothing is
+      // predicated: surplus lanes re-read the block's last entry and park
+      // their product in the spare slots.
+      int c[PER];
+      T v[PER];
 #pragma unroll
-    for (int k = 0; k < kStreamNnz / kBS; ++k) {
-      const int e = e0 + k * kBS + tid;
-      if (e < e1) prod[k * kBS + tid] = A.val[e] * gather(A.col[e]);
+      for (int k = 0; k < PER; ++k) {
+        const int e = min(e0 + k * kBS + tid, e1 - 1);
+        c[k] = __builtin_nontemporal_load(A.col + e);
+        v[k] = __builtin_nontemporal_load(A.val + e);
+      }
+      T x[PER];
+#pragma unroll
+      for (int k = 0; k < PER; ++k) x[k] = gather(c[k]);
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int slot = k * kBS + tid;
+        prod[slot < cnt ? slot : NNZ + tid] = v[k] * x[k];
+      }
     }
     __syncthreads();
-    const int i = r0 + tid;
-    if (i < r1) {
+    const int lane = tid % G;
+    for (int i = r0 + tid / G; i < r1; i += kBS / G) {
       const int b = A.ptr[i] - e0, e = A.ptr[i + 1] - e0;
       T s = T(0);
-      for (int k = b; k < e; ++k) s += prod[k];
-      epi(i, s, d);
+      for (int k = b + lane; k < e; k += G) s += prod[k];
+      s = group_sum<G>(s);
+      if (lane == 0) epi(i, s, d);
     }
   } else {
     // one long row: strided over the workgroup, then a fixed-order tree
@@ -318,9 +362,17 @@ __global__ void __launch_bounds__(kFinBS) finalize_kernel(const double* partials
   double s[2] = {0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    double a = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += kFinBS) a += partials[k * nparts + b];
-    a = wave_sum(a);
+    const double* p = partials + k * nparts;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 3 * kFinBS < nparts; b += 4 * kFinBS) {
+      a0 += p[b];
+      a1 += p[b + kFinBS];
+      a2 += p[b + 2 * kFinBS];
+      a3 += p[b + 3 * kFinBS];
+    }
+    for (; b < nparts; b += kFinBS) a0 += p[b];
+    double a = wave_sum((a0 + a1) + (a2 + a3));
     if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = a;
   }
   __syncthreads();
@@ -515,20 +567,30 @@ __global__ void __launch_bounds__(kVecBS) scale_kernel(int n, T* z, const T* m, 
 // ---------------------------------------------------------------- coarse solve
 
 // z = Ainv f with the dense inverse of the coarsest operator (FP64, row-major),
-// one wavefront per row, FP64 accumulation; f and z in the V-cycle's types.
+// one workgroup per row, FP64 accumulation; f and z in the V-cycle's types.
 template <class TF, class TZ>
 __global__ void __launch_bounds__(kBS) coarse_gemv_kernel(int n, const double* __restrict__ Ainv,
                                                           const TF* __restrict__ f, TZ* __restrict__ z,
                                                           const int* skip) {
   if (skip && *skip) return;
-  const int row = blockIdx.x * (kBS / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= n) return;
+  const int row = blockIdx.x;
   const double* a = Ainv + static_cast<int64_t>(row) * n;
-  double s = 0.0;
-  for (int j = lane; j < n; j += 64) s += a[j] * static_cast<double>(f[j]);
-  s = wave_sum(s);
-  if (lane == 0) z[row] = static_cast<TZ>(s);
+  double s0 = 0.0, s1 = 0.0;
+  int j = threadIdx.x;
+  for (; j + kBS < n; j += 2 * kBS) {
+    s0 += a[j] * static_cast<double>(f[j]);
+    s1 += a[j + kBS] * static_cast<double>(f[j + kBS]);
+  }
+  if (j < n) s0 += a[j] * static_cast<double>(f[j]);
+  double s = wave_sum(s0 + s1);
+  __shared__ double sh[kBS / 64];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBS / 64; ++w) t += sh[w];
+    z[row] = static_cast<TZ>(t);
+  }
 }
 
 // partials of a . b (FP64)

@@ -59,7 +59,8 @@ struct DevLevel {
   T* y = nullptr;  // prolongated correction
   T* t = nullptr;  // ping-pong buffer for repeated sweeps
   T* zp[2] = {nullptr, nullptr};  // stored pre-smoothed iterate (npre > 1)
-  T* z = nullptr;  // output on levels > 0
+  T* z = nullptr;   // output on levels > 0
+  T* mf = nullptr;  // m .* f, written by the restriction (levels > 0, npre = 1)
 };
 
 template <class T>
@@ -87,7 +88,7 @@ class Vcycle {
   int run(const double* f0, double* z0, double* partials, const int* skip, hipStream_t s) {
     const int L = static_cast<int>(h_->lev.size()) + 1;
     if (L == 1) {
-      coarse_gemv_kernel<double, double><<<(nL_ + 3) / 4, kBS, 0, s>>>(nL_, Ainv_, f0, z0, skip);
+      coarse_gemv_kernel<double, double><<<nL_, kBS, 0, s>>>(nL_, Ainv_, f0, z0, skip);
       AMG_LAUNCHED();
       if (DOT) {
         int nb = vec_blocks(nL_);
@@ -100,11 +101,11 @@ class Vcycle {
     // down
     for (int l = 0; l < L - 1; ++l) {
       DevLevel<T>& lv = h_->lev[l];
-      T* fnext = (l + 1 < L - 1) ? h_->lev[l + 1].f : h_->fL;
-      if (l == 0) down<double>(lv, f0, fnext, skip, s);
-      else down<T>(lv, lv.f, fnext, skip, s);
+      DevLevel<T>* next = (l + 1 < L - 1) ? &h_->lev[l + 1] : nullptr;
+      if (l == 0) down<double>(lv, f0, next, skip, s);
+      else down<T>(lv, lv.f, next, skip, s);
     }
-    coarse_gemv_kernel<T, T><<<(nL_ + 3) / 4, kBS, 0, s>>>(nL_, Ainv_, h_->fL, h_->zL, skip);
+    coarse_gemv_kernel<T, T><<<nL_, kBS, 0, s>>>(nL_, Ainv_, h_->fL, h_->zL, skip);
     AMG_LAUNCHED();
     // up
     int nparts = 0;
@@ -118,15 +119,32 @@ class Vcycle {
   }
 
  private:
-  // Pre-relaxation, residual and restriction of one level.
+  // Pre-relaxation, residual and restriction of one level.  `next` is the
+  // next level (NULL when that is the coarsest).  On levels > 0 with one
+  // pre-sweep, m .* f was written by the restriction that produced f.
   template <class TF>
-  void down(DevLevel<T>& lv, const TF* f, T* fnext, const int* skip, hipStream_t s) {
+  void down(DevLevel<T>& lv, const TF* f, DevLevel<T>* next, const int* skip, hipStream_t s) {
+    T* fnext = next ? next->f : h_->fL;
+    auto restrict_from = [&](auto gather) {
+      if (next && o_.npre == 1)
+        launch_spmv(lv.R, gather, EpiRestrict<T>{next->f, next->mf, next->m}, nullptr, skip, s);
+      else
+        launch_spmv(lv.R, gather, EpiStore<T, T>{fnext}, nullptr, skip, s);
+    };
     if (o_.npre == 0) {
-      launch_spmv(lv.R, GatherX<T, TF>{f}, EpiStore<T, T>{fnext}, nullptr, skip, s);
+      restrict_from(GatherX<T, TF>{f});
       return;
     }
     if (o_.npre == 1) {
-      launch_spmv(lv.A, GatherMF<T, TF>{lv.m, f}, EpiResid<T, TF>{lv.r, f}, nullptr, skip, s);
+      if constexpr (std::is_same<TF, T>::value) {
+        if (lv.mf) {
+          launch_spmv(lv.A, GatherX<T, T>{lv.mf}, EpiResid<T, TF>{lv.r, f}, nullptr, skip, s);
+        } else {
+          launch_spmv(lv.A, GatherMF<T, TF>{lv.m, f}, EpiResid<T, TF>{lv.r, f}, nullptr, skip, s);
+        }
+      } else {
+        launch_spmv(lv.A, GatherMF<T, TF>{lv.m, f}, EpiResid<T, TF>{lv.r, f}, nullptr, skip, s);
+      }
     } else {
       scale_kernel<T, TF><<<vec_blocks(lv.n), kVecBS, 0, s>>>(lv.n, lv.zp[0], lv.m, f, skip);
       AMG_LAUNCHED();
@@ -139,7 +157,7 @@ class Vcycle {
       pre_cur_ = cur;
       launch_spmv(lv.A, GatherX<T, T>{lv.zp[cur]}, EpiResid<T, TF>{lv.r, f}, nullptr, skip, s);
     }
-    launch_spmv(lv.R, GatherX<T, T>{lv.r}, EpiStore<T, T>{fnext}, nullptr, skip, s);
+    restrict_from(GatherX<T, T>{lv.r});
   }
 
   // Prolongation + correction and post-relaxation of one level; output zout.
@@ -149,7 +167,10 @@ class Vcycle {
     if (o_.npre == 0) {
       launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 0>{lv.y, lv.m, f, nullptr}, nullptr, skip, s);
     } else if (o_.npre == 1) {
-      launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 1>{lv.y, lv.m, f, nullptr}, nullptr, skip, s);
+      if (lv.mf)
+        launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 2>{lv.y, lv.m, f, lv.mf}, nullptr, skip, s);
+      else
+        launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 1>{lv.y, lv.m, f, nullptr}, nullptr, skip, s);
     } else {
       launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 2>{lv.y, lv.m, f, lv.zp[pre_cur_]}, nullptr,
                   skip, s);
@@ -244,7 +265,7 @@ void check_params(const amg_params& p) {
   if (p.npre < 0 || p.npost < 0 || p.npre > 16 || p.npost > 16) throw SetupError{-1, "npre/npost must be in [0, 16]"};
   if (p.coarse_enough < 1 || p.max_levels < 1 || p.max_iter < 1) throw SetupError{-1, "coarse_enough, max_levels, max_iter must be >= 1"};
   if (!(p.tol >= 0.0) || !(p.eps_strong >= 0.0)) throw SetupError{-1, "tol and eps_strong must be >= 0"};
-  if (p.check_every < 1) throw SetupError{-1, "check_every must be >= 1"};
+  if (p.check_every < 1 || p.check_every > 64) throw SetupError{-1, "check_every must be in [1, 64]"};
 }
 
 Csr to_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val) {
@@ -313,6 +334,7 @@ void upload_levels(amg_solver& S, DevHierarchy<T>& H) {
     if (l > 0) {
       d.f = ar.get<T>(d.n);
       d.z = ar.get<T>(d.n);
+      if (npre == 1) d.mf = ar.get<T>(d.n);
     }
     d.r = ar.get<T>(d.n);
     d.y = ar.get<T>(d.n);
@@ -429,7 +451,7 @@ void build_graph(amg_solver& S) {
   if (S.iter_exec) return;
   AMG_HIP(hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal));
   try {
-    enqueue_iteration(S, S.cap_stream);
+    for (int it = 0; it < S.prm.check_every; ++it) enqueue_iteration(S, S.cap_stream);
   } catch (...) {
     hipGraph_t g;
     (void)hipStreamEndCapture(S.cap_stream, &g);
@@ -467,9 +489,10 @@ amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, hipStrea
     else enqueue_bicg_start(S, s);
     k = poll(S, s);
     while (k.done == kRunning) {
-      for (int it = 0; it < S.prm.check_every; ++it) {
-        if (S.prm.use_graph) AMG_HIP(hipGraphLaunch(S.iter_exec, s));
-        else enqueue_iteration(S, s);
+      if (S.prm.use_graph) {
+        AMG_HIP(hipGraphLaunch(S.iter_exec, s));  // check_every iterations
+      } else {
+        for (int it = 0; it < S.prm.check_every; ++it) enqueue_iteration(S, s);
       }
       k = poll(S, s);
     }
@@ -679,42 +702,62 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
   fill_kernel<T><<<vec_blocks(lv.n), kVecBS, 0, s>>>(lv.n, lv.y, T(1));
   fill_kernel<T><<<vec_blocks(lv.nc), kVecBS, 0, s>>>(lv.nc, const_cast<T*>(zc), T(1));
   AMG_LAUNCHED();
-  hipEvent_t e0, e1;
-  AMG_HIP(hipEventCreate(&e0));
-  AMG_HIP(hipEventCreate(&e1));
-  auto launch = [&]() {
+  auto launch = [&](hipStream_t st) {
     switch (which) {
       case 0:
-        launch_spmv(S.A0, GatherX<double, double>{S.p}, EpiStoreDot{S.q, S.p}, S.partials, nullptr, s);
+        launch_spmv(S.A0, GatherX<double, double>{S.p}, EpiStoreDot{S.q, S.p}, S.partials, nullptr, st);
         break;
       case 1:
-        launch_spmv(lv.A, GatherMF<T, double>{lv.m, S.r}, EpiResid<T, double>{lv.r, S.r}, nullptr, nullptr, s);
+        launch_spmv(lv.A, GatherMF<T, double>{lv.m, S.r}, EpiResid<T, double>{lv.r, S.r}, nullptr, nullptr, st);
         break;
       case 2:
         launch_spmv(lv.A, GatherX<T, T>{lv.y}, EpiSmooth<T, double, double, 1>{S.z, lv.y, lv.m, S.r}, S.partials,
-                    nullptr, s);
+                    nullptr, st);
         break;
       case 3:
-        launch_spmv(lv.R, GatherX<T, T>{lv.r}, EpiStore<T, T>{fnext}, nullptr, nullptr, s);
+        launch_spmv(lv.R, GatherX<T, T>{lv.r}, EpiStore<T, T>{fnext}, nullptr, nullptr, st);
         break;
-      default:
-        launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, double, 1>{lv.y, lv.m, S.r, nullptr}, nullptr, nullptr, s);
+      case 4:
+        launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, double, 1>{lv.y, lv.m, S.r, nullptr}, nullptr, nullptr,
+                    st);
         break;
+      default: {
+        VcycleOpts o{S.prm.npre, S.prm.npost};
+        Vcycle<T> V(&H, S.Ainv, S.nL, o);
+        V.template run<0>(S.r, S.z, S.partials, nullptr, st);
+        break;
+      }
     }
   };
+  // The timed launches are captured into one graph so that the measured
+  // interval holds only device work (no host launch gaps).
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  AMG_HIP(hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int k = 0; k < reps; ++k) launch(S.cap_stream);
+  } catch (...) {
+    (void)hipStreamEndCapture(S.cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  AMG_HIP(hipStreamEndCapture(S.cap_stream, &g));
+  AMG_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+  hipEvent_t e0, e1;
+  AMG_HIP(hipEventCreate(&e0));
+  AMG_HIP(hipEventCreate(&e1));
+  AMG_HIP(hipGraphLaunch(ge, s));  // warm-up
+  AMG_HIP(hipEventRecord(e0, s));
+  AMG_HIP(hipGraphLaunch(ge, s));
+  AMG_HIP(hipEventRecord(e1, s));
+  AMG_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(ge);
+  (void)hipGraphDestroy(g);
   if (which == 5) {
-    VcycleOpts o{S.prm.npre, S.prm.npost};
-    Vcycle<T> V(&H, S.Ainv, S.nL, o);
-    auto cycle = [&]() { V.template run<0>(S.r, S.z, S.partials, nullptr, s); };
-    cycle();
-    AMG_HIP(hipEventRecord(e0, s));
-    for (int k = 0; k < reps; ++k) cycle();
-    AMG_HIP(hipEventRecord(e1, s));
-    AMG_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     // Algorithmic bytes of one V-cycle with npre = npost = 1: per level
     // 2 passes over A_l, one over P_l and R_l each, 11 vector passes of n_l
     // (level 1: f and z are FP64), 2 of n_{l+1}; dense coarse inverse + f, z.
@@ -730,15 +773,6 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
     *bytes = b;
     return 1000.0 * ms / reps;
   }
-  launch();  // warm-up
-  AMG_HIP(hipEventRecord(e0, s));
-  for (int k = 0; k < reps; ++k) launch();
-  AMG_HIP(hipEventRecord(e1, s));
-  AMG_HIP(hipEventSynchronize(e1));
-  float ms = 0.f;
-  AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   const double idx = 4.0;
   switch (which) {
     case 0: *bytes = zA * (8 + idx) + idx * (n + 1) + 16 * n; break;                    // p in, q out

@@ -1,9 +1,10 @@
 """Device SpMV kernels vs a plain CPU product (GPU).
 
-Covers both SpMV variants the library selects by row length (LDS-staged
-stream blocks for short rows, including rows longer than one LDS block; G
-lanes per row for long rows), empty rows, a ragged tail, rectangular shapes,
-FP64 and FP32, and sampled rows of the full-size 150^3 Poisson operator.
+Covers the SpMV variants the library selects by mean row length (LDS-staged
+stream blocks whose rows are reduced by G = 1, 4, 16 or 64 lanes, including
+rows longer than one LDS block; 64 lanes per row straight from memory for
+very long rows), empty rows, a ragged tail, rectangular shapes, FP64 and
+FP32, and sampled rows of the full-size 150^3 Poisson operator.
 """
 
 import zlib
@@ -50,9 +51,11 @@ CASES = [
     ("one_row", 1, 50, lambda r: np.array([7])),
     ("long_row_in_stream", 3000, 6000, lambda r: np.where(np.arange(3000) == 1234, 5000, r.integers(1, 8, 3000))),
     ("rectangular_tall", 20000, 3000, lambda r: r.integers(1, 5, 20000)),
-    ("vector_13", 4001, 4001, lambda r: r.integers(10, 17, 4001)),
-    ("vector_30", 3001, 5000, lambda r: r.integers(20, 41, 3001)),
-    ("vector_100", 1003, 5000, lambda r: r.integers(60, 141, 1003)),
+    ("stream_g4_13", 4001, 4001, lambda r: r.integers(10, 17, 4001)),
+    ("stream_g4_30", 3001, 5000, lambda r: r.integers(20, 41, 3001)),
+    ("stream_g16_100", 1003, 5000, lambda r: r.integers(60, 141, 1003)),
+    ("stream_g64_300", 503, 5000, lambda r: r.integers(200, 401, 503)),
+    ("stream_g64_mixed_long", 203, 20000, lambda r: np.where(np.arange(203) % 50 == 7, 6000, r.integers(200, 400, 203))),
     ("vector_long_rows", 300, 20000, lambda r: r.integers(1000, 9000, 300)),
 ]
 
@@ -67,7 +70,10 @@ def test_spmv_matches_cpu(name, rows, cols, gen, precision):
     x, y, info = _run(rows, cols, rp, col, val, prec)
     yr, scale = _ref(rp, col, val, rows, cols, x, precision)
     mean = rp[-1] / max(rows, 1)
-    assert info["kind"] == ("stream" if mean <= 12 else "vector")
+    assert info["kind"] == ("stream" if mean <= 512 else "vector")
+    if info["kind"] == "stream":
+        expect = 1 if mean <= 12 else 4 if mean <= 48 else 16 if mean <= 192 else 64
+        assert info["lanes"] == expect
     # worst case grows with the row length (per-lane partial sums + a tree)
     tol = 5e-14 if precision == "fp64" else 2e-5
     err = np.abs(y - yr)
