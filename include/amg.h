@@ -201,6 +201,47 @@ void amg_csr_release(amg_matrix m);
 amg_status amg_time_kernel(amg_handle h, int32_t which, int32_t reps, void* hip_stream,
                            double* avg_us, double* bytes);
 
+/* --- serving: continuous batching of many independent systems -------------- */
+
+/*
+ * A request loop over independent systems A u = f of uneven sizes (section 3:
+ * the hierarchy depends only on A, is built on the CPU and then lives on the
+ * backend).  Submitted requests are set up by `setup_threads` host worker
+ * threads, placed in a device pool of hbm_budget_bytes (allocated once here;
+ * a request whose footprint exceeds the budget fails with AMG_ERR_OOM) and
+ * admitted into one of max_slots (1..64) live slots at an iteration
+ * boundary.  Each amg_server_step admits what is ready, runs check_every PCG
+ * iterations of every live solve in one captured graph of batched kernels
+ * (one launch per operation covers all live solves), then retires the
+ * solves that stopped.  Parameters as for amg_setup, restricted to PCG with
+ * npre = npost = 1; precision AMG_MIXED is the served configuration.  A
+ * request's solution is bitwise identical to amg_solve's for the same system
+ * and parameters, whatever else is in the batch.  Not thread-safe: one
+ * thread drives a server.
+ */
+typedef struct amg_server_s* amg_server;
+amg_status amg_server_create(const amg_params* p, size_t hbm_budget_bytes, int32_t max_slots,
+                             int32_t setup_threads, void* hip_stream, amg_server* out);
+/* Copy a request in (host arrays, validated like amg_setup; f_host double[n]). */
+amg_status amg_server_submit(amg_server s, uint64_t request_id, int64_t n, const int64_t* row_ptr,
+                             const int32_t* col, const double* val, const double* f_host);
+/* One step; *live = solves in slots after it, *waiting = submitted, not yet admitted. */
+amg_status amg_server_step(amg_server s, int32_t* live, int32_t* waiting);
+/* Block until at least `count` submitted requests are set up and waiting for
+ * a slot (AMG_OK), or until timeout_s passes or nothing is left in setup
+ * (AMG_NOT_CONVERGED); *ready (may be NULL) = requests waiting for a slot. */
+amg_status amg_server_wait_ready(amg_server s, int32_t count, double timeout_s, int32_t* ready);
+/* Oldest finished request: AMG_OK with its id and size n (0 if it failed before
+ * solving), or AMG_NOT_CONVERGED (1) when none is finished. */
+amg_status amg_server_poll(amg_server s, uint64_t* request_id, int64_t* n);
+/* Take that request: x_host double[n] (may be NULL), info (may be NULL), times
+ * (may be NULL) = {submit, setup done, admitted, finished} in seconds of a
+ * monotonic clock.  Returns the request's own status. */
+amg_status amg_server_fetch(amg_server s, uint64_t request_id, double* x_host, amg_info* info,
+                            double* times);
+/* Stop the workers and free everything.  NULL-safe. */
+void amg_server_destroy(amg_server s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -96,6 +96,13 @@ def lib():
         "amg_csr_kernel_info": (i32, [vp, P32, P32, P32]),
         "amg_csr_release": (None, [vp]),
         "amg_time_kernel": (i32, [vp, i32, i32, vp, PD, PD]),
+        "amg_server_create": (i32, [C.POINTER(Params), C.c_size_t, i32, i32, vp, C.POINTER(vp)]),
+        "amg_server_submit": (i32, [vp, C.c_uint64, i64, P64, P32, PD, PD]),
+        "amg_server_step": (i32, [vp, P32, P32]),
+        "amg_server_wait_ready": (i32, [vp, i32, C.c_double, P32]),
+        "amg_server_poll": (i32, [vp, C.POINTER(C.c_uint64), P64]),
+        "amg_server_fetch": (i32, [vp, C.c_uint64, PD, C.POINTER(Info), PD]),
+        "amg_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -111,6 +118,8 @@ def exported_symbols():
         "amg_last_error", "amg_vcycle", "amg_num_levels", "amg_level_info", "amg_get_aggregates",
         "amg_get_level_csr", "amg_get_smoother", "amg_csr_upload", "amg_csr_spmv",
         "amg_csr_kernel_info", "amg_csr_release", "amg_time_kernel",
+        "amg_server_create", "amg_server_submit", "amg_server_step", "amg_server_wait_ready", "amg_server_poll",
+        "amg_server_fetch", "amg_server_destroy",
     ]
 
 
@@ -355,6 +364,72 @@ class DeviceMatrix:
     def release(self):
         if self._h:
             lib().amg_csr_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop (``amg_server_*``).
+
+    ``submit`` copies a system in; ``step`` admits ready requests, runs
+    ``check_every`` batched PCG iterations of every live solve and retires
+    finished ones; ``results`` drains finished requests as
+    ``(request_id, x, info, status, times)`` with times = (submit, setup done,
+    admitted, finished) on the library's monotonic clock.
+    """
+
+    def __init__(self, hbm_budget_bytes, max_slots=32, setup_threads=8, **params):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("amg.Server needs a HIP device")
+        params.setdefault("precision", "mixed")
+        self.params = make_params(**params)
+        h = C.c_void_p()
+        _check(lib().amg_server_create(C.byref(self.params), int(hbm_budget_bytes), int(max_slots),
+                                       int(setup_threads), C.c_void_p(_torch_stream().cuda_stream), C.byref(h)))
+        self._h = h
+
+    def submit(self, request_id, A, f):
+        rp, c, v = _csr_arrays(A)
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        _check(lib().amg_server_submit(self._h, int(request_id), int(A.n), _ptr(rp, C.c_int64),
+                                       _ptr(c, C.c_int32), _ptr(v, C.c_double), _ptr(f, C.c_double)))
+
+    def wait_ready(self, count, timeout=60.0):
+        """Block until ``count`` requests are set up (True) or timeout / nothing left (False)."""
+        r = C.c_int32()
+        return _check(lib().amg_server_wait_ready(self._h, int(count), float(timeout), C.byref(r))) == AMG_OK
+
+    def step(self):
+        live, waiting = C.c_int32(), C.c_int32()
+        _check(lib().amg_server_step(self._h, C.byref(live), C.byref(waiting)))
+        return live.value, waiting.value
+
+    def results(self):
+        out = []
+        while True:
+            rid, n = C.c_uint64(), C.c_int64()
+            code = _check(lib().amg_server_poll(self._h, C.byref(rid), C.byref(n)))
+            if code == AMG_NOT_CONVERGED:
+                return out
+            x = np.empty(n.value, dtype=np.float64)
+            info = Info()
+            times = np.zeros(4, dtype=np.float64)
+            status = lib().amg_server_fetch(self._h, rid.value, _ptr(x, C.c_double), C.byref(info),
+                                            _ptr(times, C.c_double))
+            d = info.as_dict()
+            d["status"] = status
+            out.append((rid.value, x, d, status, tuple(times)))
+
+    def release(self):
+        if self._h:
+            lib().amg_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

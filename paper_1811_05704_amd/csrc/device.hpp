@@ -79,6 +79,8 @@ class DevArena {
   }
   size_t bytes() const { return bytes_; }
   hipStream_t stream() const { return stream_; }
+  // Stream that release() synchronises before freeing (the owner's compute stream).
+  void set_stream(hipStream_t s) { stream_ = s; }
   void release() {
     if (!blocks_.empty()) (void)hipStreamSynchronize(stream_);
     for (void* p : blocks_) {

@@ -37,7 +37,10 @@ namespace {
 constexpr int32_t kUnagg = -2;
 constexpr int32_t kIsolated = -1;
 
+thread_local int tl_max_threads = 0;  // 0: use the hardware concurrency (at most 16)
+
 int num_threads() {
+  if (tl_max_threads > 0) return tl_max_threads;
   unsigned h = std::thread::hardware_concurrency();
   if (h == 0) h = 1;
   return static_cast<int>(std::min(h, 16u));
@@ -72,6 +75,8 @@ std::vector<double> diagonal(const Csr& A) {
 }
 
 }  // namespace
+
+void set_setup_threads(int n) { tl_max_threads = n; }
 
 void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val) {
   if (n <= 0 || !ptr || !col || !val) fail(-1, "null array or non-positive size");

@@ -48,6 +48,9 @@ struct SetupError {
 // Validate a CSR input as the C ABI requires; throws SetupError.
 void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val);
 
+// Limit the worker threads the setup of the calling thread uses (0 = default).
+void set_setup_threads(int n);
+
 // Full hierarchy; throws SetupError.
 HostHierarchy build_hierarchy(Csr A, const SetupParams& prm);
 

@@ -228,20 +228,19 @@ constexpr int stream_nnz() {
 }
 constexpr int kStreamMaxRows = 1024;  // rows per stream block
 
-// Stream variant.  Block b covers rows [blk[b], blk[b+1]): either at most
+// Stream variant.  Block vb covers rows [blk[vb], blk[vb+1]): either at most
 // kStreamMaxRows rows with at most stream_nnz<T>() entries, or a single longer
 // row.  Phase 1: every lane loads its share of the block's val/col (all loads
 // issued before any use; streamed with non-temporal hints so that L2 keeps x),
 // gathers x and stores the products in LDS.  Phase 2: G lanes per row sum the
-// row's products (strided, then a butterfly) and apply the epilogue.
+// row's products (strided, then a butterfly) and apply the epilogue.  The
+// block's dot-product partials go to partials[k * nparts + vb].  `prod` is the
+// caller's LDS buffer of stream_nnz<T>() + kBS entries.
 template <int G, class T, class Gth, class E>
-__global__ void __launch_bounds__(kBS) csr_stream_kernel(CsrView<T> A, Gth gather, E epi,
-                                                         double* partials, const int* skip) {
-  if (skip && *skip) return;
+__device__ __forceinline__ void stream_block(const CsrView<T>& A, const Gth& gather, const E& epi, int vb,
+                                             double* partials, int nparts, T* prod) {
   constexpr int NNZ = stream_nnz<T>();
   constexpr int PER = NNZ / kBS;
-  __shared__ T prod[NNZ + kBS];  // the last kBS slots take surplus lanes' products
-  const int vb = xcd_remap(blockIdx.x, gridDim.x);
   const int r0 = A.blk[vb], r1 = A.blk[vb + 1];
   const int e0 = A.ptr[r0], e1 = A.ptr[r1];
   const int cnt = e1 - e0;
@@ -282,22 +281,29 @@ __global__ void __launch_bounds__(kBS) csr_stream_kernel(CsrView<T> A, Gth gathe
     // one long row: strided over the workgroup, then a fixed-order tree
     T s = T(0);
     for (int e = e0 + tid; e < e1; e += kBS) s += A.val[e] * gather(A.col[e]);
-    __shared__ T red[kBS / 64];
     s = group_sum<64>(s);
-    if ((tid & 63) == 0) red[tid >> 6] = s;
+    if ((tid & 63) == 0) prod[tid >> 6] = s;
     __syncthreads();
     if (tid == 0) {
       T t = T(0);
-      for (int w = 0; w < kBS / 64; ++w) t += red[w];
+      for (int w = 0; w < kBS / 64; ++w) t += prod[w];
       epi(r0, t, d);
     }
   }
-  if constexpr (E::K > 0) block_partials<E::K, kBS>(d, partials, gridDim.x, vb);
+  if constexpr (E::K > 0) block_partials<E::K, kBS>(d, partials, nparts, vb);
+}
+
+template <int G, class T, class Gth, class E>
+static __global__ void __launch_bounds__(kBS) csr_stream_kernel(CsrView<T> A, Gth gather, E epi,
+                                                         double* partials, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ T prod[stream_nnz<T>() + kBS];  // the last kBS slots take surplus lanes' products
+  stream_block<G>(A, gather, epi, xcd_remap(blockIdx.x, gridDim.x), partials, gridDim.x, prod);
 }
 
 // Vector variant: L lanes per row, kBS / L rows per workgroup.
 template <int L, class T, class G, class E>
-__global__ void __launch_bounds__(kBS) csr_vector_kernel(CsrView<T> A, G gather, E epi,
+static __global__ void __launch_bounds__(kBS) csr_vector_kernel(CsrView<T> A, G gather, E epi,
                                                          double* partials, const int* skip) {
   if (skip && *skip) return;
   constexpr int RPB = kBS / L;
@@ -350,8 +356,7 @@ enum FinOp : int {
 };
 
 template <int K>
-__global__ void __launch_bounds__(kFinBS) finalize_kernel(const double* partials, int nparts,
-                                                          KState* st, int op) {
+__device__ __forceinline__ void finalize_body(const double* partials, int nparts, KState* st, int op) {
   const bool always = (op == kFinInit || op == kFinTrue || op == kFinBiHalfDone);
   if (!always && st->done != kRunning) return;
   if (op == kFinBiHalfDone) {
@@ -450,6 +455,12 @@ __global__ void __launch_bounds__(kFinBS) finalize_kernel(const double* partials
   }
 }
 
+template <int K>
+static __global__ void __launch_bounds__(kFinBS) finalize_kernel(const double* partials, int nparts,
+                                                               KState* st, int op) {
+  finalize_body<K>(partials, nparts, st, op);
+}
+
 // ---------------------------------------------------------------- vector kernels (FP64)
 
 constexpr int kVecBS = 256;
@@ -458,35 +469,46 @@ __device__ __forceinline__ int vec_grid_start() {
   return xcd_remap(blockIdx.x, gridDim.x) * kVecBS + threadIdx.x;
 }
 
-// x += alpha p; r -= alpha q; partial r.r
-__global__ void __launch_bounds__(kVecBS) pcg_update_kernel(int n, double* x, double* r,
-                                                            const double* p, const double* q,
-                                                            const KState* st, double* partials) {
-  if (st->done != kRunning) return;
+// x += alpha p; r -= alpha q; partial r.r.  Block vb of nb handles indices
+// vb*kVecBS + tid + k*nb*kVecBS and writes partial slot vb.
+__device__ __forceinline__ void pcg_update_block(int n, double* x, double* r, const double* p, const double* q,
+                                                 const KState* st, double* partials, int vb, int nb) {
   const double alpha = st->alpha;
   double d[1] = {0.0};
-  const int stride = gridDim.x * kVecBS;
-  for (int i = vec_grid_start(); i < n; i += stride) {
+  const int stride = nb * kVecBS;
+  for (int i = vb * kVecBS + threadIdx.x; i < n; i += stride) {
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
     d[0] += ri * ri;
   }
-  block_partials<1, kVecBS>(d, partials, gridDim.x, xcd_remap(blockIdx.x, gridDim.x));
+  block_partials<1, kVecBS>(d, partials, nb, vb);
+}
+
+static __global__ void __launch_bounds__(kVecBS) pcg_update_kernel(int n, double* x, double* r,
+                                                                   const double* p, const double* q,
+                                                                   const KState* st, double* partials) {
+  if (st->done != kRunning) return;
+  pcg_update_block(n, x, r, p, q, st, partials, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 // p = z + beta p  (p = z on the first iteration)
-__global__ void __launch_bounds__(kVecBS) pcg_dir_kernel(int n, double* p, const double* z,
-                                                         const KState* st) {
-  if (st->done != kRunning) return;
+__device__ __forceinline__ void pcg_dir_block(int n, double* p, const double* z, const KState* st, int vb,
+                                              int nb) {
   const double beta = st->beta;
   const bool first = st->first;
-  const int stride = gridDim.x * kVecBS;
-  for (int i = vec_grid_start(); i < n; i += stride) p[i] = first ? z[i] : z[i] + beta * p[i];
+  const int stride = nb * kVecBS;
+  for (int i = vb * kVecBS + threadIdx.x; i < n; i += stride) p[i] = first ? z[i] : z[i] + beta * p[i];
+}
+
+static __global__ void __launch_bounds__(kVecBS) pcg_dir_kernel(int n, double* p, const double* z,
+                                                                const KState* st) {
+  if (st->done != kRunning) return;
+  pcg_dir_block(n, p, z, st, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 // BiCGStab: p = r (first) or p = r + beta (p - omega v)
-__global__ void __launch_bounds__(kVecBS) bicg_p_kernel(int n, double* p, const double* r,
+static __global__ void __launch_bounds__(kVecBS) bicg_p_kernel(int n, double* p, const double* r,
                                                         const double* v, const KState* st) {
   if (st->done != kRunning) return;
   const double beta = st->beta, omega = st->omega;
@@ -497,7 +519,7 @@ __global__ void __launch_bounds__(kVecBS) bicg_p_kernel(int n, double* p, const 
 }
 
 // BiCGStab: s = r - alpha v; partial s.s
-__global__ void __launch_bounds__(kVecBS) bicg_s_kernel(int n, double* s, const double* r,
+static __global__ void __launch_bounds__(kVecBS) bicg_s_kernel(int n, double* s, const double* r,
                                                         const double* v, const KState* st,
                                                         double* partials) {
   if (st->done != kRunning) return;
@@ -513,7 +535,7 @@ __global__ void __launch_bounds__(kVecBS) bicg_s_kernel(int n, double* s, const 
 }
 
 // BiCGStab half-step exit: x += alpha p_hat (only when the s-test passed)
-__global__ void __launch_bounds__(kVecBS) bicg_half_kernel(int n, double* x, const double* phat,
+static __global__ void __launch_bounds__(kVecBS) bicg_half_kernel(int n, double* x, const double* phat,
                                                            const KState* st) {
   if (st->done != kHalfStep) return;
   const double alpha = st->alpha;
@@ -522,7 +544,7 @@ __global__ void __launch_bounds__(kVecBS) bicg_half_kernel(int n, double* x, con
 }
 
 // BiCGStab: x += alpha p_hat + omega s_hat; r = s - omega t; partials r.r, rt.r
-__global__ void __launch_bounds__(kVecBS) bicg_xr_kernel(int n, double* x, double* r,
+static __global__ void __launch_bounds__(kVecBS) bicg_xr_kernel(int n, double* x, double* r,
                                                          const double* phat, const double* shat,
                                                          const double* s, const double* t,
                                                          const double* rt, const KState* st,
@@ -542,21 +564,21 @@ __global__ void __launch_bounds__(kVecBS) bicg_xr_kernel(int n, double* x, doubl
 }
 
 template <class TD, class TS>
-__global__ void __launch_bounds__(kVecBS) copy_kernel(int n, TD* dst, const TS* src) {
+static __global__ void __launch_bounds__(kVecBS) copy_kernel(int n, TD* dst, const TS* src) {
   const int stride = gridDim.x * kVecBS;
   for (int i = blockIdx.x * kVecBS + threadIdx.x; i < n; i += stride)
     dst[i] = static_cast<TD>(src[i]);
 }
 
 template <class T>
-__global__ void __launch_bounds__(kVecBS) fill_kernel(int n, T* dst, T v) {
+static __global__ void __launch_bounds__(kVecBS) fill_kernel(int n, T* dst, T v) {
   const int stride = gridDim.x * kVecBS;
   for (int i = blockIdx.x * kVecBS + threadIdx.x; i < n; i += stride) dst[i] = v;
 }
 
 // z = m .* f   (first pre-sweep from zero, materialised when npre > 1)
 template <class T, class TF>
-__global__ void __launch_bounds__(kVecBS) scale_kernel(int n, T* z, const T* m, const TF* f,
+static __global__ void __launch_bounds__(kVecBS) scale_kernel(int n, T* z, const T* m, const TF* f,
                                                        const int* skip) {
   if (skip && *skip) return;
   const int stride = gridDim.x * kVecBS;
@@ -569,11 +591,8 @@ __global__ void __launch_bounds__(kVecBS) scale_kernel(int n, T* z, const T* m, 
 // z = Ainv f with the dense inverse of the coarsest operator (FP64, row-major),
 // one workgroup per row, FP64 accumulation; f and z in the V-cycle's types.
 template <class TF, class TZ>
-__global__ void __launch_bounds__(kBS) coarse_gemv_kernel(int n, const double* __restrict__ Ainv,
-                                                          const TF* __restrict__ f, TZ* __restrict__ z,
-                                                          const int* skip) {
-  if (skip && *skip) return;
-  const int row = blockIdx.x;
+__device__ __forceinline__ void coarse_row(int n, const double* __restrict__ Ainv, const TF* __restrict__ f,
+                                           TZ* __restrict__ z, int row) {
   const double* a = Ainv + static_cast<int64_t>(row) * n;
   double s0 = 0.0, s1 = 0.0;
   int j = threadIdx.x;
@@ -593,8 +612,16 @@ __global__ void __launch_bounds__(kBS) coarse_gemv_kernel(int n, const double* _
   }
 }
 
+template <class TF, class TZ>
+__global__ void __launch_bounds__(kBS) coarse_gemv_kernel(int n, const double* __restrict__ Ainv,
+                                                          const TF* __restrict__ f, TZ* __restrict__ z,
+                                                          const int* skip) {
+  if (skip && *skip) return;
+  coarse_row<TF, TZ>(n, Ainv, f, z, blockIdx.x);
+}
+
 // partials of a . b (FP64)
-__global__ void __launch_bounds__(kVecBS) dot_kernel(int n, const double* a, const double* b,
+static __global__ void __launch_bounds__(kVecBS) dot_kernel(int n, const double* a, const double* b,
                                                      double* partials, const int* skip) {
   if (skip && *skip) return;
   double d[1] = {0.0};
@@ -605,7 +632,7 @@ __global__ void __launch_bounds__(kVecBS) dot_kernel(int n, const double* a, con
 
 // zout = y (no post-sweep); optionally partials of f . zout
 template <class T, class TF, class TZ, int DOT>
-__global__ void __launch_bounds__(kVecBS) copy_dot_kernel(int n, TZ* zout, const T* y, const TF* f,
+static __global__ void __launch_bounds__(kVecBS) copy_dot_kernel(int n, TZ* zout, const T* y, const TF* f,
                                                           double* partials, const int* skip) {
   if (skip && *skip) return;
   double d[1] = {0.0};
@@ -616,6 +643,137 @@ __global__ void __launch_bounds__(kVecBS) copy_dot_kernel(int n, TZ* zout, const
     if constexpr (DOT) d[0] += static_cast<double>(f[i]) * static_cast<double>(o);
   }
   if constexpr (DOT) block_partials<1, kVecBS>(d, partials, gridDim.x, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// ---------------------------------------------------------------- batched kernels (serving)
+//
+// One launch runs the same step of many independent solves.  A batch lists,
+// per live solve, its operands and its number of work blocks; the fixed grid
+// strides over the concatenated blocks.  Each block does exactly what the
+// corresponding block of the single-solve kernel does (same rows, same
+// partial slot, same summation order), so every solve's result is bitwise the
+// same alone and in any mix.
+
+constexpr int kMaxSlots = 64;
+
+template <class Item>
+struct Batch {
+  int n;                     // live items
+  int total;                 // total work blocks
+  int off[kMaxSlots + 1];    // first work block of each item
+  Item it[kMaxSlots];
+};
+
+__device__ __forceinline__ int batch_item(const int* off, int n, int w) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class T, class Gth, class E>
+struct SpmvItem {
+  CsrView<T> A;
+  Gth g;
+  E e;
+  double* partials;
+  const int* skip;
+  int lanes;
+};
+
+template <class T, class Gth, class E>
+__global__ void __launch_bounds__(kBS) batched_spmv_kernel(const Batch<SpmvItem<T, Gth, E>>* B) {
+  __shared__ T prod[stream_nnz<T>() + kBS];
+  const int n = B->n, total = B->total;
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int i = batch_item(B->off, n, w);
+    const SpmvItem<T, Gth, E> it = B->it[i];
+    if (!*it.skip) {
+      const int vb = w - B->off[i], nb = B->off[i + 1] - B->off[i];
+      switch (it.lanes) {
+        case 1: stream_block<1>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 4: stream_block<4>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 16: stream_block<16>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        default: stream_block<64>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+struct UpdItem {
+  int n;
+  double* x;
+  double* r;
+  const double* p;
+  const double* q;
+  const KState* st;
+  double* partials;
+};
+
+static __global__ void __launch_bounds__(kVecBS) batched_update_kernel(const Batch<UpdItem>* B) {
+  const int n = B->n, total = B->total;
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int i = batch_item(B->off, n, w);
+    const UpdItem it = B->it[i];
+    if (it.st->done == kRunning)
+      pcg_update_block(it.n, it.x, it.r, it.p, it.q, it.st, it.partials, w - B->off[i], B->off[i + 1] - B->off[i]);
+    __syncthreads();
+  }
+}
+
+struct DirItem {
+  int n;
+  double* p;
+  const double* z;
+  const KState* st;
+};
+
+static __global__ void __launch_bounds__(kVecBS) batched_dir_kernel(const Batch<DirItem>* B) {
+  const int n = B->n, total = B->total;
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int i = batch_item(B->off, n, w);
+    const DirItem it = B->it[i];
+    if (it.st->done == kRunning) pcg_dir_block(it.n, it.p, it.z, it.st, w - B->off[i], B->off[i + 1] - B->off[i]);
+  }
+}
+
+struct FinItem {
+  const double* partials;
+  int nparts;
+  KState* st;
+};
+
+template <int K>
+__global__ void __launch_bounds__(kFinBS) batched_finalize_kernel(const Batch<FinItem>* B, int op) {
+  for (int w = blockIdx.x; w < B->n; w += gridDim.x) {
+    const FinItem it = B->it[w];
+    finalize_body<K>(it.partials, it.nparts, it.st, op);
+    __syncthreads();
+  }
+}
+
+template <class T>
+struct GemvItem {
+  int n;
+  const double* Ainv;
+  const T* f;
+  T* z;
+  const int* skip;
+};
+
+template <class T>
+__global__ void __launch_bounds__(kBS) batched_gemv_kernel(const Batch<GemvItem<T>>* B) {
+  const int n = B->n, total = B->total;
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int i = batch_item(B->off, n, w);
+    const GemvItem<T> it = B->it[i];
+    if (!*it.skip) coarse_row<T, T>(it.n, it.Ainv, it.f, it.z, w - B->off[i]);
+    __syncthreads();
+  }
 }
 
 }  // namespace amg

@@ -1,609 +1,6 @@
-// Solve phase on the device and the C ABI (include/amg.h).
-//
-// Section 2 ("AMG solve") and its closing remark: one V-cycle is one
-// preconditioning step of a Krylov method.  Section 3: the hierarchy is built
-// on the CPU, transferred to the backend once, and reused for every right-hand
-// side; smoothers and Krylov methods are expressed with the backend's
-// primitives (here: fused HIP kernels on gfx950).
-//
-// V-cycle, per level l < L (zero initial guess on every level; one pre- and
-// one post-sweep of the diagonal smoother m in the common configuration):
-//   r_l     = f_l - A_l (m .* f_l)      pre-sweep fused into the residual
-//   f_{l+1} = R_l r_l                   restriction
-//   ... coarser levels, then z_L = A_L^-1 f_L (dense inverse, FP64) ...
-//   y_l     = m .* f_l + P_l z_{l+1}    prolongation + correction, pre-sweep recomputed
-//   z_l     = y_l + m .* (f_l - A_l y_l)  post-sweep (level 1 of PCG also forms r . z)
-// The Krylov loop (PCG or BiCGStab) is FP64; its scalars (alpha, beta, omega,
-// convergence flag) live on the device, so one iteration is a fixed sequence of
-// kernels that is captured once into a hipGraph and replayed; the host polls
-// the flag every few iterations.  Kernels early-exit once the flag is set, so
-// replays past convergence are no-ops and the iteration count stays exact.
+// C ABI of the solver (include/amg.h): setup, solve, queries, measurement.
 
-#include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
-
-#include <chrono>
-#include <cmath>
-#include <memory>
-#include <string>
-#include <type_traits>
-#include <vector>
-
-#include "device.hpp"
-
-namespace amg {
-
-namespace {
-
-thread_local std::string g_last_error;
-
-amg_status set_error(int code, const std::string& msg) {
-  g_last_error = msg;
-  return static_cast<amg_status>(code);
-}
-
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-}  // namespace
-
-template <class T>
-struct DevLevel {
-  int32_t n = 0, nc = 0;
-  DevCsr<T> A, P, R;
-  T* m = nullptr;
-  T* f = nullptr;  // right-hand side (unused on level 0: the caller's vector)
-  T* r = nullptr;  // residual
-  T* y = nullptr;  // prolongated correction
-  T* t = nullptr;  // ping-pong buffer for repeated sweeps
-  T* zp[2] = {nullptr, nullptr};  // stored pre-smoothed iterate (npre > 1)
-  T* z = nullptr;   // output on levels > 0
-  T* mf = nullptr;  // m .* f, written by the restriction (levels > 0, npre = 1)
-};
-
-template <class T>
-struct DevHierarchy {
-  std::vector<DevLevel<T>> lev;  // levels 0 .. L-2
-  T* fL = nullptr;               // coarsest right-hand side / solution
-  T* zL = nullptr;
-};
-
-struct VcycleOpts {
-  int npre = 1, npost = 1;
-};
-
-// ------------------------------------------------------------------ V-cycle
-
-template <class T>
-class Vcycle {
- public:
-  Vcycle(DevHierarchy<T>* h, const double* Ainv, int32_t nL, VcycleOpts o)
-      : h_(h), Ainv_(Ainv), nL_(nL), o_(o) {}
-
-  // z0 = V(f0); f0, z0 double[n].  With DOT, writes the partials of f0 . z0
-  // and returns their count; otherwise returns 0.
-  template <int DOT>
-  int run(const double* f0, double* z0, double* partials, const int* skip, hipStream_t s) {
-    const int L = static_cast<int>(h_->lev.size()) + 1;
-    if (L == 1) {
-      coarse_gemv_kernel<double, double><<<nL_, kBS, 0, s>>>(nL_, Ainv_, f0, z0, skip);
-      AMG_LAUNCHED();
-      if (DOT) {
-        int nb = vec_blocks(nL_);
-        dot_kernel<<<nb, kVecBS, 0, s>>>(nL_, f0, z0, partials, skip);
-        AMG_LAUNCHED();
-        return nb;
-      }
-      return 0;
-    }
-    // down
-    for (int l = 0; l < L - 1; ++l) {
-      DevLevel<T>& lv = h_->lev[l];
-      DevLevel<T>* next = (l + 1 < L - 1) ? &h_->lev[l + 1] : nullptr;
-      if (l == 0) down<double>(lv, f0, next, skip, s);
-      else down<T>(lv, lv.f, next, skip, s);
-    }
-    coarse_gemv_kernel<T, T><<<nL_, kBS, 0, s>>>(nL_, Ainv_, h_->fL, h_->zL, skip);
-    AMG_LAUNCHED();
-    // up
-    int nparts = 0;
-    for (int l = L - 2; l >= 0; --l) {
-      DevLevel<T>& lv = h_->lev[l];
-      const T* zc = (l + 1 < L - 1) ? h_->lev[l + 1].z : h_->zL;
-      if (l == 0) nparts = up<double, double, DOT>(lv, f0, zc, z0, partials, skip, s);
-      else up<T, T, 0>(lv, lv.f, zc, lv.z, partials, skip, s);
-    }
-    return nparts;
-  }
-
- private:
-  // Pre-relaxation, residual and restriction of one level.  `next` is the
-  // next level (NULL when that is the coarsest).  On levels > 0 with one
-  // pre-sweep, m .* f was written by the restriction that produced f.
-  template <class TF>
-  void down(DevLevel<T>& lv, const TF* f, DevLevel<T>* next, const int* skip, hipStream_t s) {
-    T* fnext = next ? next->f : h_->fL;
-    auto restrict_from = [&](auto gather) {
-      if (next && o_.npre == 1)
-        launch_spmv(lv.R, gather, EpiRestrict<T>{next->f, next->mf, next->m}, nullptr, skip, s);
-      else
-        launch_spmv(lv.R, gather, EpiStore<T, T>{fnext}, nullptr, skip, s);
-    };
-    if (o_.npre == 0) {
-      restrict_from(GatherX<T, TF>{f});
-      return;
-    }
-    if (o_.npre == 1) {
-      if constexpr (std::is_same<TF, T>::value) {
-        if (lv.mf) {
-          launch_spmv(lv.A, GatherX<T, T>{lv.mf}, EpiResid<T, TF>{lv.r, f}, nullptr, skip, s);
-        } else {
-          launch_spmv(lv.A, GatherMF<T, TF>{lv.m, f}, EpiResid<T, TF>{lv.r, f}, nullptr, skip, s);
-        }
-      } else {
-        launch_spmv(lv.A, GatherMF<T, TF>{lv.m, f}, EpiResid<T, TF>{lv.r, f}, nullptr, skip, s);
-      }
-    } else {
-      scale_kernel<T, TF><<<vec_blocks(lv.n), kVecBS, 0, s>>>(lv.n, lv.zp[0], lv.m, f, skip);
-      AMG_LAUNCHED();
-      int cur = 0;
-      for (int k = 1; k < o_.npre; ++k) {
-        launch_spmv(lv.A, GatherX<T, T>{lv.zp[cur]}, EpiSmooth<T, TF, T, 0>{lv.zp[1 - cur], lv.zp[cur], lv.m, f},
-                    nullptr, skip, s);
-        cur = 1 - cur;
-      }
-      pre_cur_ = cur;
-      launch_spmv(lv.A, GatherX<T, T>{lv.zp[cur]}, EpiResid<T, TF>{lv.r, f}, nullptr, skip, s);
-    }
-    restrict_from(GatherX<T, T>{lv.r});
-  }
-
-  // Prolongation + correction and post-relaxation of one level; output zout.
-  template <class TF, class TZ, int DOT>
-  int up(DevLevel<T>& lv, const TF* f, const T* zc, TZ* zout, double* partials, const int* skip,
-         hipStream_t s) {
-    if (o_.npre == 0) {
-      launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 0>{lv.y, lv.m, f, nullptr}, nullptr, skip, s);
-    } else if (o_.npre == 1) {
-      if (lv.mf)
-        launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 2>{lv.y, lv.m, f, lv.mf}, nullptr, skip, s);
-      else
-        launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 1>{lv.y, lv.m, f, nullptr}, nullptr, skip, s);
-    } else {
-      launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 2>{lv.y, lv.m, f, lv.zp[pre_cur_]}, nullptr,
-                  skip, s);
-    }
-    if (o_.npost == 0) {
-      int nb = vec_blocks(lv.n);
-      copy_dot_kernel<T, TF, TZ, DOT><<<nb, kVecBS, 0, s>>>(lv.n, zout, lv.y, f, partials, skip);
-      AMG_LAUNCHED();
-      return DOT ? nb : 0;
-    }
-    T* cur = lv.y;
-    T* other = lv.t;
-    int nparts = 0;
-    for (int k = 0; k < o_.npost; ++k) {
-      const bool last = (k == o_.npost - 1);
-      if (last) {
-        nparts = launch_spmv(lv.A, GatherX<T, T>{cur}, EpiSmooth<T, TF, TZ, DOT>{zout, cur, lv.m, f}, partials,
-                             skip, s);
-      } else {
-        launch_spmv(lv.A, GatherX<T, T>{cur}, EpiSmooth<T, TF, T, 0>{other, cur, lv.m, f}, nullptr, skip, s);
-        std::swap(cur, other);
-      }
-    }
-    return DOT ? nparts : 0;
-  }
-
-  DevHierarchy<T>* h_;
-  const double* Ainv_;
-  int32_t nL_;
-  VcycleOpts o_;
-  int pre_cur_ = 0;
-};
-
-// ------------------------------------------------------------------ solver object
-
-}  // namespace amg
-
-struct amg_solver {
-  amg_params prm{};
-  amg::HostHierarchy host;
-  double setup_s = 0.0;
-  bool on_device = false;
-  int device = 0;
-
-  std::unique_ptr<amg::DevArena> arena;
-  hipStream_t cap_stream = nullptr;
-
-  amg::DevCsr<double> A0;  // FP64 fine operator for the Krylov loop
-  amg::DevHierarchy<double> h64;
-  amg::DevHierarchy<float> h32;
-  double* Ainv = nullptr;
-  int32_t nL = 0;
-  int64_t n = 0;
-
-  amg::KState* st = nullptr;
-  amg::KState* st_host = nullptr;  // pinned mirror for polling
-  double* partials = nullptr;
-  // Krylov vectors
-  double *f = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr;
-  double *rt = nullptr, *v = nullptr, *phat = nullptr, *s = nullptr, *shat = nullptr, *t = nullptr;
-
-  hipGraphExec_t iter_exec = nullptr;
-  hipGraph_t iter_graph = nullptr;
-
-  ~amg_solver() {
-    if (iter_exec) (void)hipGraphExecDestroy(iter_exec);
-    if (iter_graph) (void)hipGraphDestroy(iter_graph);
-    if (st_host) (void)hipHostFree(st_host);
-    arena.reset();
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
-  }
-};
-
-namespace amg {
-
-namespace {
-
-SetupParams setup_params(const amg_params& p) {
-  SetupParams s;
-  s.relax = p.relax;
-  s.eps_strong = p.eps_strong;
-  s.jacobi_omega = p.jacobi_omega;
-  s.coarse_enough = p.coarse_enough;
-  s.max_levels = p.max_levels;
-  return s;
-}
-
-void check_params(const amg_params& p) {
-  if (p.solver != AMG_CG && p.solver != AMG_BICGSTAB) throw SetupError{-1, "solver must be AMG_CG or AMG_BICGSTAB"};
-  if (p.relax != AMG_SPAI0 && p.relax != AMG_JACOBI) throw SetupError{-1, "relax must be AMG_SPAI0 or AMG_JACOBI"};
-  if (p.precision != AMG_FP64 && p.precision != AMG_MIXED) throw SetupError{-1, "precision must be AMG_FP64 or AMG_MIXED"};
-  if (p.npre < 0 || p.npost < 0 || p.npre > 16 || p.npost > 16) throw SetupError{-1, "npre/npost must be in [0, 16]"};
-  if (p.coarse_enough < 1 || p.max_levels < 1 || p.max_iter < 1) throw SetupError{-1, "coarse_enough, max_levels, max_iter must be >= 1"};
-  if (!(p.tol >= 0.0) || !(p.eps_strong >= 0.0)) throw SetupError{-1, "tol and eps_strong must be >= 0"};
-  if (p.check_every < 1 || p.check_every > 64) throw SetupError{-1, "check_every must be in [1, 64]"};
-}
-
-Csr to_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val) {
-  Csr A;
-  A.rows = A.cols = n;
-  A.ptr.assign(ptr, ptr + n + 1);
-  A.col.assign(col, col + ptr[n]);
-  A.val.assign(val, val + ptr[n]);
-  return A;
-}
-
-// Dense inverse of the coarsest operator on the device (LU with partial
-// pivoting, then inversion; FP64).  The row-major host matrix read as
-// column-major is A^T, and inv(A^T) read back as row-major is inv(A).
-void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream) {
-  const int32_t n = static_cast<int32_t>(AL.rows);
-  std::vector<double> dense(static_cast<size_t>(n) * n, 0.0);
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t e = AL.ptr[i]; e < AL.ptr[i + 1]; ++e) dense[static_cast<size_t>(i) * n + AL.col[e]] = AL.val[e];
-  S.Ainv = S.arena->upload(dense.data(), dense.size());
-  rocblas_int* ipiv = S.arena->get<rocblas_int>(n);
-  rocblas_int* dinfo = S.arena->get<rocblas_int>(1);
-  rocblas_handle hb;
-  if (rocblas_create_handle(&hb) != rocblas_status_success) throw DevError{-6, "rocblas_create_handle failed"};
-  rocblas_set_stream(hb, stream);
-  rocblas_int info = 0;
-  rocblas_status st1 = rocsolver_dgetrf(hb, n, n, S.Ainv, n, ipiv, dinfo);
-  hipError_t e1 = hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, stream);
-  hipError_t e2 = hipStreamSynchronize(stream);
-  if (st1 != rocblas_status_success || e1 != hipSuccess || e2 != hipSuccess) {
-    rocblas_destroy_handle(hb);
-    throw DevError{-6, "coarse LU factorisation failed"};
-  }
-  if (info != 0) {
-    rocblas_destroy_handle(hb);
-    throw DevError{-4, "zero pivot " + std::to_string(info) + " in the coarsest LU (n = " + std::to_string(n) + ")"};
-  }
-  rocblas_status st2 = rocsolver_dgetri(hb, n, S.Ainv, n, ipiv, dinfo);
-  e1 = hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, stream);
-  e2 = hipStreamSynchronize(stream);
-  rocblas_destroy_handle(hb);
-  if (st2 != rocblas_status_success || e1 != hipSuccess || e2 != hipSuccess || info != 0)
-    throw DevError{-4, "coarse inversion failed"};
-}
-
-template <class T>
-void upload_levels(amg_solver& S, DevHierarchy<T>& H) {
-  DevArena& ar = *S.arena;
-  const int L = static_cast<int>(S.host.levels.size());
-  const int npre = S.prm.npre;
-  for (int l = 0; l < L - 1; ++l) {
-    const HostLevel& hl = S.host.levels[l];
-    DevLevel<T> d;
-    d.n = static_cast<int32_t>(hl.A.rows);
-    d.nc = static_cast<int32_t>(hl.P.cols);
-    if constexpr (std::is_same<T, double>::value) {
-      d.A = (l == 0) ? S.A0 : upload_csr<T>(ar, hl.A);
-    } else {
-      d.A = upload_csr<T>(ar, hl.A);
-    }
-    d.P = upload_csr<T>(ar, hl.P);
-    d.R = upload_csr<T>(ar, hl.R);
-    std::vector<T> m(hl.m.begin(), hl.m.end());
-    d.m = ar.upload(m.data(), m.size());
-    AMG_HIP(hipStreamSynchronize(ar.stream()));
-    if (l > 0) {
-      d.f = ar.get<T>(d.n);
-      d.z = ar.get<T>(d.n);
-      if (npre == 1) d.mf = ar.get<T>(d.n);
-    }
-    d.r = ar.get<T>(d.n);
-    d.y = ar.get<T>(d.n);
-    d.t = ar.get<T>(d.n);
-    if (npre > 1) {
-      d.zp[0] = ar.get<T>(d.n);
-      d.zp[1] = ar.get<T>(d.n);
-    }
-    H.lev.push_back(d);
-  }
-  if (L > 1) {
-    H.fL = ar.get<T>(S.nL);
-    H.zL = ar.get<T>(S.nL);
-  }
-}
-
-int64_t max_parts(const amg_solver& S) {
-  int64_t m = vec_blocks(S.n);
-  m = std::max<int64_t>(m, S.A0.nblocks);
-  auto scan = [&](const auto& H) {
-    for (const auto& lv : H.lev) {
-      m = std::max<int64_t>(m, lv.A.nblocks);
-      m = std::max<int64_t>(m, vec_blocks(lv.n));
-    }
-  };
-  scan(S.h64);
-  scan(S.h32);
-  return m;
-}
-
-template <class F>
-auto with_vcycle(amg_solver& S, F fn) {
-  VcycleOpts o{S.prm.npre, S.prm.npost};
-  if (S.prm.precision == AMG_MIXED) {
-    Vcycle<float> V(&S.h32, S.Ainv, S.nL, o);
-    return fn(V);
-  }
-  Vcycle<double> V(&S.h64, S.Ainv, S.nL, o);
-  return fn(V);
-}
-
-// ------------------------------------------------------------------ Krylov
-
-void fin(amg_solver& S, int K, int nparts, int op, hipStream_t s) {
-  if (K == 1) finalize_kernel<1><<<1, kFinBS, 0, s>>>(S.partials, nparts, S.st, op);
-  else finalize_kernel<2><<<1, kFinBS, 0, s>>>(S.partials, nparts, S.st, op);
-  AMG_LAUNCHED();
-}
-
-const int* skip_of(amg_solver& S) { return &S.st->done; }
-
-// r = f - A x with (r.r, f.f) and the init scalar update.
-void enqueue_init(amg_solver& S, hipStream_t s) {
-  int nb = launch_spmv(S.A0, GatherX<double, double>{S.x}, EpiResidNorms{S.r, S.f}, S.partials, nullptr, s);
-  fin(S, 2, nb, kFinInit, s);
-}
-
-void enqueue_pcg_start(amg_solver& S, hipStream_t s) {
-  enqueue_init(S, s);
-  int nb = with_vcycle(S, [&](auto& V) { return V.template run<1>(S.r, S.z, S.partials, skip_of(S), s); });
-  fin(S, 1, nb, kFinPcgRho, s);
-  pcg_dir_kernel<<<vec_blocks(S.n), kVecBS, 0, s>>>(static_cast<int>(S.n), S.p, S.z, S.st);
-  AMG_LAUNCHED();
-}
-
-void enqueue_pcg_iteration(amg_solver& S, hipStream_t s) {
-  const int n = static_cast<int>(S.n);
-  const int vb = vec_blocks(n);
-  int nb = launch_spmv(S.A0, GatherX<double, double>{S.p}, EpiStoreDot{S.q, S.p}, S.partials, skip_of(S), s);
-  fin(S, 1, nb, kFinAlpha, s);
-  pcg_update_kernel<<<vb, kVecBS, 0, s>>>(n, S.x, S.r, S.p, S.q, S.st, S.partials);
-  AMG_LAUNCHED();
-  fin(S, 1, vb, kFinPcgRR, s);
-  nb = with_vcycle(S, [&](auto& V) { return V.template run<1>(S.r, S.z, S.partials, skip_of(S), s); });
-  fin(S, 1, nb, kFinPcgRho, s);
-  pcg_dir_kernel<<<vb, kVecBS, 0, s>>>(n, S.p, S.z, S.st);
-  AMG_LAUNCHED();
-}
-
-void enqueue_bicg_start(amg_solver& S, hipStream_t s) {
-  enqueue_init(S, s);
-  copy_kernel<double, double><<<vec_blocks(S.n), kVecBS, 0, s>>>(static_cast<int>(S.n), S.rt, S.r);
-  AMG_LAUNCHED();
-}
-
-void enqueue_bicg_iteration(amg_solver& S, hipStream_t s) {
-  const int n = static_cast<int>(S.n);
-  const int vb = vec_blocks(n);
-  bicg_p_kernel<<<vb, kVecBS, 0, s>>>(n, S.p, S.r, S.v, S.st);
-  AMG_LAUNCHED();
-  with_vcycle(S, [&](auto& V) { return V.template run<0>(S.p, S.phat, S.partials, skip_of(S), s); });
-  int nb = launch_spmv(S.A0, GatherX<double, double>{S.phat}, EpiStoreDot{S.v, S.rt}, S.partials, skip_of(S), s);
-  fin(S, 1, nb, kFinBiAlpha, s);
-  bicg_s_kernel<<<vb, kVecBS, 0, s>>>(n, S.s, S.r, S.v, S.st, S.partials);
-  AMG_LAUNCHED();
-  fin(S, 1, vb, kFinBiS, s);
-  bicg_half_kernel<<<vb, kVecBS, 0, s>>>(n, S.x, S.phat, S.st);
-  AMG_LAUNCHED();
-  fin(S, 1, 0, kFinBiHalfDone, s);
-  with_vcycle(S, [&](auto& V) { return V.template run<0>(S.s, S.shat, S.partials, skip_of(S), s); });
-  nb = launch_spmv(S.A0, GatherX<double, double>{S.shat}, EpiStoreDot2{S.t, S.s}, S.partials, skip_of(S), s);
-  fin(S, 2, nb, kFinBiOmega, s);
-  bicg_xr_kernel<<<vb, kVecBS, 0, s>>>(n, S.x, S.r, S.phat, S.shat, S.s, S.t, S.rt, S.st, S.partials);
-  AMG_LAUNCHED();
-  fin(S, 2, vb, kFinBiR, s);
-}
-
-void enqueue_iteration(amg_solver& S, hipStream_t s) {
-  if (S.prm.solver == AMG_CG) enqueue_pcg_iteration(S, s);
-  else enqueue_bicg_iteration(S, s);
-}
-
-void build_graph(amg_solver& S) {
-  if (S.iter_exec) return;
-  AMG_HIP(hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal));
-  try {
-    for (int it = 0; it < S.prm.check_every; ++it) enqueue_iteration(S, S.cap_stream);
-  } catch (...) {
-    hipGraph_t g;
-    (void)hipStreamEndCapture(S.cap_stream, &g);
-    if (g) (void)hipGraphDestroy(g);
-    throw;
-  }
-  AMG_HIP(hipStreamEndCapture(S.cap_stream, &S.iter_graph));
-  AMG_HIP(hipGraphInstantiate(&S.iter_exec, S.iter_graph, nullptr, nullptr, 0));
-}
-
-KState poll(amg_solver& S, hipStream_t s) {
-  AMG_HIP(hipMemcpyAsync(S.st_host, S.st, sizeof(KState), hipMemcpyDeviceToHost, s));
-  AMG_HIP(hipStreamSynchronize(s));
-  return *S.st_host;
-}
-
-amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, hipStream_t s, amg_info* info) {
-  const double t0 = now_s();
-  const int n = static_cast<int>(S.n);
-  const size_t bytes = sizeof(double) * S.n;
-  AMG_HIP(hipMemcpyAsync(S.f, f_dev, bytes, hipMemcpyDeviceToDevice, s));
-  AMG_HIP(hipMemcpyAsync(S.x, u_dev, bytes, hipMemcpyDeviceToDevice, s));
-  KState init{};
-  init.tol = S.prm.tol;
-  init.max_iter = S.prm.max_iter;
-  init.first = 1;
-  *S.st_host = init;
-  AMG_HIP(hipMemcpyAsync(S.st, S.st_host, sizeof(KState), hipMemcpyHostToDevice, s));
-  if (S.prm.use_graph) build_graph(S);
-
-  int restarts = 0;
-  KState k{};
-  for (;;) {
-    if (S.prm.solver == AMG_CG) enqueue_pcg_start(S, s);
-    else enqueue_bicg_start(S, s);
-    k = poll(S, s);
-    while (k.done == kRunning) {
-      if (S.prm.use_graph) {
-        AMG_HIP(hipGraphLaunch(S.iter_exec, s));  // check_every iterations
-      } else {
-        for (int it = 0; it < S.prm.check_every; ++it) enqueue_iteration(S, s);
-      }
-      k = poll(S, s);
-    }
-    if (k.done == kZeroRhs) break;
-    // true residual of the current iterate
-    int nb = launch_spmv(S.A0, GatherX<double, double>{S.x}, EpiResidNorms{S.tmp, S.f}, S.partials, nullptr, s);
-    fin(S, 2, nb, kFinTrue, s);
-    k = poll(S, s);
-    if (k.done == kConverged && k.true_rr > k.tol2 && restarts == 0) {
-      ++restarts;  // restart once from the current iterate; the count continues
-      continue;
-    }
-    break;
-  }
-  if (k.done == kZeroRhs) {
-    fill_kernel<double><<<vec_blocks(n), kVecBS, 0, s>>>(n, S.x, 0.0);
-    AMG_LAUNCHED();
-  }
-  AMG_HIP(hipMemcpyAsync(u_dev, S.x, bytes, hipMemcpyDeviceToDevice, s));
-  AMG_HIP(hipStreamSynchronize(s));
-
-  amg_status status = AMG_OK;
-  switch (k.done) {
-    case kConverged:
-      status = (k.true_rr <= k.tol2) ? AMG_OK : AMG_NOT_CONVERGED;
-      break;
-    case kZeroRhs: status = AMG_OK; break;
-    case kMaxIter: status = AMG_NOT_CONVERGED; break;
-    case kBreakdown: status = AMG_ERR_BREAKDOWN; break;
-    default: status = AMG_ERR_NAN; break;
-  }
-  if (info) {
-    info->iters = k.iters;
-    info->levels = static_cast<int32_t>(S.host.levels.size());
-    info->restarts = restarts;
-    info->status = status;
-    const bool zero = (k.done == kZeroRhs);
-    info->rel_resid = zero ? 0.0 : std::sqrt(k.rr / k.ff);
-    info->true_rel_resid = zero ? 0.0 : std::sqrt(k.true_rr / k.ff);
-    info->setup_s = S.setup_s;
-    info->solve_s = now_s() - t0;
-    double nnz = 0;
-    for (auto& lv : S.host.levels) nnz += double(lv.A.nnz());
-    info->op_complexity = nnz / double(S.host.levels[0].A.nnz());
-  }
-  if (status == AMG_NOT_CONVERGED) g_last_error = "iteration limit or tolerance not reached";
-  if (status == AMG_ERR_BREAKDOWN) g_last_error = "Krylov breakdown (zero inner product)";
-  if (status == AMG_ERR_NAN) g_last_error = "non-finite value in the iteration";
-  return status;
-}
-
-void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t s) {
-  AMG_HIP(hipGetDevice(&S.device));
-  S.arena = std::make_unique<DevArena>(alloc, s);
-  AMG_HIP(hipStreamCreateWithFlags(&S.cap_stream, hipStreamNonBlocking));
-  DevArena& ar = *S.arena;
-  const HostLevel& fine = S.host.levels[0];
-  S.n = fine.A.rows;
-  const Csr& AL = S.host.levels.back().A;
-  S.nL = static_cast<int32_t>(AL.rows);
-  S.A0 = upload_csr<double>(ar, fine.A);
-  if (S.prm.precision == AMG_MIXED) upload_levels<float>(S, S.h32);
-  else upload_levels<double>(S, S.h64);
-  coarse_inverse(S, AL, s);
-  S.st = ar.get<KState>(1);
-  AMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.st_host), sizeof(KState), hipHostMallocDefault));
-  S.partials = ar.get<double>(2 * max_parts(S));
-  const int64_t n = S.n;
-  S.f = ar.get<double>(n);
-  S.x = ar.get<double>(n);
-  S.r = ar.get<double>(n);
-  S.z = ar.get<double>(n);
-  S.p = ar.get<double>(n);
-  S.q = ar.get<double>(n);
-  S.tmp = ar.get<double>(n);
-  if (S.prm.solver == AMG_BICGSTAB) {
-    S.rt = ar.get<double>(n);
-    S.v = ar.get<double>(n);
-    S.phat = ar.get<double>(n);
-    S.s = ar.get<double>(n);
-    S.shat = ar.get<double>(n);
-    S.t = ar.get<double>(n);
-  }
-  AMG_HIP(hipStreamSynchronize(s));
-  S.on_device = true;
-}
-
-}  // namespace
-
-// --------------------------------------------------------------- C ABI helpers
-
-template <class F>
-amg_status guarded(F fn) {
-  try {
-    return fn();
-  } catch (const SetupError& e) {
-    return set_error(e.code, e.msg);
-  } catch (const DevError& e) {
-    return set_error(e.code, e.msg);
-  } catch (const std::bad_alloc&) {
-    return set_error(AMG_ERR_OOM, "host allocation failed");
-  } catch (const std::exception& e) {
-    return set_error(AMG_ERR_INVALID_ARG, e.what());
-  } catch (...) {
-    return set_error(AMG_ERR_INVALID_ARG, "unknown error");
-  }
-}
-
-}  // namespace amg
-
-// dot and copy helpers used by the V-cycle driver live with the kernels.
+#include "solver.hpp"
 
 using namespace amg;
 

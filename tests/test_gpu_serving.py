@@ -1,0 +1,105 @@
+"""Continuous-batching server (GPU).
+
+Every served result must be bitwise identical to the single-solve path
+(``amg_solve`` with the same parameters) and hence the same alone and in any
+mix; admission under a small HBM budget must still complete every request;
+a request that can never fit must fail cleanly.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import announce, true_rel_residual
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from paper_1811_05704_amd import amg  # noqa: E402
+
+import problems  # noqa: E402
+
+
+def request(n, seed):
+    g = problems.gaussian_field(n, 1.0, 8.0, seed)
+    A = problems.diffusion3d(n, g)
+    return A, problems.rhs_ones(A.n)
+
+
+def serve(reqs, budget=2 << 30, slots=8, threads=4, timeout=120, together=False):
+    """Serve the requests; with `together`, wait until all are set up so that
+    they are admitted in one step and run in one batch."""
+    srv = amg.Server(budget, max_slots=slots, setup_threads=threads)
+    for rid, A, f in reqs:
+        srv.submit(rid, A, f)
+    if together:
+        assert srv.wait_ready(len(reqs), timeout)
+    got = {}
+    t0 = time.time()
+    max_live = 0
+    while len(got) < len(reqs):
+        live, waiting = srv.step()
+        max_live = max(max_live, live)
+        for r in srv.results():
+            got[r[0]] = r
+        if live == 0:
+            time.sleep(0.002)
+        assert time.time() - t0 < timeout, "server did not finish"
+    srv.release()
+    return got, max_live
+
+
+def single(A, f):
+    S = amg.Solver(A, precision="mixed")
+    x, info = S.solve(torch.tensor(f, device="cuda"))
+    S.release()
+    return x.cpu().numpy(), info
+
+
+def test_served_results_equal_single_solves():
+    sizes = [16, 22, 18, 27, 20, 24, 17, 30]
+    reqs = [(i, *request(n, 10000 + i)) for i, n in enumerate(sizes)]
+    announce("serving", len(reqs), "requests")
+    got, max_live = serve(reqs, together=True)
+    assert max_live == len(reqs)  # all solves in one batch
+    for rid, A, f in reqs:
+        x_s, info_s = single(A, f)
+        _, x, info, status, times = got[rid]
+        assert status == 0, (rid, status)
+        assert info["iters"] == info_s["iters"]
+        assert np.array_equal(x, x_s), rid
+        assert true_rel_residual(A, x, f) <= 1e-8
+        submit, ready, admit, done = times
+        assert submit <= ready <= admit <= done
+
+
+def test_result_same_alone_and_in_mix():
+    A, f = request(21, 10100)
+    alone, _ = serve([(7, A, f)], slots=4)
+    others = [(i, *request(n, 10200 + i)) for i, n in enumerate([19, 25, 16, 23])]
+    mix, max_live = serve(others[:2] + [(7, A, f)] + others[2:], slots=8, together=True)
+    assert max_live == 5
+    assert np.array_equal(alone[7][1], mix[7][1])
+    assert alone[7][2]["iters"] == mix[7][2]["iters"]
+
+
+def test_admission_under_small_budget():
+    reqs = [(i, *request(20, 10300 + i)) for i in range(6)]
+    # a 20^3 request needs about 11 MiB of device memory: two fit at a time
+    budget = 26 << 20
+    announce("serving small budget")
+    got, max_live = serve(reqs, budget=budget, slots=8, threads=3)
+    assert 1 <= max_live < 6
+    for rid, A, f in reqs:
+        assert got[rid][3] == 0
+        assert true_rel_residual(A, got[rid][1], f) <= 1e-8
+
+
+def test_request_larger_than_budget_fails_cleanly():
+    small = request(16, 10400)   # about 4 MiB
+    big = request(28, 10401)     # about 63 MiB (dense coarse inverse of 2691 rows)
+    got, _ = serve([(1, *small), (2, *big)], budget=24 << 20, slots=2, threads=2)
+    assert got[1][3] == 0
+    assert got[2][3] == -5  # AMG_ERR_OOM: can never fit
