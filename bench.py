@@ -125,6 +125,149 @@ def pmc_probe(N, torch, amg, problems):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------------ serving
+
+
+def _gen_values(args):
+    """Worker: coefficient values of request i (structure is shared per n)."""
+    i, n, seed = args
+    import problems
+
+    g = problems.gaussian_field(n, 1.0, 8.0, seed)
+    return i, problems.diffusion3d(n, g).val
+
+
+def serving_schedule(count, seed_sizes=6, seed_gaps=5):
+    """Request sizes n_i ~ U{16..96}, field seeds 10000 + i, unit-rate exponential gaps."""
+    import numpy as np
+
+    sizes = np.random.default_rng(seed_sizes).integers(16, 97, size=count)
+    gaps = np.random.default_rng(seed_gaps).exponential(1.0, size=count)
+    return sizes, gaps
+
+
+def run_serving(args):
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import problems
+
+    count = args.serving_requests
+    sizes, gaps = serving_schedule(count)
+    log(f"serving: generating {count} requests (mean n^3 = {float(np.mean(sizes.astype(float) ** 3)):.0f})")
+    t = time.perf_counter()
+    structs = {}
+    for n in sorted(set(int(v) for v in sizes)):
+        P = problems.poisson3d(n)
+        structs[n] = (P.row_ptr, P.col)
+    vals = [None] * count
+    with mp.get_context("fork").Pool(processes=max(1, min(16, os.cpu_count() or 1))) as pool:
+        for i, v in pool.imap_unordered(_gen_values, [(i, int(sizes[i]), 10000 + i) for i in range(count)],
+                                        chunksize=2):
+            vals[i] = v
+    log(f"serving: generated in {time.perf_counter() - t:.1f} s")
+
+    import torch
+
+    from paper_1811_05704_amd import amg
+
+    torch.cuda.set_device(0)
+    free, _total = torch.cuda.mem_get_info()
+
+    class Req:
+        __slots__ = ("n", "row_ptr", "col", "val")
+
+    def req(i):
+        r = Req()
+        n = int(sizes[i])
+        r.n = n ** 3
+        r.row_ptr, r.col = structs[n]
+        r.val = vals[i]
+        return r
+
+    ones = {int(n): np.ones(int(n) ** 3) for n in set(sizes.tolist())}
+
+    def one_run(arrivals, budget, window=None, label=""):
+        """Serve all requests; arrivals = offsets in s (None: closed loop with `window` in flight)."""
+        srv = amg.Server(budget, max_slots=64, setup_threads=args.setup_threads, precision="mixed")
+        lat, iters, stat = [], [], []
+        t0 = time.perf_counter()
+        nxt = 0
+        inflight = 0
+        sub_time = {}
+        done = 0
+        max_live = 0
+        while done < count:
+            now = time.perf_counter() - t0
+            while nxt < count and ((arrivals is None and inflight < window) or
+                                   (arrivals is not None and arrivals[nxt] <= now)):
+                r = req(nxt)
+                srv.submit(nxt, r, ones[int(sizes[nxt])])
+                sub_time[nxt] = (arrivals[nxt] if arrivals is not None else now)
+                nxt += 1
+                inflight += 1
+            live, waiting = srv.step()
+            max_live = max(max_live, live)
+            for rid, x, info, status, times in srv.results():
+                tdone = time.perf_counter() - t0
+                lat.append(tdone - sub_time.pop(rid))
+                iters.append(info["iters"])
+                stat.append(status)
+                done += 1
+                inflight -= 1
+            if live == 0:
+                time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+        srv.release()
+        ok = sum(1 for s in stat if s == 0)
+        res = {
+            "solves_per_s": count / wall,
+            "wall_s": wall,
+            "latency_p50_s": pct(lat, 50),
+            "latency_p99_s": pct(lat, 99),
+            "latency_mean_s": float(np.mean(lat)),
+            "max_live": max_live,
+            "ok": ok,
+            "iters_mean": float(np.mean(iters)),
+            "iters_max": int(np.max(iters)),
+        }
+        log(f"serving {label}: {res['solves_per_s']:.1f} solves/s, p50 {res['latency_p50_s']:.3f} s, "
+            f"p99 {res['latency_p99_s']:.3f} s, max live {max_live}, ok {ok}/{count}")
+        return res
+
+    budget = int(0.8 * free)
+    sat = one_run(None, budget, window=args.serving_window, label="closed loop")
+    mu = sat["solves_per_s"]
+    rates = {}
+    for frac in (0.5, 0.9, 1.2):
+        lam = frac * mu
+        arrivals = np.cumsum(gaps) / lam
+        rates[f"{frac}mu"] = {"rate_per_s": lam, **one_run(arrivals, budget, label=f"{frac} mu")}
+    small = one_run(np.cumsum(gaps) / (0.9 * mu), 2 << 30, label="0.9 mu, 2 GiB budget")
+    line = {
+        "metric": "served solves/s and p50/p99 latency (arrival -> result on host), mixed AMG-PCG",
+        "value": rates["0.9mu"]["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32 V-cycle / f64 Krylov",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{count} diffusion systems n^3, n~U{{16..96}} (seed 6), k=exp(g), g Gaussian "
+                        "sigma 1 length 8 (seed 10000+i), f=1, tol 1e-8, setup + mixed AMG-PCG per request, "
+                        "Poisson arrivals (gaps seed 5)",
+            "budget_bytes": budget,
+            "setup_threads": args.setup_threads,
+            "max_slots": 64,
+        },
+        "closed_loop": sat,
+        "rates": rates,
+        "small_budget_0.9mu": small,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +277,11 @@ def main():
     ap.add_argument("--reps", type=int, default=50, help="launches per kernel / V-cycle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="serving benchmark: Poisson arrivals of diffusion systems, continuous batching")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-window", type=int, default=64, help="in-flight requests of the closed loop")
+    ap.add_argument("--setup-threads", type=int, default=12)
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch a 1 GiB copy and a few launches of each hot kernel (run under "
                          "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
@@ -142,6 +290,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is "
               "not part of this build", file=sys.stderr)
         sys.exit(2)
+
+    if args.serving:
+        run_serving(args)
+        return
 
     import numpy as np
     import torch

@@ -26,6 +26,7 @@ import math
 from dataclasses import dataclass
 
 import numpy as np
+from scipy import ndimage
 
 
 @dataclass
@@ -52,14 +53,8 @@ def poisson3d_nnz(N: int) -> int:
     return 7 * N**3 - 6 * N**2
 
 
-def _assemble7(N: int, diag: np.ndarray, lo: list, hi: list) -> CSR:
-    """Assemble a 7-point operator.
-
-    ``lo[d]`` holds, for every node, the matrix entry coupling it to its
-    neighbour at -e_d (d = 0: x, 1: y, 2: z); ``hi[d]`` the entry to +e_d.
-    Entries whose neighbour lies outside the grid are dropped.  Columns come
-    out sorted: -z, -y, -x, diag, +x, +y, +z.
-    """
+def _structure7(N: int):
+    """Row pointers, columns and the (n, 7) existence mask of the 7-point pattern."""
     n = N**3
     idx = np.arange(n, dtype=np.int64)
     i = idx % N
@@ -67,25 +62,46 @@ def _assemble7(N: int, diag: np.ndarray, lo: list, hi: list) -> CSR:
     k = idx // (N * N)
     strides = (1, N, N * N)
     coords = (i, j, k)
-    vals, cols, mask = [], [], []
+    cols, mask = [], []
     for d in (2, 1, 0):
-        vals.append(lo[d])
         cols.append(idx - strides[d])
         mask.append(coords[d] > 0)
-    vals.append(diag)
     cols.append(idx)
     mask.append(np.ones(n, dtype=bool))
     for d in (0, 1, 2):
-        vals.append(hi[d])
         cols.append(idx + strides[d])
         mask.append(coords[d] < N - 1)
-    V = np.stack(vals, axis=1)
-    C = np.stack(cols, axis=1)
     M = np.stack(mask, axis=1)
-    counts = M.sum(axis=1)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(counts, out=row_ptr[1:])
-    return CSR(n, row_ptr, C[M].astype(np.int32), V[M].astype(np.float64))
+    np.cumsum(M.sum(axis=1), out=row_ptr[1:])
+    col = np.stack(cols, axis=1)[M].astype(np.int32)
+    for a in (row_ptr, col, M):
+        a.flags.writeable = False
+    return row_ptr, col, M
+
+
+_STRUCT_CACHE: dict = {}
+
+
+def _assemble7(N: int, diag: np.ndarray, lo: list, hi: list) -> CSR:
+    """Assemble a 7-point operator.
+
+    ``lo[d]`` holds, for every node, the matrix entry coupling it to its
+    neighbour at -e_d (d = 0: x, 1: y, 2: z); ``hi[d]`` the entry to +e_d.
+    Entries whose neighbour lies outside the grid are dropped.  Columns come
+    out sorted: -z, -y, -x, diag, +x, +y, +z.  The (read-only) row pointers and
+    columns of grids up to 128^3 are shared between calls.
+    """
+    if N <= 128:
+        if N not in _STRUCT_CACHE:
+            if len(_STRUCT_CACHE) >= 16:
+                _STRUCT_CACHE.pop(next(iter(_STRUCT_CACHE)))
+            _STRUCT_CACHE[N] = _structure7(N)
+        row_ptr, col, M = _STRUCT_CACHE[N]
+    else:
+        row_ptr, col, M = _structure7(N)
+    V = np.stack([lo[2], lo[1], lo[0], diag, hi[0], hi[1], hi[2]], axis=1)
+    return CSR(N**3, row_ptr, col, V[M].astype(np.float64, copy=False))
 
 
 def poisson3d(N: int) -> CSR:
@@ -114,14 +130,11 @@ def gaussian_field(N: int, sigma: float, ell: float, seed: int) -> np.ndarray:
     M = N + 2 * r
     a = np.random.default_rng(seed).standard_normal((M, M, M))
     for axis in range(3):
-        shape = list(a.shape)
-        shape[axis] = N
-        out = np.zeros(shape)
-        for tap in range(2 * r + 1):
-            sl = [slice(None)] * 3
-            sl[axis] = slice(tap, tap + N)
-            out += w[tap] * a[tuple(sl)]
-        a = out
+        # centred correlation, then keep the "valid" part along this axis
+        a = ndimage.correlate1d(a, w, axis=axis, mode="constant")
+        sl = [slice(None)] * 3
+        sl[axis] = slice(r, r + N)
+        a = a[tuple(sl)]
     return (sigma * a).reshape(-1)
 
 
