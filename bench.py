@@ -36,6 +36,33 @@ WORKLOADS = {
 }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_poisson150.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1811_05704_amd", "csrc", f) for f in ("kernels.hpp", "device.hpp")]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec, kernel):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or None
+    when the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch", {}).get(f"{prec}:{kernel}")
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -67,6 +94,24 @@ def kernel_table(S, reps):
         us, by = S.time_kernel(k, reps=reps)
         out[k] = {"us": us, "bytes": by, "GBps": by / us / 1e3, "frac": by / us / 1e3 / HBM_PEAK_GBS}
     return out
+
+
+def copy_bandwidth(torch, gib=2, reps=20):
+    """Achievable HBM reference: device-to-device copy of `gib` GiB (read + write)."""
+    n = (gib << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(A, f, x_gpu_by_prec):
@@ -115,7 +160,7 @@ def pmc_probe(N, torch, amg, problems):
         dst.copy_(src)
     torch.cuda.synchronize()
     A = problems.poisson3d(N)
-    out = {"copy_bytes": src.numel() * 8}
+    out = {"copy_bytes": src.numel() * 8, "kernel_source_hash": kernel_source_hash()}
     for prec in ("fp64", "mixed"):
         S = amg.Solver(A, precision=prec)
         for k in S.KERNELS:
@@ -191,7 +236,7 @@ def run_serving(args):
     def one_run(arrivals, budget, window=None, label=""):
         """Serve all requests; arrivals = offsets in s (None: closed loop with `window` in flight)."""
         srv = amg.Server(budget, max_slots=64, setup_threads=args.setup_threads, precision="mixed")
-        lat, iters, stat = [], [], []
+        lat, iters, stat, setup_s, solve_s, queue_s = [], [], [], [], [], []
         t0 = time.perf_counter()
         nxt = 0
         inflight = 0
@@ -214,6 +259,9 @@ def run_serving(args):
                 lat.append(tdone - sub_time.pop(rid))
                 iters.append(info["iters"])
                 stat.append(status)
+                setup_s.append(info["setup_s"])
+                solve_s.append(info["solve_s"])
+                queue_s.append(times[2] - times[1])  # set up, waiting for a slot
                 done += 1
                 inflight -= 1
             if live == 0:
@@ -231,6 +279,9 @@ def run_serving(args):
             "ok": ok,
             "iters_mean": float(np.mean(iters)),
             "iters_max": int(np.max(iters)),
+            "setup_s_mean": float(np.mean(setup_s)),
+            "device_solve_s_mean": float(np.mean(solve_s)),
+            "slot_wait_s_mean": float(np.mean(queue_s)),
         }
         log(f"serving {label}: {res['solves_per_s']:.1f} solves/s, p50 {res['latency_p50_s']:.3f} s, "
             f"p99 {res['latency_p99_s']:.3f} s, max live {max_live}, ok {ok}/{count}")
@@ -342,6 +393,8 @@ def main():
         }
         S.release()
 
+    copy_gbps = copy_bandwidth(torch)
+    log(f"device copy reference: {copy_gbps:.0f} GB/s")
     base = results["fp64"]
     dom_name, dom = max(base["kernels"].items(), key=lambda kv: kv[1]["us"])
     line = {
@@ -371,10 +424,11 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": dom["frac"],
-            "traffic": None,
+            "traffic": measured_traffic("fp64", dom_name),
         },
         "vcycle_GBps": base["vcycle_GBps"],
         "vcycle_frac_of_peak": base["vcycle_frac_of_peak"],
+        "copy_GBps": copy_gbps,
         "fp64": base,
     }
     if "mixed" in results:

@@ -138,7 +138,7 @@ Schedule make_schedule(const Csr& M, int force_kind = -1) {
   const double mean = rows ? double(M.nnz()) / double(rows) : 0.0;
   s.kind = force_kind >= 0 ? force_kind : (mean <= kVectorMinMean ? 0 : 1);
   if (s.kind == 0) {
-    constexpr int64_t cap = stream_nnz<T>();
+    constexpr int64_t cap = stream_cap<T>();
     s.lanes = stream_lanes(mean);
     s.blk.push_back(0);
     int64_t r = 0;
@@ -175,14 +175,15 @@ DevCsr<T> upload_csr(DevArena& ar, const Csr& M, int force_kind = -1) {
   std::vector<int32_t> p32(M.ptr.begin(), M.ptr.end());
   if (p32.empty()) p32.assign(1, 0);
   d.ptr = ar.upload(p32.data(), p32.size());
-  d.col = ar.upload(M.col.data(), M.col.size());
-  if constexpr (std::is_same<T, double>::value) {
-    d.val = ar.upload(M.val.data(), M.val.size());
-  } else {
-    std::vector<T> v(M.val.size());
-    for (size_t k = 0; k < v.size(); ++k) v[k] = static_cast<T>(M.val[k]);  // round to nearest
-    d.val = ar.upload(v.data(), v.size());
-  }
+  // col and val carry 4 zero entries of padding: the stream kernel's aligned
+  // 4-entry loads may read up to 3 entries past the last one.
+  const size_t nz = M.col.size();
+  std::vector<int32_t> c(nz + 4, 0);
+  std::copy(M.col.begin(), M.col.end(), c.begin());
+  d.col = ar.upload(c.data(), c.size());
+  std::vector<T> v(nz + 4, T(0));
+  for (size_t k = 0; k < nz; ++k) v[k] = static_cast<T>(M.val[k]);  // FP32: round to nearest
+  d.val = ar.upload(v.data(), v.size());
   Schedule s = make_schedule<T>(M, force_kind);
   d.kind = s.kind;
   d.lanes = s.lanes;

@@ -220,11 +220,45 @@ struct EpiSmooth {
 
 // ---------------------------------------------------------------- SpMV kernels
 
-// Entries staged in LDS per stream block: 16 KB of products (2048 FP64 or
-// 4096 FP32 values, 8 or 16 per thread).
+// Entries staged in LDS per stream block: AMG_STREAM_BYTES of products
+// (16 KB: 2048 FP64 or 4096 FP32 values, 8 or 16 per thread).
+#ifndef AMG_STREAM_BYTES
+#define AMG_STREAM_BYTES 16384
+#endif
+// Entries per lane and load instruction in the stream kernel (1 or 4).
+#ifndef AMG_STREAM_VEC
+#define AMG_STREAM_VEC 1
+#endif
+constexpr int kStreamVec = AMG_STREAM_VEC;
+
 template <class T>
 constexpr int stream_nnz() {
-  return 16384 / static_cast<int>(sizeof(T));
+  return AMG_STREAM_BYTES / static_cast<int>(sizeof(T));
+}
+
+// Most entries a stream block may hold: with 4-entry loads the aligned load
+// window starts up to 3 entries before the block.
+template <class T>
+constexpr int stream_cap() {
+  return stream_nnz<T>() - (kStreamVec - 1);
+}
+
+// Loads of 4 consecutive entries (16-byte aligned indices).
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void load4(const int32_t* p, int (&c)[4]) {
+  const v4i_t v = __builtin_nontemporal_load(reinterpret_cast<const v4i_t*>(p));
+  c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double* p, double (&c)[4]) {
+  const v2d_t a = __builtin_nontemporal_load(reinterpret_cast<const v2d_t*>(p));
+  const v2d_t b = __builtin_nontemporal_load(reinterpret_cast<const v2d_t*>(p) + 1);
+  c[0] = a.x; c[1] = a.y; c[2] = b.x; c[3] = b.y;
+}
+__device__ __forceinline__ void load4(const float* p, float (&c)[4]) {
+  const v4f_t v = __builtin_nontemporal_load(reinterpret_cast<const v4f_t*>(p));
+  c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
 }
 constexpr int kStreamMaxRows = 1024;  // rows per stream block
 
@@ -246,26 +280,57 @@ __device__ __forceinline__ void stream_block(const CsrView<T>& A, const Gth& gat
   const int cnt = e1 - e0;
   const int tid = threadIdx.x;
   double d[E::K > 0 ? E::K : 1] = {};
-  if (cnt <= NNZ) {
+  if (cnt <= stream_cap<T>()) {
     if (cnt > 0) {
-      // All loads of a lane are issued before any is used, and nothing is
-      // predicated: surplus lanes re-read the block's last entry and park
-      // their product in the spare slots.
-      int c[PER];
-      T v[PER];
+      if constexpr (kStreamVec == 1) {
+        // All loads of a lane are issued before any is used, and nothing is
+        // predicated: surplus lanes re-read the block's last entry and park
+        // their product in the spare slots.
+        int c[PER];
+        T v[PER];
 #pragma unroll
-      for (int k = 0; k < PER; ++k) {
-        const int e = min(e0 + k * kBS + tid, e1 - 1);
-        c[k] = __builtin_nontemporal_load(A.col + e);
-        v[k] = __builtin_nontemporal_load(A.val + e);
-      }
-      T x[PER];
+        for (int k = 0; k < PER; ++k) {
+          const int e = min(e0 + k * kBS + tid, e1 - 1);
+          c[k] = __builtin_nontemporal_load(A.col + e);
+          v[k] = __builtin_nontemporal_load(A.val + e);
+        }
+        T x[PER];
 #pragma unroll
-      for (int k = 0; k < PER; ++k) x[k] = gather(c[k]);
+        for (int k = 0; k < PER; ++k) x[k] = gather(c[k]);
 #pragma unroll
-      for (int k = 0; k < PER; ++k) {
-        const int slot = k * kBS + tid;
-        prod[slot < cnt ? slot : NNZ + tid] = v[k] * x[k];
+        for (int k = 0; k < PER; ++k) {
+          const int slot = k * kBS + tid;
+          prod[slot < cnt ? slot : NNZ + tid] = v[k] * x[k];
+        }
+      } else {
+        // Each lane loads 4 consecutive entries with 16-byte loads from a
+        // window aligned down to a multiple of 4; arrays are padded so the
+        // last window stays inside the allocation.
+        constexpr int PV = PER / 4;
+        const int a0 = e0 & ~3;
+        const int last = (e1 - 1) & ~3;
+        int c[PV][4];
+        T v[PV][4];
+#pragma unroll
+        for (int k = 0; k < PV; ++k) {
+          const int b = min(a0 + (k * kBS + tid) * 4, last);
+          load4(A.col + b, c[k]);
+          load4(A.val + b, v[k]);
+        }
+        T x[PV][4];
+#pragma unroll
+        for (int k = 0; k < PV; ++k)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) x[k][q] = gather(c[k][q]);
+#pragma unroll
+        for (int k = 0; k < PV; ++k) {
+          const int b = a0 + (k * kBS + tid) * 4;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e = b + q;
+            prod[(e >= e0 && e < e1) ? e - e0 : NNZ + tid] = v[k][q] * x[k][q];
+          }
+        }
       }
     }
     __syncthreads();
