@@ -29,11 +29,24 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "solve s + V-cycle HBM GB/s, Poisson 150³ FP64 vs mixed; p50/p99 latency"
 
 WORKLOADS = {
-    # name: (grid N, rhs)
-    "poisson150": (150, "uniform"),
-    "poisson32": (32, "ones"),
-    "poisson200": (200, "uniform"),
+    # name: (grid N, rhs, matrix kind, solver, relax)
+    "poisson150": (150, "uniform", "poisson", "cg", "spai0"),
+    "poisson32": (32, "ones", "poisson", "cg", "spai0"),
+    "poisson200": (200, "uniform", "poisson", "cg", "spai0"),
+    "diffusion128": (128, "ones", "diffusion", "cg", "spai0"),
+    "diffusion128-bicgstab": (128, "ones", "diffusion", "bicgstab", "jacobi"),
+    "convection128-bicgstab": (128, "ones", "convection", "bicgstab", "jacobi"),
 }
+
+
+def workload_matrix(kind, N):
+    import problems
+
+    if kind == "poisson":
+        return problems.poisson3d(N)
+    g = problems.gaussian_field(N, 2.0, 8.0, 1)
+    vel = (50.0, 25.0, 12.5) if kind == "convection" else None
+    return problems.diffusion3d(N, g, velocity=vel)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_poisson150.json")
@@ -114,7 +127,7 @@ def copy_bandwidth(torch, gib=2, reps=20):
     return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(A, f, x_gpu_by_prec):
+def cpu_baseline(A, f, x_gpu_by_prec, solver="cg", relax="spai0"):
     """The oracle, single-threaded, on the host: one full FP64 solve at the
     benchmark size (the oracle hierarchy is built first and not timed)."""
     import numpy as np
@@ -124,11 +137,12 @@ def cpu_baseline(A, f, x_gpu_by_prec):
 
     with threadpool_limits(limits=1):
         t = time.perf_counter()
-        h = oracle.setup(A)
+        prm = oracle.Params(solver=solver, relax=relax)
+        h = oracle.setup(A, prm)
         t_setup = time.perf_counter() - t
         log(f"oracle setup {t_setup:.1f} s")
         t = time.perf_counter()
-        xo, io, _ = oracle.solve(A, f, h=h)
+        xo, io, _ = oracle.solve(A, f, prm, h=h)
         t_solve = time.perf_counter() - t
     errs = {p: float(np.linalg.norm(x - xo) / np.linalg.norm(xo)) for p, x in x_gpu_by_prec.items()}
     return {
@@ -352,11 +366,11 @@ def main():
     import problems
     from paper_1811_05704_amd import amg
 
-    N, rhs = WORKLOADS[args.workload]
+    N, rhs, kind, solver, relax = WORKLOADS[args.workload]
     if args.pmc_probe:
         pmc_probe(N, torch, amg, problems)
         return
-    A = problems.poisson3d(N)
+    A = workload_matrix(kind, N)
     f_host = problems.rhs_uniform(A.n, 0) if rhs == "uniform" else problems.rhs_ones(A.n)
     torch.cuda.set_device(0)
     f = torch.tensor(f_host, device="cuda")
@@ -367,7 +381,7 @@ def main():
     precs = ["fp64"] if args.no_mixed else ["fp64", "mixed"]
     for prec in precs:
         log(f"setup {prec}")
-        S = amg.Solver(A, precision=prec)
+        S = amg.Solver(A, precision=prec, solver=solver, relax=relax)
         levels = [S.level_info(l) for l in range(S.nlevels)]
         log(f"{prec}: levels {levels}")
         x, info, times, wall = run_solves(S, f, args.steps, args.warmup, torch)
@@ -411,9 +425,11 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"poisson3d {N}^3 (n={A.n}, nnz={A.nnz}), f={'U[0,1) seed 0' if rhs == 'uniform' else 'ones'}, "
-                        "AMG-PCG: smoothed aggregation eps 0.08, SPAI-0 1+1 sweeps, V-cycle, "
-                        "coarse <= 3000 dense, tol 1e-8",
+            "workload": f"{kind}3d {N}^3 (n={A.n}, nnz={A.nnz}), f={'U[0,1) seed 0' if rhs == 'uniform' else 'ones'}, "
+                        f"AMG-{'PCG' if solver == 'cg' else 'BiCGStab'}: smoothed aggregation eps 0.08, "
+                        f"{relax} 1+1 sweeps, V-cycle, coarse <= 3000 dense, tol 1e-8"
+                        + (", k=exp(g) sigma 2 length 8 seed 1" if kind != "poisson" else "")
+                        + (", upwind v=(1,0.5,0.25)*50" if kind == "convection" else ""),
             "n": A.n,
             "nnz": A.nnz,
         },
@@ -424,7 +440,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": dom["frac"],
-            "traffic": measured_traffic("fp64", dom_name),
+            "traffic": measured_traffic("fp64", dom_name) if args.workload == "poisson150" else None,
         },
         "vcycle_GBps": base["vcycle_GBps"],
         "vcycle_frac_of_peak": base["vcycle_frac_of_peak"],
@@ -435,7 +451,7 @@ def main():
         line["mixed"] = results["mixed"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cb, errs = cpu_baseline(A, f_host, xs)
+        cb, errs = cpu_baseline(A, f_host, xs, solver, relax)
         line["cpu_baseline"] = cb
         for p, e in errs.items():
             results[p]["err_vs_fp64_oracle"] = e

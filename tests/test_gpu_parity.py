@@ -258,3 +258,58 @@ def test_full_size_poisson150(precision):
     assert abs(info["iters"] - io.iters) <= 1
     assert true_rel_residual(A, x, f) <= 1e-8
     S.release()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("variant", ["sym-cg-spai0", "sym-bicgstab-jacobi", "nonsym-bicgstab-jacobi"])
+def test_full_size_diffusion128(variant):
+    """128^3 variable-coefficient diffusion, k = exp(g), sigma 2, length 8
+    (field seed 1), f = 1; the nonsymmetric form adds upwind convection
+    (1, 0.5, 0.25) * 50.  Iterations within +-1 of the oracle, true residual
+    <= 1e-8 recomputed on the CPU, one V-cycle within 1e-12 of the oracle."""
+    N = 128
+    g = problems.gaussian_field(N, 2.0, 8.0, 1)
+    vel = (50.0, 25.0, 12.5) if variant.startswith("nonsym") else None
+    A = problems.diffusion3d(N, g, velocity=vel)
+    f = problems.rhs_ones(A.n)
+    _, solver, relax = variant.split("-")
+    announce("full size diffusion 128^3", variant)
+    S = amg.Solver(A, solver=solver, relax=relax)
+    prm = oracle.Params(solver=solver, relax=relax)
+    h = oracle.setup(A, prm)
+    assert S.nlevels == h.nlevels
+    r = np.random.default_rng(13).standard_normal(A.n)
+    assert rel_err(host(S.vcycle(dev(r))), oracle.vcycle(h, r)) <= 1e-12
+    x, info = S.solve(dev(f))
+    x = host(x)
+    _, io, _ = oracle.solve(A, f, prm, h=h)
+    print(variant, "device iters", info["iters"], "oracle", io.iters, "solve_s", info["solve_s"])
+    assert info["status"] == 0
+    assert abs(info["iters"] - io.iters) <= 1
+    assert true_rel_residual(A, x, f) <= 1e-8
+    S.release()
+
+
+@pytest.mark.timeout(900)
+def test_full_size_poisson200_mixed_and_fp64():
+    """200^3 Poisson, f = U[0,1) seed 0: the mixed-precision solve (FP32
+    V-cycle, FP64 Krylov and coarse solve) and the plain FP64 solve both reach
+    a true FP64 relative residual <= 1e-8; iterations within +-1 of the oracle
+    (FP64 and FP32-V-cycle oracles)."""
+    A = problems.poisson3d(200)
+    f = problems.rhs_uniform(A.n, 0)
+    h = oracle.setup(A)
+    out = {}
+    for precision in ("fp64", "mixed"):
+        announce("full size 200^3", precision)
+        S = amg.Solver(A, precision=precision)
+        x, info = S.solve(dev(f))
+        x = host(x)
+        _, io, _ = oracle.solve(A, f, mixed=(precision == "mixed"), h=h)
+        print(precision, "device iters", info["iters"], "oracle", io.iters, "solve_s", info["solve_s"])
+        assert abs(info["iters"] - io.iters) <= 1
+        assert true_rel_residual(A, x, f) <= 1e-8
+        out[precision] = x
+        S.release()
+    # both are solutions to 1e-8: they agree far below the discretisation scale
+    assert rel_err(out["mixed"], out["fp64"]) <= 1e-6
