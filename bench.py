@@ -251,6 +251,7 @@ def run_serving(args):
         """Serve all requests; arrivals = offsets in s (None: closed loop with `window` in flight)."""
         srv = amg.Server(budget, max_slots=64, setup_threads=args.setup_threads, precision="mixed")
         lat, iters, stat, setup_s, solve_s, queue_s = [], [], [], [], [], []
+        failed = []
         t0 = time.perf_counter()
         nxt = 0
         inflight = 0
@@ -273,6 +274,9 @@ def run_serving(args):
                 lat.append(tdone - sub_time.pop(rid))
                 iters.append(info["iters"])
                 stat.append(status)
+                if status != 0:
+                    failed.append({"id": int(rid), "n": int(sizes[rid]), "status": int(status), "iters": info["iters"],
+                                   "true_rel_resid": info["true_rel_resid"]})
                 setup_s.append(info["setup_s"])
                 solve_s.append(info["solve_s"])
                 queue_s.append(times[2] - times[1])  # set up, waiting for a slot
@@ -296,13 +300,19 @@ def run_serving(args):
             "setup_s_mean": float(np.mean(setup_s)),
             "device_solve_s_mean": float(np.mean(solve_s)),
             "slot_wait_s_mean": float(np.mean(queue_s)),
+            "failed": failed[:32],
         }
         log(f"serving {label}: {res['solves_per_s']:.1f} solves/s, p50 {res['latency_p50_s']:.3f} s, "
             f"p99 {res['latency_p99_s']:.3f} s, max live {max_live}, ok {ok}/{count}")
+        if failed:
+            log(f"  not ok: {failed[:8]}")
         return res
 
     budget = int(0.8 * free)
     sat = one_run(None, budget, window=args.serving_window, label="closed loop")
+    if args.serving_closed_only:
+        print(json.dumps({"closed_loop": sat}), flush=True)
+        return
     mu = sat["solves_per_s"]
     rates = {}
     for frac in (0.5, 0.9, 1.2):
@@ -347,6 +357,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-window", type=int, default=64, help="in-flight requests of the closed loop")
     ap.add_argument("--setup-threads", type=int, default=12)
+    ap.add_argument("--serving-closed-only", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch a 1 GiB copy and a few launches of each hot kernel (run under "
                          "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")

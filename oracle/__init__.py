@@ -19,6 +19,8 @@ from .sa_amg import (  # noqa: F401
     smoothed_prolongator,
     spai0_diagonal,
     jacobi_diagonal,
+    chebyshev_upper_bound,
+    chebyshev_sweep,
     setup,
     vcycle,
     vcycle_fp32,

@@ -22,8 +22,11 @@ Where it comes from
   :func:`prolongator_damping`, :func:`smoothed_prolongator`
 * Section 3, "Relaxation methods": damped Jacobi and the sparse approximate
   inverse SPAI-0 (Broeker and Grote, 2002: the diagonal M minimising
-  ||I - M A||_F row by row).                -> :func:`spai0_diagonal`,
-  :func:`jacobi_diagonal`
+  ||I - M A||_F row by row); Chebyshev relaxation as the diagonally scaled
+  Chebyshev iteration of Saad 2003 (cited by the paper for its relaxation
+  methods) on [hi/30, hi], hi the Gershgorin bound of D^-1 A.
+                                            -> :func:`spai0_diagonal`,
+  :func:`jacobi_diagonal`, :func:`chebyshev_sweep`
 * Section 2, algorithm "AMG solve": one V-cycle -- pre-relaxation, residual,
   restriction on the way down; a direct solve on the coarsest level;
   prolongation with correction and post-relaxation on the way up.
@@ -67,9 +70,11 @@ class Params:
     """Method parameters (the paper's nested ``params``, section 3.1, flattened)."""
 
     solver: str = "cg"  # "cg" | "bicgstab"
-    relax: str = "spai0"  # "spai0" | "jacobi"
+    relax: str = "spai0"  # "spai0" | "jacobi" | "chebyshev"
     eps_strong: float = 0.08  # strength threshold on level 1, halved per level
     jacobi_omega: float = 0.72
+    cheb_degree: int = 3  # Chebyshev steps per sweep
+    cheb_ratio: float = 30.0  # lower end of the Chebyshev interval = upper / ratio
     npre: int = 1
     npost: int = 1
     coarse_enough: int = 3000
@@ -85,8 +90,9 @@ class Level:
     agg: np.ndarray | None = None  # aggregate id per node, -1 = isolated
     P: sp.csr_matrix | None = None
     R: sp.csr_matrix | None = None
-    m: np.ndarray | None = None  # smoother diagonal
+    m: np.ndarray | None = None  # smoother diagonal (Chebyshev: 1 / a_ii)
     omega: float | None = None  # prolongator damping
+    cheb_hi: float | None = None  # Chebyshev: upper end of the spectrum bound of D^-1 A
 
 
 @dataclass
@@ -260,6 +266,61 @@ def jacobi_diagonal(A: sp.csr_matrix, omega: float) -> np.ndarray:
     return omega / _as_csr(A).diagonal()
 
 
+def chebyshev_upper_bound(A: sp.csr_matrix) -> float:
+    """Gershgorin bound of the spectrum of D^-1 A: max_i sum_j |a_ij| / |a_ii|."""
+    A = _as_csr(A)
+    absrow = abs(A) @ np.ones(A.shape[0])
+    return float(np.max(absrow / np.abs(A.diagonal())))
+
+
+def chebyshev_sweep(A, dinv, f, x, hi, lo, degree):
+    """Diagonally scaled Chebyshev iteration (Saad 2003, Alg. 12.1, with the
+    preconditioner D) of `degree` steps for A x = f from the guess x, for a
+    spectrum of D^-1 A inside [lo, hi].  Returns (x, r) with r = f - A x.
+
+    theta = (hi + lo) / 2, delta = (hi - lo) / 2, sigma = theta / delta;
+    r = f - A x, rho = 1 / sigma, d = D^-1 r / theta; then repeatedly
+    x += d, r -= A d, rho' = 1 / (2 sigma - rho),
+    d = rho' rho d + (2 rho' / delta) D^-1 r.
+    """
+    theta = 0.5 * (hi + lo)
+    delta = 0.5 * (hi - lo)
+    sigma = theta / delta
+    r = f - A @ x
+    rho = 1.0 / sigma
+    d = dinv * r / theta
+    for step in range(degree):
+        x = x + d
+        r = r - A @ d
+        if step == degree - 1:
+            break
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * (dinv * r)
+        rho = rho_new
+    return x, r
+
+
+def chebyshev_sweep_fp32(A32, dinv32, f32, x32, hi, lo, degree):
+    """:func:`chebyshev_sweep` in FP32 arithmetic (coefficients rounded to FP32)."""
+    f32_ = np.float32
+    theta = 0.5 * (hi + lo)
+    delta = 0.5 * (hi - lo)
+    sigma = theta / delta
+    r = f32 - A32 @ x32
+    rho = 1.0 / sigma
+    d = dinv32 * r * f32_(1.0 / theta)
+    x = x32
+    for step in range(degree):
+        x = x + d
+        r = r - A32 @ d
+        if step == degree - 1:
+            break
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = f32_(rho_new * rho) * d + f32_(2.0 * rho_new / delta) * (dinv32 * r)
+        rho = rho_new
+    return x
+
+
 def setup(A, params: Params | None = None) -> Hierarchy:
     """Build the hierarchy (section 2, "AMG setup"), FP64."""
     prm = params or Params()
@@ -283,13 +344,17 @@ def setup(A, params: Params | None = None) -> Hierarchy:
         P = smoothed_prolongator(A_F, d_F, tentative_prolongator(agg), omega)
         R = P.T.tocsr()
         R.sort_indices()
+        cheb_hi = None
         if prm.relax == "spai0":
             m = spai0_diagonal(A)
         elif prm.relax == "jacobi":
             m = jacobi_diagonal(A, prm.jacobi_omega)
+        elif prm.relax == "chebyshev":
+            m = 1.0 / A.diagonal()
+            cheb_hi = chebyshev_upper_bound(A)
         else:
             raise ValueError(prm.relax)
-        levels.append(Level(A=A, agg=agg, P=P, R=R, m=m, omega=omega))
+        levels.append(Level(A=A, agg=agg, P=P, R=R, m=m, omega=omega, cheb_hi=cheb_hi))
         stats["omega"].append(omega)
         stats["eps"].append(eps)
         Ac = (R @ (A @ P)).tocsr()
@@ -314,6 +379,15 @@ def vcycle(h: Hierarchy, f: np.ndarray, level: int = 0) -> np.ndarray:
         return sla.lu_solve(h.lu, f)
     prm = h.params
     z = np.zeros_like(f)
+    if prm.relax == "chebyshev":
+        lo = lv.cheb_hi / prm.cheb_ratio
+        for _ in range(prm.npre):
+            z, _r = chebyshev_sweep(lv.A, lv.m, f, z, lv.cheb_hi, lo, prm.cheb_degree)
+        r = f - lv.A @ z
+        z = z + lv.P @ vcycle(h, lv.R @ r, level + 1)
+        for _ in range(prm.npost):
+            z, _r = chebyshev_sweep(lv.A, lv.m, f, z, lv.cheb_hi, lo, prm.cheb_degree)
+        return z
     for _ in range(prm.npre):
         z = z + lv.m * (f - lv.A @ z)
     r = f - lv.A @ z
@@ -330,7 +404,7 @@ def hierarchy_fp32(h: Hierarchy) -> list:
     out = []
     for lv in h.levels[:-1]:
         out.append(dict(A=lv.A.astype(np.float32), P=lv.P.astype(np.float32),
-                        R=lv.R.astype(np.float32), m=lv.m.astype(np.float32)))
+                        R=lv.R.astype(np.float32), m=lv.m.astype(np.float32), cheb_hi=lv.cheb_hi))
     return out
 
 
@@ -350,6 +424,16 @@ def vcycle_fp32(h: Hierarchy, f: np.ndarray, h32: list | None = None) -> np.ndar
             return sla.lu_solve(h.lu, f32.astype(np.float64)).astype(np.float32)
         lv = h32[level]
         z = np.zeros_like(f32)
+        if prm.relax == "chebyshev":
+            hi = lv["cheb_hi"]
+            lo = hi / prm.cheb_ratio
+            for _ in range(prm.npre):
+                z = chebyshev_sweep_fp32(lv["A"], lv["m"], f32, z, hi, lo, prm.cheb_degree)
+            r = f32 - lv["A"] @ z
+            z = z + lv["P"] @ cycle(level + 1, lv["R"] @ r)
+            for _ in range(prm.npost):
+                z = chebyshev_sweep_fp32(lv["A"], lv["m"], f32, z, hi, lo, prm.cheb_degree)
+            return z
         for _ in range(prm.npre):
             z = z + lv["m"] * (f32 - lv["A"] @ z)
         r = f32 - lv["A"] @ z

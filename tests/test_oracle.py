@@ -366,3 +366,57 @@ def test_coarse_lu_solves_coarsest_system():
     b = np.random.default_rng(3).standard_normal(Ac.shape[0])
     z = oracle.vcycle(h, b, h.nlevels - 1)
     assert np.linalg.norm(Ac @ z - b) / np.linalg.norm(b) < 1e-13
+
+
+# ---------------------------------------------------------------- Chebyshev smoother
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
+def test_chebyshev_residual_polynomial_closed_form(degree):
+    # 1-D Laplacian, D = 2I: D^-1 A has eigenvalues mu_j = 1 - cos(j pi/(n+1)) with
+    # eigenvectors sin(i j pi/(n+1)).  One sweep from zero multiplies the residual of
+    # an eigenvector by T_k((theta - mu)/delta) / T_k(theta/delta).
+    from numpy.polynomial import chebyshev as C
+
+    n = 30
+    A = problems.tridiag1d(n).to_scipy()
+    hi = oracle.chebyshev_upper_bound(A)
+    assert hi == 2.0  # interior rows (1 + 2 + 1) / 2
+    lo = hi / 30.0
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    Tk = np.zeros(degree + 1)
+    Tk[-1] = 1.0
+    dinv = 1.0 / A.diagonal()
+    idx = np.arange(1, n + 1)
+    for j in (1, 3, 7, 15, 29):
+        v = np.sin(idx * j * np.pi / (n + 1))
+        mu = 1.0 - np.cos(j * np.pi / (n + 1))
+        x, r = oracle.chebyshev_sweep(A, dinv, v, np.zeros(n), hi, lo, degree)
+        expect = C.chebval((theta - mu) / delta, Tk) / C.chebval(theta / delta, Tk)
+        assert np.max(np.abs(r - expect * v)) <= 1e-13
+        assert np.max(np.abs((v - A @ x) - r)) <= 1e-13
+
+
+def test_chebyshev_vcycle_symmetric_spd_linear_and_solve():
+    N = 7
+    A = problems.poisson3d(N).to_scipy()
+    prm = oracle.Params(coarse_enough=10, relax="chebyshev")
+    h = oracle.setup(A, prm)
+    assert h.nlevels >= 3
+    B = _vcycle_matrix(h, A.shape[0])
+    assert np.max(np.abs(B - B.T)) <= 1e-13 * np.max(np.abs(B))
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+    rng = np.random.default_rng(5)
+    x, y = rng.standard_normal((2, A.shape[0]))
+    lhs = oracle.vcycle(h, 1.5 * x - 2.0 * y)
+    rhs = 1.5 * oracle.vcycle(h, x) - 2.0 * oracle.vcycle(h, y)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-14 * np.max(np.abs(rhs))
+    A8 = problems.poisson3d(8)
+    f = problems.rhs_uniform(A8.n, 1)
+    xs, info, _ = oracle.solve(A8, f, oracle.Params(relax="chebyshev", coarse_enough=20))
+    xd = np.linalg.solve(A8.to_scipy().toarray(), f)
+    assert info.converged and np.linalg.norm(xs - xd) / np.linalg.norm(xd) <= 1e-6
+    # the FP32 V-cycle follows the same polynomial
+    z64 = oracle.vcycle(h, x)
+    z32 = oracle.vcycle_fp32(h, x)
+    assert 1e-10 < np.linalg.norm(z32 - z64) / np.linalg.norm(z64) < 1e-5

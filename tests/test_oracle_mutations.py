@@ -28,6 +28,7 @@ def _pins_fail(golden):
         lambda: pins.test_filtered_matrix_lumps_weak_entries(),
         lambda: pins.test_whole_solve_vs_dense(*pins._tiny_cases()[-1]),
         lambda: pins.test_vcycle_operator_symmetric_spd_linear("spai0"),
+        lambda: pins.test_chebyshev_residual_polynomial_closed_form(3),
     ]
     for chk in checks:
         try:
@@ -105,6 +106,23 @@ def _vcycle_restrict_tentative(h, f, level=0):
     return z + lv.m * (f - lv.A @ z)
 
 
+def _chebyshev_wrong_recurrence(A, dinv, f, x, hi, lo, degree):
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    sigma = theta / delta
+    r = f - A @ x
+    rho = 1.0 / sigma
+    d = dinv * r / theta
+    for step in range(degree):
+        x = x + d
+        r = r - A @ d
+        if step == degree - 1:
+            break
+        rho_new = 1.0 / (2.0 * sigma + rho)  # wrong sign
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * (dinv * r)
+        rho = rho_new
+    return x, r
+
+
 _orig = {"filtered_matrix": sa.filtered_matrix, "prolongator_damping": sa.prolongator_damping}
 
 
@@ -116,6 +134,7 @@ MUTATIONS = {
     "filter_drops_weak": ("filtered_matrix", _filter_drops_weak),
     "post_sweep_sign": ("vcycle", _vcycle_wrong_sign),
     "restriction_tentative": ("vcycle", _vcycle_restrict_tentative),
+    "chebyshev_recurrence_sign": ("chebyshev_sweep", _chebyshev_wrong_recurrence),
 }
 
 
