@@ -288,7 +288,7 @@ def chebyshev_sweep(A, dinv, f, x, hi, lo, degree):
     sigma = theta / delta
     r = f - A @ x
     rho = 1.0 / sigma
-    d = dinv * r / theta
+    d = (dinv * r) / theta
     for step in range(degree):
         x = x + d
         r = r - A @ d
@@ -308,7 +308,7 @@ def chebyshev_sweep_fp32(A32, dinv32, f32, x32, hi, lo, degree):
     sigma = theta / delta
     r = f32 - A32 @ x32
     rho = 1.0 / sigma
-    d = dinv32 * r * f32_(1.0 / theta)
+    d = (dinv32 * r) / f32_(theta)
     x = x32
     for step in range(degree):
         x = x + d
@@ -318,7 +318,7 @@ def chebyshev_sweep_fp32(A32, dinv32, f32, x32, hi, lo, degree):
         rho_new = 1.0 / (2.0 * sigma - rho)
         d = f32_(rho_new * rho) * d + f32_(2.0 * rho_new / delta) * (dinv32 * r)
         rho = rho_new
-    return x
+    return x, r
 
 
 def setup(A, params: Params | None = None) -> Hierarchy:
@@ -380,10 +380,11 @@ def vcycle(h: Hierarchy, f: np.ndarray, level: int = 0) -> np.ndarray:
     prm = h.params
     z = np.zeros_like(f)
     if prm.relax == "chebyshev":
+        # the residual restricted is the one the Chebyshev iteration carries
         lo = lv.cheb_hi / prm.cheb_ratio
+        r = f
         for _ in range(prm.npre):
-            z, _r = chebyshev_sweep(lv.A, lv.m, f, z, lv.cheb_hi, lo, prm.cheb_degree)
-        r = f - lv.A @ z
+            z, r = chebyshev_sweep(lv.A, lv.m, f, z, lv.cheb_hi, lo, prm.cheb_degree)
         z = z + lv.P @ vcycle(h, lv.R @ r, level + 1)
         for _ in range(prm.npost):
             z, _r = chebyshev_sweep(lv.A, lv.m, f, z, lv.cheb_hi, lo, prm.cheb_degree)
@@ -427,12 +428,12 @@ def vcycle_fp32(h: Hierarchy, f: np.ndarray, h32: list | None = None) -> np.ndar
         if prm.relax == "chebyshev":
             hi = lv["cheb_hi"]
             lo = hi / prm.cheb_ratio
+            r = f32
             for _ in range(prm.npre):
-                z = chebyshev_sweep_fp32(lv["A"], lv["m"], f32, z, hi, lo, prm.cheb_degree)
-            r = f32 - lv["A"] @ z
+                z, r = chebyshev_sweep_fp32(lv["A"], lv["m"], f32, z, hi, lo, prm.cheb_degree)
             z = z + lv["P"] @ cycle(level + 1, lv["R"] @ r)
             for _ in range(prm.npost):
-                z = chebyshev_sweep_fp32(lv["A"], lv["m"], f32, z, hi, lo, prm.cheb_degree)
+                z, _r = chebyshev_sweep_fp32(lv["A"], lv["m"], f32, z, hi, lo, prm.cheb_degree)
             return z
         for _ in range(prm.npre):
             z = z + lv["m"] * (f32 - lv["A"] @ z)
