@@ -46,7 +46,7 @@ typedef enum {
 } amg_status;
 
 enum { AMG_CG = 0, AMG_BICGSTAB = 1 };         /* Krylov method (section 3) */
-enum { AMG_SPAI0 = 0, AMG_JACOBI = 1 };        /* relaxation (section 3)    */
+enum { AMG_SPAI0 = 0, AMG_JACOBI = 1, AMG_CHEBYSHEV = 2 }; /* relaxation (section 3) */
 enum { AMG_FP64 = 0, AMG_MIXED = 1 };          /* value type of the V-cycle */
 
 /*
@@ -56,11 +56,14 @@ enum { AMG_FP64 = 0, AMG_MIXED = 1 };          /* value type of the V-cycle */
  * amg_params_default() fills: CG, SPAI-0, FP64, eps_strong 0.08 (halved on
  * every coarser level), jacobi_omega 0.72, npre = npost = 1, coarse_enough
  * 3000, max_levels 30, max_iter 500, tol 1e-8 (relative to ||f||_2),
- * use_graph 1, check_every 4.
+ * use_graph 1, check_every 4, cheb_degree 3, cheb_ratio 30.
+ * AMG_CHEBYSHEV is the diagonally scaled Chebyshev iteration (Saad 2003,
+ * cited in section 3) of cheb_degree steps per sweep on [hi/cheb_ratio, hi],
+ * hi the Gershgorin bound of D^-1 A_l; it needs npre, npost >= 1.
  */
 typedef struct {
   int32_t solver;        /* AMG_CG | AMG_BICGSTAB                               */
-  int32_t relax;         /* AMG_SPAI0 | AMG_JACOBI                              */
+  int32_t relax;         /* AMG_SPAI0 | AMG_JACOBI | AMG_CHEBYSHEV              */
   int32_t precision;     /* AMG_FP64 | AMG_MIXED (FP32 V-cycle, FP64 Krylov)    */
   int32_t npre;          /* pre-relaxation sweeps per level (>= 0)              */
   int32_t npost;         /* post-relaxation sweeps per level (>= 0)             */
@@ -74,6 +77,8 @@ typedef struct {
                             captured hipGraph; 0: launch kernels directly     */
   int32_t check_every;   /* iterations enqueued between host convergence polls
                             (1..64)                                            */
+  int32_t cheb_degree;   /* AMG_CHEBYSHEV: steps per sweep (1..16)              */
+  double cheb_ratio;     /* AMG_CHEBYSHEV: upper / lower end of the interval   */
 } amg_params;
 
 /* Optional device allocator; NULL everywhere means hipMalloc / hipFree. */
@@ -168,8 +173,13 @@ amg_status amg_get_aggregates(amg_handle h, int32_t level, int32_t* agg_host);
 amg_status amg_get_level_csr(amg_handle h, int32_t level, int32_t which,
                              int64_t* row_ptr, int32_t* col, double* val);
 
-/* Smoother diagonal m_l (host double[n]) and prolongator damping omega_l. */
-amg_status amg_get_smoother(amg_handle h, int32_t level, double* m_host, double* omega);
+/*
+ * Smoother diagonal m_l (host double[n]), prolongator damping omega_l and,
+ * for AMG_CHEBYSHEV, the Gershgorin bound of the spectrum of D_l^-1 A_l
+ * (0 for the other smoothers).  Any output pointer may be NULL.
+ */
+amg_status amg_get_smoother(amg_handle h, int32_t level, double* m_host, double* omega,
+                            double* cheb_hi);
 
 /*
  * Device SpMV y = A x for a standalone CSR matrix, using the same kernel

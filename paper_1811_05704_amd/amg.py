@@ -26,7 +26,7 @@ AMG_ERR = {
     -7: "AMG_ERR_BREAKDOWN", -8: "AMG_ERR_TOO_LARGE", -9: "AMG_ERR_NAN",
 }
 SOLVERS = {"cg": 0, "bicgstab": 1}
-RELAX = {"spai0": 0, "jacobi": 1}
+RELAX = {"spai0": 0, "jacobi": 1, "chebyshev": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 
 
@@ -43,6 +43,7 @@ class Params(C.Structure):
         ("max_levels", C.c_int32), ("max_iter", C.c_int32),
         ("eps_strong", C.c_double), ("jacobi_omega", C.c_double), ("tol", C.c_double),
         ("use_graph", C.c_int32), ("check_every", C.c_int32),
+        ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
     ]
 
 
@@ -90,7 +91,7 @@ def lib():
         "amg_level_info": (i32, [vp, i32, P64, P64, P64]),
         "amg_get_aggregates": (i32, [vp, i32, P32]),
         "amg_get_level_csr": (i32, [vp, i32, i32, P64, P32, PD]),
-        "amg_get_smoother": (i32, [vp, i32, PD, PD]),
+        "amg_get_smoother": (i32, [vp, i32, PD, PD, PD]),
         "amg_csr_upload": (i32, [i64, i64, P64, P32, PD, i32, vp, C.POINTER(vp)]),
         "amg_csr_spmv": (i32, [vp, vp, vp, vp]),
         "amg_csr_kernel_info": (i32, [vp, P32, P32, P32]),
@@ -133,7 +134,7 @@ def make_params(**kw) -> Params:
     """Defaults of ``amg_params_default`` overridden by keyword arguments.
 
     Accepts the names of the struct fields and string values for ``solver``
-    ("cg" | "bicgstab"), ``relax`` ("spai0" | "jacobi") and ``precision``
+    ("cg" | "bicgstab"), ``relax`` ("spai0" | "jacobi" | "chebyshev") and ``precision``
     ("fp64" | "mixed").
     """
     p = Params()
@@ -210,8 +211,9 @@ class _Handle:
         n, _, _ = self.level_info(level)
         m = np.empty(n, dtype=np.float64)
         om = C.c_double()
-        _check(lib().amg_get_smoother(self._h, level, _ptr(m, C.c_double), C.byref(om)))
-        return m, om.value
+        hi = C.c_double()
+        _check(lib().amg_get_smoother(self._h, level, _ptr(m, C.c_double), C.byref(om), C.byref(hi)))
+        return m, om.value, hi.value
 
     def release(self):
         if self._h:

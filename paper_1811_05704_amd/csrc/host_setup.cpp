@@ -20,8 +20,9 @@
 // of each definition (rows in column order), without fused multiply-adds.
 //
 // The smoother diagonal for each level (section 3, "Relaxation methods"):
-// SPAI-0, m_i = a_ii / sum_j a_ij^2 (Broeker and Grote 2002), or damped
-// Jacobi, m_i = omega_J / a_ii.
+// SPAI-0, m_i = a_ii / sum_j a_ij^2 (Broeker and Grote 2002), damped Jacobi,
+// m_i = omega_J / a_ii, or for Chebyshev m_i = 1 / a_ii together with the
+// Gershgorin bound of the spectrum of D^-1 A.
 
 #include "host_setup.hpp"
 
@@ -394,6 +395,21 @@ Csr smoothed_prolongator(const Csr& A, const Graph& S, const std::vector<int32_t
   return P;
 }
 
+// Gershgorin bound of the spectrum of D^-1 A: max_i (sum_j |a_ij|) / |a_ii|,
+// each row summed in column order.
+double gershgorin_dinv(const Csr& A) {
+  double hi = 0.0;
+  for (int64_t i = 0; i < A.rows; ++i) {
+    double row = 0.0, aii = 0.0;
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      row += std::fabs(A.val[k]);
+      if (A.col[k] == i) aii = A.val[k];
+    }
+    hi = std::max(hi, row / std::fabs(aii));
+  }
+  return hi;
+}
+
 std::vector<double> smoother_diagonal(const Csr& A, const SetupParams& prm) {
   std::vector<double> m(A.rows);
   parallel_rows(A.rows, [&](int64_t b, int64_t e) {
@@ -404,7 +420,7 @@ std::vector<double> smoother_diagonal(const Csr& A, const SetupParams& prm) {
         sq += v * v;
         if (A.col[k] == i) aii = v;
       }
-      m[i] = (prm.relax == 0) ? aii / sq : prm.jacobi_omega / aii;
+      m[i] = (prm.relax == 0) ? aii / sq : (prm.relax == 1) ? prm.jacobi_omega / aii : 1.0 / aii;
     }
   });
   return m;
@@ -428,6 +444,7 @@ HostHierarchy build_hierarchy(Csr A, const SetupParams& prm) {
     L.P = smoothed_prolongator(A, S, agg, nc, &L.omega);
     L.R = transpose(L.P);
     L.m = smoother_diagonal(A, prm);
+    if (prm.relax == 2) L.cheb_hi = gershgorin_dinv(A);
     Csr AP = spgemm(A, L.P);
     Csr Ac = spgemm(L.R, AP);
     L.agg = std::move(agg);

@@ -19,7 +19,7 @@ struct Csr {
 };
 
 struct SetupParams {
-  int relax = 0;  // 0 SPAI-0, 1 damped Jacobi
+  int relax = 0;  // 0 SPAI-0, 1 damped Jacobi, 2 Chebyshev
   double eps_strong = 0.08;
   double jacobi_omega = 0.72;
   int coarse_enough = 3000;
@@ -32,6 +32,7 @@ struct HostLevel {
   std::vector<int32_t> agg;   // aggregate per node, -1 isolated
   std::vector<double> m;      // smoother diagonal
   double omega = 0.0;         // prolongator damping
+  double cheb_hi = 0.0;       // Chebyshev: Gershgorin bound of D^-1 A
   double eps = 0.0;           // strength threshold used on this level
 };
 

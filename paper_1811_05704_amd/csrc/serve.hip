@@ -110,6 +110,12 @@ class DevicePool {
 // Device bytes a request will occupy (hierarchy in the V-cycle's precision,
 // the FP64 fine matrix, dense coarse inverse, vectors, partials), rounded up
 // per allocation; used to reject requests that can never fit.
+// Device bytes held only during setup: the coarse LU factors and pivots.
+size_t coarse_transient(const HostHierarchy& H) {
+  const size_t nL = H.levels.back().A.rows;
+  return nL * nL * 8 + nL * 24 + 4 * 256;
+}
+
 size_t footprint(const HostHierarchy& H, const amg_params& p) {
   const size_t vs = p.precision == AMG_MIXED ? 4 : 8;
   auto csr = [&](const Csr& M, size_t v) { return (M.rows + 1) * 4 + M.nnz() * (4 + v) + 4096; };
@@ -124,6 +130,7 @@ size_t footprint(const HostHierarchy& H, const amg_params& p) {
   }
   const size_t nL = H.levels.back().A.rows;
   b += nL * nL * 8 + nL * 64;
+  b += coarse_transient(H);  // LU factors while the coarse inverse is formed
   b += f.A.rows * 8 * 16;  // Krylov vectors and partials
   return b + 64 * 256;
 }
@@ -424,6 +431,14 @@ void worker_main(amg_server_s* V, int threads) {
       }
       AMG_HIP(hipMemcpyAsync(S.f, q->f.data(), sizeof(double) * S.n, hipMemcpyHostToDevice, ws));
       AMG_HIP(hipStreamSynchronize(ws));
+      {
+        // the coarse LU factors are gone: hand their share of the budget back
+        const size_t t = std::min(coarse_transient(S.host), q->reserved);
+        std::lock_guard<std::mutex> lk(V->mu);
+        V->reserved -= t;
+        q->reserved -= t;
+      }
+      V->cv_mem.notify_all();
       S.arena->set_stream(V->stream);  // from now on the solve lives on the server's stream
       S.setup_s = now_s() - t0;
       q->t_ready = now_s();
@@ -618,8 +633,8 @@ amg_status amg_server_create(const amg_params* p, size_t hbm_budget_bytes, int32
     if (p) V->prm = *p;
     else amg_params_default(&V->prm);
     check_params(V->prm);
-    if (V->prm.solver != AMG_CG || V->prm.npre != 1 || V->prm.npost != 1)
-      throw SetupError{-1, "serving runs PCG with one pre- and one post-sweep"};
+    if (V->prm.solver != AMG_CG || V->prm.npre != 1 || V->prm.npost != 1 || V->prm.relax == AMG_CHEBYSHEV)
+      throw SetupError{-1, "serving runs PCG with one pre- and one post-sweep of SPAI-0 or Jacobi"};
     AMG_HIP(hipGetDevice(&V->device));
     V->max_slots = max_slots;
     V->stream = static_cast<hipStream_t>(hip_stream);

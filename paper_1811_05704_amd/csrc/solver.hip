@@ -21,6 +21,8 @@ void amg_params_default(amg_params* p) {
   p->tol = 1e-8;
   p->use_graph = 1;
   p->check_every = 4;
+  p->cheb_degree = 3;
+  p->cheb_ratio = 30.0;
 }
 
 const char* amg_last_error(void) { return g_last_error.c_str(); }
@@ -84,6 +86,45 @@ amg_status amg_vcycle(amg_handle h, const double* r_dev, double* z_dev, void* hi
 namespace amg {
 namespace {
 
+// Algorithmic bytes of one V-cycle with Chebyshev relaxation, one pre- and
+// one post-sweep of k steps: k passes over A_l for each sweep, one over P_l
+// and R_l, and each vector read or written once per kernel (level 1: f and z
+// FP64); dense coarse inverse + f, z.
+template <class T>
+double cheb_vcycle_bytes(const amg_solver& S, const DevHierarchy<T>& H) {
+  const double sz = sizeof(T);
+  double b = 0.0;
+  const size_t nlev = H.lev.size();
+  for (size_t l = 0; l < nlev; ++l) {
+    const DevLevel<T>& L = H.lev[l];
+    const int k = L.cheb.degree;
+    const double n = L.n, nc = L.nc;
+    const double szf = (l == 0) ? 8.0 : sz;
+    const double passA = double(L.A.nnz) * (sz + 4) + 4.0 * (n + 1);
+    b += 2.0 * k * passA;                                          // pre and post sweeps
+    b += double(L.P.nnz) * (sz + 4) * 2.0 + 4.0 * (n + 1) + 4.0 * (nc + 1);  // P and R
+    // pre-sweep from zero, residual kept
+    if (l == 0) b += n * (sz + szf);                               // m, f
+    else b += n * sz * ((k == 1) ? 2.0 : 3.0);                     // d0, f (, m)
+    b += n * sz * ((k == 1) ? 2.0 : 3.0);                          // x, r (, d')
+    if (k >= 2) b += 7.0 * sz * n * (k - 2) + 5.0 * sz * n;        // middle steps, last step
+    // restriction: r in; f_c (and d0_c from m_c) out
+    b += sz * n + ((l + 1 < nlev) ? 3.0 * sz * nc : sz * nc);
+    // prolongation: z_c, x_pre in; y out
+    b += sz * nc + 2.0 * sz * n;
+    // post-sweep from y
+    if (k == 1) {
+      b += n * (2.0 * sz + szf) + n * szf;                         // y, f, m in; z out
+    } else {
+      b += n * (2.0 * sz + szf) + 2.0 * sz * n;                    // init: y, f, m in; r, d out
+      b += 7.0 * sz * n * (k - 2);                                 // middle steps
+      b += 4.0 * sz * n + szf * n;                                 // fused last: d, x, r, m in; z out
+    }
+  }
+  b += 8.0 * double(S.nL) * double(S.nL) + 2.0 * double(S.nL) * sz;
+  return b;
+}
+
 template <class T>
 double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps, hipStream_t s,
                           double* bytes) {
@@ -119,7 +160,7 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
                     st);
         break;
       default: {
-        VcycleOpts o{S.prm.npre, S.prm.npost};
+        VcycleOpts o{S.prm.npre, S.prm.npost, S.prm.relax};
         Vcycle<T> V(&H, S.Ainv, S.nL, o);
         V.template run<0>(S.r, S.z, S.partials, nullptr, st);
         break;
@@ -154,6 +195,10 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
   (void)hipEventDestroy(e1);
   (void)hipGraphExecDestroy(ge);
   (void)hipGraphDestroy(g);
+  if (which == 5 && S.prm.relax == AMG_CHEBYSHEV) {
+    *bytes = cheb_vcycle_bytes(S, H);
+    return 1000.0 * ms / reps;
+  }
   if (which == 5) {
     // Algorithmic bytes of one V-cycle with npre = npost = 1: per level
     // 2 passes over A_l, one over P_l and R_l each, 11 vector passes of n_l
@@ -241,12 +286,13 @@ amg_status amg_get_level_csr(amg_handle h, int32_t level, int32_t which, int64_t
   });
 }
 
-amg_status amg_get_smoother(amg_handle h, int32_t level, double* m_host, double* omega) {
+amg_status amg_get_smoother(amg_handle h, int32_t level, double* m_host, double* omega, double* cheb_hi) {
   return guarded([&]() -> amg_status {
     const HostLevel& L = level_of(h, level);
     if (L.m.empty()) throw SetupError{-1, "the coarsest level has no smoother"};
     if (m_host) std::memcpy(m_host, L.m.data(), L.m.size() * sizeof(double));
     if (omega) *omega = L.omega;
+    if (cheb_hi) *cheb_hi = L.cheb_hi;
     return AMG_OK;
   });
 }

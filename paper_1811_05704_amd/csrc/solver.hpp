@@ -24,6 +24,7 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <memory>
@@ -31,6 +32,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "chebyshev.hpp"
 #include "device.hpp"
 
 namespace amg {
@@ -57,7 +59,10 @@ struct DevLevel {
   T* t = nullptr;  // ping-pong buffer for repeated sweeps
   T* zp[2] = {nullptr, nullptr};  // stored pre-smoothed iterate (npre > 1)
   T* z = nullptr;   // output on levels > 0
-  T* mf = nullptr;  // m .* f, written by the restriction (levels > 0, npre = 1)
+  T* mf = nullptr;  // m .* f, written by the restriction (levels > 0, npre = 1);
+                    // Chebyshev: the first direction (m .* f) / theta
+  T* dc[2] = {nullptr, nullptr};  // Chebyshev directions (ping-pong)
+  ChebCoef<T> cheb;               // Chebyshev coefficients
 };
 
 template <class T>
@@ -69,6 +74,7 @@ struct DevHierarchy {
 
 struct VcycleOpts {
   int npre = 1, npost = 1;
+  int relax = AMG_SPAI0;
 };
 
 // ------------------------------------------------------------------ V-cycle
@@ -121,6 +127,10 @@ class Vcycle {
   // pre-sweep, m .* f was written by the restriction that produced f.
   template <class TF>
   void down(DevLevel<T>& lv, const TF* f, DevLevel<T>* next, const int* skip, hipStream_t s) {
+    if (o_.relax == AMG_CHEBYSHEV && o_.npre > 0) {
+      cheb_down(lv, f, next, skip, s);
+      return;
+    }
     T* fnext = next ? next->f : h_->fL;
     auto restrict_from = [&](auto gather) {
       if (next && o_.npre == 1)
@@ -161,6 +171,7 @@ class Vcycle {
   template <class TF, class TZ, int DOT>
   int up(DevLevel<T>& lv, const TF* f, const T* zc, TZ* zout, double* partials, const int* skip,
          hipStream_t s) {
+    if (o_.relax == AMG_CHEBYSHEV) return cheb_up<TF, TZ, DOT>(lv, f, zc, zout, partials, skip, s);
     if (o_.npre == 0) {
       launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 0>{lv.y, lv.m, f, nullptr}, nullptr, skip, s);
     } else if (o_.npre == 1) {
@@ -194,11 +205,135 @@ class Vcycle {
     return DOT ? nparts : 0;
   }
 
+  // ---- Chebyshev relaxation (one sweep = `degree` steps, see chebyshev.hpp)
+
+  // Pre-sweeps from a zero guess, x in zp[]; the last one keeps its residual
+  // in lv.r, which is restricted.
+  template <class TF>
+  void cheb_down(DevLevel<T>& lv, const TF* f, DevLevel<T>* next, const int* skip, hipStream_t s) {
+    int xi = 0;
+    for (int k = 0; k < o_.npre; ++k) {
+      const bool keep_r = (k == o_.npre - 1);
+      xi = cheb_sweep<TF, T, 0>(lv, f, k == 0, keep_r, xi, lv.zp, lv.zp[xi], nullptr, skip, s);
+    }
+    pre_cur_ = xi;
+    if (next)
+      launch_spmv(lv.R, GatherX<T, T>{lv.r}, EpiRestrictCheb<T>{next->f, next->mf, next->m, next->cheb.theta},
+                  nullptr, skip, s);
+    else
+      launch_spmv(lv.R, GatherX<T, T>{lv.r}, EpiStore<T, T>{h_->fL}, nullptr, skip, s);
+  }
+
+  // Prolongation + correction, then post-sweeps from y; the last writes zout.
+  template <class TF, class TZ, int DOT>
+  int cheb_up(DevLevel<T>& lv, const TF* f, const T* zc, TZ* zout, double* partials, const int* skip,
+              hipStream_t s) {
+    if (o_.npre == 0)
+      launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 0>{lv.y, lv.m, f, nullptr}, nullptr, skip, s);
+    else
+      launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, TF, 2>{lv.y, lv.m, f, lv.zp[pre_cur_]}, nullptr,
+                  skip, s);
+    if (o_.npost == 0) {
+      int nb = vec_blocks(lv.n);
+      copy_dot_kernel<T, TF, TZ, DOT><<<nb, kVecBS, 0, s>>>(lv.n, zout, lv.y, f, partials, skip);
+      AMG_LAUNCHED();
+      return DOT ? nb : 0;
+    }
+    T* xs[2] = {lv.y, lv.t};
+    int xi = 0;
+    for (int k = 0; k + 1 < o_.npost; ++k) xi = cheb_sweep<TF, T, 0>(lv, f, false, false, xi, xs, xs[xi], nullptr, skip, s);
+    cheb_nparts_ = 0;
+    cheb_sweep<TF, TZ, DOT>(lv, f, false, false, xi, xs, zout, partials, skip, s);
+    return DOT ? cheb_nparts_ : 0;
+  }
+
+  // One step (s = A d) of a sweep; coefficients of step j.
+  template <int Z, int D0, int MODE, int DOT, class TF, class TZ>
+  int cheb_step(DevLevel<T>& lv, const TF* f, const T* d, T* dn, T* x, TZ* out, int j, double* partials,
+                const int* skip, hipStream_t s) {
+    const ChebCoef<T>& c = lv.cheb;
+    EpiChebStep<T, TF, TZ, Z, D0, MODE, DOT> e{x, lv.r, d, dn, lv.m, f, c.theta, c.c1[j], c.c2[j], out};
+    if constexpr (Z && !D0)
+      return launch_spmv(lv.A, GatherMFc<T, TF>{lv.m, f, c.theta}, e, DOT ? partials : nullptr, skip, s);
+    else
+      return launch_spmv(lv.A, GatherX<T, T>{d}, e, DOT ? partials : nullptr, skip, s);
+  }
+
+  // One sweep on level lv for A x = f with x = xs[xi] (ignored when
+  // from_zero).  keep_r: the last step is carried out in full, leaving the
+  // result in xs[xi] and its residual in lv.r.  Otherwise the result goes to
+  // out (which may be xs[xi] except when the sweep is a single step from a
+  // nonzero guess: that product gathers x, so the result goes to
+  // xs[1 - xi]).  Returns the index of the buffer holding the result when out
+  // is one of xs; DOT partial counts go to cheb_nparts_.
+  template <class TF, class TZ, int DOT>
+  int cheb_sweep(DevLevel<T>& lv, const TF* f, bool from_zero, bool keep_r, int xi, T* const* xs, TZ* out,
+                 double* partials, const int* skip, hipStream_t s) {
+    const ChebCoef<T>& c = lv.cheb;
+    const int k = c.degree;
+    T* x = xs[xi];
+    const T* d0 = lv.mf;  // stored first direction (levels > 0), else recomputed
+    if (from_zero && k == 1 && !keep_r) {
+      // x = d0 and no residual wanted: no product.  (Never the DOT sweep,
+      // which starts from the prolongated iterate.)
+      if (d0)
+        cheb_first_kernel<T, TF, TZ, 1><<<vec_blocks(lv.n), kVecBS, 0, s>>>(lv.n, out, d0, lv.m, f, c.theta, skip);
+      else
+        cheb_first_kernel<T, TF, TZ, 0><<<vec_blocks(lv.n), kVecBS, 0, s>>>(lv.n, out, d0, lv.m, f, c.theta, skip);
+      AMG_LAUNCHED();
+      return xi;
+    }
+    int cur = 0;
+    if (!from_zero) {
+      if (k == 1 && !keep_r) {
+        TZ* o = out;
+        int res = xi;
+        if (static_cast<const void*>(out) == static_cast<const void*>(x)) {
+          o = reinterpret_cast<TZ*>(xs[1 - xi]);
+          res = 1 - xi;
+        }
+        int nb = launch_spmv(lv.A, GatherX<T, T>{x},
+                             EpiChebInit<T, TF, TZ, 1, DOT>{x, lv.r, nullptr, lv.m, f, c.theta, o},
+                             DOT ? partials : nullptr, skip, s);
+        if (DOT) cheb_nparts_ = nb;
+        return res;
+      }
+      launch_spmv(lv.A, GatherX<T, T>{x}, EpiChebInit<T, TF, T, 0, 0>{x, lv.r, lv.dc[0], lv.m, f, c.theta, nullptr},
+                  nullptr, skip, s);
+    }
+    for (int j = 0; j < k; ++j) {
+      const bool zero = from_zero && j == 0;
+      const int mode = (j == k - 1) ? kChebLast : (!keep_r && j == k - 2) ? kChebFused : kChebMid;
+      const T* dcur = zero ? d0 : lv.dc[cur];
+      T* dnext = zero ? lv.dc[0] : lv.dc[1 - cur];
+      if (mode == kChebFused) {
+        int nb;
+        if (!zero) nb = cheb_step<0, 0, kChebFused, DOT>(lv, f, dcur, dnext, x, out, j, partials, skip, s);
+        else if (d0) nb = cheb_step<1, 1, kChebFused, DOT>(lv, f, dcur, dnext, x, out, j, partials, skip, s);
+        else nb = cheb_step<1, 0, kChebFused, DOT>(lv, f, dcur, dnext, x, out, j, partials, skip, s);
+        if (DOT) cheb_nparts_ = nb;
+        return xi;
+      }
+      if (mode == kChebLast) {
+        if (!zero) cheb_step<0, 0, kChebLast, 0>(lv, f, dcur, dnext, x, x, j, nullptr, skip, s);
+        else if (d0) cheb_step<1, 1, kChebLast, 0>(lv, f, dcur, dnext, x, x, j, nullptr, skip, s);
+        else cheb_step<1, 0, kChebLast, 0>(lv, f, dcur, dnext, x, x, j, nullptr, skip, s);
+      } else {
+        if (!zero) cheb_step<0, 0, kChebMid, 0>(lv, f, dcur, dnext, x, x, j, nullptr, skip, s);
+        else if (d0) cheb_step<1, 1, kChebMid, 0>(lv, f, dcur, dnext, x, x, j, nullptr, skip, s);
+        else cheb_step<1, 0, kChebMid, 0>(lv, f, dcur, dnext, x, x, j, nullptr, skip, s);
+      }
+      cur = zero ? 0 : 1 - cur;
+    }
+    return xi;
+  }
+
   DevHierarchy<T>* h_;
   const double* Ainv_;
   int32_t nL_;
   VcycleOpts o_;
   int pre_cur_ = 0;
+  int cheb_nparts_ = 0;
 };
 
 // ------------------------------------------------------------------ solver object
@@ -255,7 +390,12 @@ inline SetupParams setup_params(const amg_params& p) {
 
 inline void check_params(const amg_params& p) {
   if (p.solver != AMG_CG && p.solver != AMG_BICGSTAB) throw SetupError{-1, "solver must be AMG_CG or AMG_BICGSTAB"};
-  if (p.relax != AMG_SPAI0 && p.relax != AMG_JACOBI) throw SetupError{-1, "relax must be AMG_SPAI0 or AMG_JACOBI"};
+  if (p.relax != AMG_SPAI0 && p.relax != AMG_JACOBI && p.relax != AMG_CHEBYSHEV)
+    throw SetupError{-1, "relax must be AMG_SPAI0, AMG_JACOBI or AMG_CHEBYSHEV"};
+  if (p.relax == AMG_CHEBYSHEV) {
+    if (p.cheb_degree < 1 || p.cheb_degree > kMaxChebDegree) throw SetupError{-1, "cheb_degree must be in [1, 16]"};
+    if (!(p.cheb_ratio > 1.0)) throw SetupError{-1, "cheb_ratio must be > 1"};
+  }
   if (p.precision != AMG_FP64 && p.precision != AMG_MIXED) throw SetupError{-1, "precision must be AMG_FP64 or AMG_MIXED"};
   if (p.npre < 0 || p.npost < 0 || p.npre > 16 || p.npost > 16) throw SetupError{-1, "npre/npost must be in [0, 16]"};
   if (p.coarse_enough < 1 || p.max_levels < 1 || p.max_iter < 1) throw SetupError{-1, "coarse_enough, max_levels, max_iter must be >= 1"};
@@ -272,17 +412,36 @@ inline Csr to_csr(int64_t n, const int64_t* ptr, const int32_t* col, const doubl
   return A;
 }
 
-// Dense inverse of the coarsest operator on the device (LU with partial
-// pivoting, then inversion; FP64).  The row-major host matrix read as
+// M = I (n x n, dense)
+static __global__ void __launch_bounds__(kVecBS) identity_kernel(int n, double* M) {
+  const int64_t total = static_cast<int64_t>(n) * n;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kVecBS;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * kVecBS + threadIdx.x; k < total; k += stride)
+    M[k] = (k / n == k % n) ? 1.0 : 0.0;
+}
+
+// Dense inverse of the coarsest operator on the device (FP64): LU with
+// partial pivoting of a transient copy (rocsolver getrf), then the n
+// triangular solves LU X = I (getrs).  The row-major host matrix read as
 // column-major is A^T, and inv(A^T) read back as row-major is inv(A).
-inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, rocblas_handle shared = nullptr) {
+// rocsolver's in-place getri is not used: on the ROCm 7.2 / gfx950 stack it
+// returns a wrong inverse for some orders (for example 255, 511, 895, 1023;
+// getrf and getrs are correct there), so the inverse is also checked once:
+// Ainv (A v) must reproduce a known vector v.
+inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, const amg_allocator* alloc,
+                           rocblas_handle shared = nullptr) {
   const int32_t n = static_cast<int32_t>(AL.rows);
   std::vector<double> dense(static_cast<size_t>(n) * n, 0.0);
   for (int64_t i = 0; i < n; ++i)
     for (int64_t e = AL.ptr[i]; e < AL.ptr[i + 1]; ++e) dense[static_cast<size_t>(i) * n + AL.col[e]] = AL.val[e];
-  S.Ainv = S.arena->upload(dense.data(), dense.size());
-  rocblas_int* ipiv = S.arena->get<rocblas_int>(n);
-  rocblas_int* dinfo = S.arena->get<rocblas_int>(1);
+  S.Ainv = S.arena->get<double>(static_cast<size_t>(n) * n);
+  DevArena tmp(alloc, stream);  // LU factors, pivots: freed on return
+  double* lu = tmp.upload(dense.data(), dense.size());
+  rocblas_int* ipiv = tmp.get<rocblas_int>(n);
+  rocblas_int* dinfo = tmp.get<rocblas_int>(1);
+  identity_kernel<<<std::min<int64_t>((static_cast<int64_t>(n) * n + kVecBS - 1) / kVecBS, 65536), kVecBS, 0,
+                    stream>>>(n, S.Ainv);
+  AMG_LAUNCHED();
   rocblas_handle hb = shared;
   if (!hb && rocblas_create_handle(&hb) != rocblas_status_success) throw DevError{-6, "rocblas_create_handle failed"};
   rocblas_set_stream(hb, stream);
@@ -290,7 +449,7 @@ inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, roc
     if (!shared) rocblas_destroy_handle(hb);
   };
   rocblas_int info = 0;
-  rocblas_status st1 = rocsolver_dgetrf(hb, n, n, S.Ainv, n, ipiv, dinfo);
+  rocblas_status st1 = rocsolver_dgetrf(hb, n, n, lu, n, ipiv, dinfo);
   hipError_t e1 = hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, stream);
   hipError_t e2 = hipStreamSynchronize(stream);
   if (st1 != rocblas_status_success || e1 != hipSuccess || e2 != hipSuccess) {
@@ -301,12 +460,27 @@ inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, roc
     release();
     throw DevError{-4, "zero pivot " + std::to_string(info) + " in the coarsest LU (n = " + std::to_string(n) + ")"};
   }
-  rocblas_status st2 = rocsolver_dgetri(hb, n, S.Ainv, n, ipiv, dinfo);
-  e1 = hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, stream);
+  rocblas_status st2 = rocsolver_dgetrs(hb, rocblas_operation_none, n, n, lu, n, ipiv, S.Ainv, n);
   e2 = hipStreamSynchronize(stream);
   release();
-  if (st2 != rocblas_status_success || e1 != hipSuccess || e2 != hipSuccess || info != 0)
-    throw DevError{-4, "coarse inversion failed"};
+  if (st2 != rocblas_status_success || e2 != hipSuccess) throw DevError{-6, "coarse triangular solves failed"};
+  // check: z = Ainv (A v) against v, v_i = 1 + (i mod 7) / 8, to 1e-3
+  // relative (a wrong inverse is off by O(1); ill-conditioning up to about
+  // 1e12 passes)
+  std::vector<double> v(n), w(n, 0.0), z(n);
+  for (int32_t i = 0; i < n; ++i) v[i] = 1.0 + (i % 7) / 8.0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t e = AL.ptr[i]; e < AL.ptr[i + 1]; ++e) w[i] += AL.val[e] * v[AL.col[e]];
+  double* wd = tmp.upload(w.data(), w.size());
+  double* zd = tmp.get<double>(n);
+  coarse_gemv_kernel<double, double><<<n, kBS, 0, stream>>>(n, S.Ainv, wd, zd, nullptr);
+  AMG_LAUNCHED();
+  AMG_HIP(hipMemcpyAsync(z.data(), zd, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+  AMG_HIP(hipStreamSynchronize(stream));
+  double err = 0.0;
+  for (int32_t i = 0; i < n; ++i) err = std::max(err, std::fabs(z[i] - v[i]) / v[i]);
+  if (!(err <= 1e-3))
+    throw DevError{-4, "coarse inverse check failed (max error " + std::to_string(err) + ", n = " + std::to_string(n) + ")"};
 }
 
 template <class T>
@@ -314,6 +488,7 @@ inline void upload_levels(amg_solver& S, DevHierarchy<T>& H) {
   DevArena& ar = *S.arena;
   const int L = static_cast<int>(S.host.levels.size());
   const int npre = S.prm.npre;
+  const bool cheb = S.prm.relax == AMG_CHEBYSHEV;
   for (int l = 0; l < L - 1; ++l) {
     const HostLevel& hl = S.host.levels[l];
     DevLevel<T> d;
@@ -332,14 +507,19 @@ inline void upload_levels(amg_solver& S, DevHierarchy<T>& H) {
     if (l > 0) {
       d.f = ar.get<T>(d.n);
       d.z = ar.get<T>(d.n);
-      if (npre == 1) d.mf = ar.get<T>(d.n);
+      if (npre == 1 || (cheb && npre > 0)) d.mf = ar.get<T>(d.n);
     }
     d.r = ar.get<T>(d.n);
     d.y = ar.get<T>(d.n);
     d.t = ar.get<T>(d.n);
-    if (npre > 1) {
+    if (npre > 1 || cheb) {
       d.zp[0] = ar.get<T>(d.n);
       d.zp[1] = ar.get<T>(d.n);
+    }
+    if (cheb) {
+      d.dc[0] = ar.get<T>(d.n);
+      d.dc[1] = ar.get<T>(d.n);
+      d.cheb = cheb_coefficients<T>(hl.cheb_hi, S.prm.cheb_ratio, S.prm.cheb_degree);
     }
     H.lev.push_back(d);
   }
@@ -365,7 +545,7 @@ inline int64_t max_parts(const amg_solver& S) {
 
 template <class F>
 inline auto with_vcycle(amg_solver& S, F fn) {
-  VcycleOpts o{S.prm.npre, S.prm.npost};
+  VcycleOpts o{S.prm.npre, S.prm.npost, S.prm.relax};
   if (S.prm.precision == AMG_MIXED) {
     Vcycle<float> V(&S.h32, S.Ainv, S.nL, o);
     return fn(V);
@@ -563,7 +743,7 @@ inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t 
   S.A0 = upload_csr<double>(ar, fine.A);
   if (S.prm.precision == AMG_MIXED) upload_levels<float>(S, S.h32);
   else upload_levels<double>(S, S.h64);
-  coarse_inverse(S, AL, s, opts.blas);
+  coarse_inverse(S, AL, s, alloc, opts.blas);
   if (opts.standalone) {
     S.st = ar.get<KState>(1);
     AMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.st_host), sizeof(KState), hipHostMallocDefault));

@@ -48,7 +48,8 @@ def _problem(name):
 
 
 def _oracle_params(kw):
-    keys = ("solver", "relax", "npre", "npost", "coarse_enough", "max_iter", "tol", "max_levels")
+    keys = ("solver", "relax", "npre", "npost", "coarse_enough", "max_iter", "tol", "max_levels",
+            "cheb_degree", "cheb_ratio")
     return oracle.Params(**{k: v for k, v in kw.items() if k in keys})
 
 
@@ -64,6 +65,19 @@ VCYCLE_CASES = [
     ("poisson20", {"npre": 1, "npost": 0}),
     ("poisson20", {"npre": 3, "npost": 2, "relax": "jacobi"}),
     ("poisson20", {"coarse_enough": 50}),
+    # Chebyshev relaxation: every sweep shape the device path distinguishes
+    ("poisson32", {"relax": "chebyshev"}),
+    ("diffusion24", {"relax": "chebyshev"}),
+    ("convection24", {"relax": "chebyshev"}),
+    ("diffusion24", {"relax": "chebyshev", "cheb_degree": 5, "cheb_ratio": 10.0}),
+    ("poisson20", {"relax": "chebyshev", "cheb_degree": 1}),
+    ("poisson20", {"relax": "chebyshev", "cheb_degree": 2}),
+    ("poisson20", {"relax": "chebyshev", "cheb_degree": 2, "npre": 2, "npost": 2}),
+    ("poisson20", {"relax": "chebyshev", "cheb_degree": 1, "npre": 2, "npost": 3}),
+    ("poisson20", {"relax": "chebyshev", "cheb_degree": 3, "npre": 3, "npost": 2}),
+    ("poisson20", {"relax": "chebyshev", "npre": 0, "npost": 1}),
+    ("poisson20", {"relax": "chebyshev", "npre": 1, "npost": 0}),
+    ("poisson20", {"relax": "chebyshev", "coarse_enough": 50}),
 ]
 
 
@@ -94,9 +108,20 @@ def test_vcycle_worked_example(golden_dir):
     S.release()
 
 
-@pytest.mark.parametrize("name", ["poisson32", "diffusion24", "convection24"])
-def test_vcycle_mixed_matches_fp32_oracle(name):
+MIXED_CASES = [
+    ("poisson32", {}),
+    ("diffusion24", {}),
+    ("convection24", {}),
+    ("poisson32", {"relax": "chebyshev"}),
+    ("diffusion24", {"relax": "chebyshev", "cheb_degree": 2}),
+    ("poisson20", {"relax": "chebyshev", "cheb_degree": 1, "npre": 2, "npost": 2}),
+]
+
+
+@pytest.mark.parametrize("name,extra", MIXED_CASES, ids=[f"{c[0]}-{i}" for i, c in enumerate(MIXED_CASES)])
+def test_vcycle_mixed_matches_fp32_oracle(name, extra):
     A, kw = _problem(name)
+    kw = {**kw, **extra}
     S = amg.Solver(A, precision="mixed", **kw)
     h = oracle.setup(A, _oracle_params(kw))
     r = np.random.default_rng(12).standard_normal(A.n)
@@ -121,6 +146,9 @@ SOLVE_CASES = [
     ("diffusion24", "ones", {"solver": "bicgstab", "relax": "jacobi"}),
     ("convection24", "ones", {"solver": "bicgstab"}),
     ("convection24", "ones", {"solver": "bicgstab", "precision": "mixed"}),
+    ("poisson32", "uniform", {"relax": "chebyshev"}),
+    ("diffusion24", "ones", {"relax": "chebyshev", "precision": "mixed"}),
+    ("diffusion24", "ones", {"relax": "chebyshev", "solver": "bicgstab"}),
 ]
 
 
@@ -142,6 +170,42 @@ def test_solve_matches_oracle(name, rhs, kw):
     assert abs(tr - info["true_rel_resid"]) <= 1e-3 * tr + 1e-15
     assert rel_err(x, xo) <= 1e-6
     S.release()
+
+
+@pytest.mark.parametrize("n", [255, 383, 511, 895, 900, 1023, 2999])
+def test_coarse_inverse_every_order(n):
+    """Single-level hierarchy (the whole matrix is the coarsest level): the
+    device's dense inverse applied to f equals a dense solve.  Orders of the
+    form 128k - 1 are included on purpose: an in-place LAPACK-style inversion
+    of the ROCm stack was found wrong at those."""
+    A = problems.tridiag1d(n)
+    S = amg.Solver(A, coarse_enough=n)
+    assert S.nlevels == 1
+    f = np.random.default_rng(n).standard_normal(n)
+    announce("coarse inverse order", n)
+    z = host(S.vcycle(dev(f)))
+    zr = np.linalg.solve(A.to_scipy().toarray(), f)
+    assert rel_err(z, zr) <= 1e-8
+    S.release()
+
+
+def test_solve_with_coarsest_order_895():
+    """Diffusion 45^3, k = exp(g), sigma 1, length 8, field seed 10332, f = 1:
+    a three-level hierarchy whose coarsest order is 895.  Iterations within
+    +-1 of the oracle and the true residual on the CPU."""
+    A = problems.diffusion3d(45, problems.gaussian_field(45, 1.0, 8.0, 10332))
+    f = problems.rhs_ones(A.n)
+    h = oracle.setup(A)
+    assert h.levels[-1].A.shape[0] == 895
+    for precision in ("fp64", "mixed"):
+        S = amg.Solver(A, precision=precision)
+        announce("coarsest order 895 solve", precision)
+        x, info = S.solve(dev(f))
+        _, io, _ = oracle.solve(A, f, h=h, mixed=(precision == "mixed"))
+        assert info["status"] == 0
+        assert abs(info["iters"] - io.iters) <= 1
+        assert true_rel_residual(A, host(x), f) <= 1e-8
+        S.release()
 
 
 def test_zero_rhs_gives_zero():
@@ -261,7 +325,8 @@ def test_full_size_poisson150(precision):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("variant", ["sym-cg-spai0", "sym-bicgstab-jacobi", "nonsym-bicgstab-jacobi"])
+@pytest.mark.parametrize("variant", ["sym-cg-spai0", "sym-bicgstab-jacobi", "nonsym-bicgstab-jacobi",
+                                     "sym-cg-chebyshev"])
 def test_full_size_diffusion128(variant):
     """128^3 variable-coefficient diffusion, k = exp(g), sigma 2, length 8
     (field seed 1), f = 1; the nonsymmetric form adds upwind convection

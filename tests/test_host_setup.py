@@ -40,6 +40,7 @@ def test_params_default_values():
     assert (p.solver, p.relax, p.precision, p.npre, p.npost) == (0, 0, 0, 1, 1)
     assert (p.coarse_enough, p.max_levels, p.max_iter) == (3000, 30, 500)
     assert p.eps_strong == 0.08 and p.jacobi_omega == 0.72 and p.tol == 1e-8
+    assert (p.cheb_degree, p.cheb_ratio) == (3, 30.0)
 
 
 def _cases():
@@ -50,6 +51,7 @@ def _cases():
         ("diffusion24", problems.diffusion3d(24, g), "spai0"),
         ("diffusion24-jacobi", problems.diffusion3d(24, g), "jacobi"),
         ("convection24", problems.diffusion3d(24, g, velocity=(50.0, 25.0, 12.5)), "jacobi"),
+        ("diffusion24-chebyshev", problems.diffusion3d(24, g), "chebyshev"),
     ]
 
 
@@ -72,9 +74,10 @@ def test_hierarchy_matches_oracle(name, A, relax):
         R = H.level_scipy(l, "R")
         assert abs(P - h.levels[l].P).max() == 0.0
         assert abs(R - P.T).max() == 0.0
-        m, omega = H.smoother(l)
+        m, omega, hi = H.smoother(l)
         assert np.array_equal(m, h.levels[l].m)
         assert omega == h.levels[l].omega
+        assert hi == (h.levels[l].cheb_hi or 0.0)
         # columns ascending in every row of the library's matrices
         for M in (Al, P, R):
             d = np.diff(M.indices)
