@@ -94,7 +94,7 @@ def lib():
         "amg_get_smoother": (i32, [vp, i32, PD, PD, PD]),
         "amg_csr_upload": (i32, [i64, i64, P64, P32, PD, i32, vp, C.POINTER(vp)]),
         "amg_csr_spmv": (i32, [vp, vp, vp, vp]),
-        "amg_csr_kernel_info": (i32, [vp, P32, P32, P32]),
+        "amg_csr_kernel_info": (i32, [vp, P32, P32, P32, P32]),
         "amg_csr_release": (None, [vp]),
         "amg_time_kernel": (i32, [vp, i32, i32, vp, PD, PD]),
         "amg_server_create": (i32, [C.POINTER(Params), C.c_size_t, i32, i32, vp, C.POINTER(vp)]),
@@ -347,9 +347,10 @@ class DeviceMatrix:
         self._h = h
 
     def kernel_info(self):
-        k, l, b = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(lib().amg_csr_kernel_info(self._h, C.byref(k), C.byref(l), C.byref(b)))
-        return {"kind": ("stream", "vector")[k.value], "lanes": l.value, "blocks": b.value}
+        k, l, b, nb = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().amg_csr_kernel_info(self._h, C.byref(k), C.byref(l), C.byref(b), C.byref(nb)))
+        return {"kind": ("stream", "vector")[k.value], "lanes": l.value, "blocks": b.value,
+                "block_bytes": nb.value}
 
     def spmv(self, x, y=None):
         import torch

@@ -113,13 +113,14 @@ struct DevCsr {
   T* val = nullptr;
   int kind = 0;   // 0 stream, 1 vector
   int lanes = 1;  // lanes per row (stream: in the LDS reduction phase)
+  int small = 0;  // stream: 4 KB blocks instead of 16 KB
   int32_t nblocks = 0;
   int32_t* blk = nullptr;
   CsrView<T> view() const { return CsrView<T>{ptr, col, val, blk, rows, nblocks}; }
 };
 
 struct Schedule {
-  int kind = 0, lanes = 1;
+  int kind = 0, lanes = 1, small = 0;
   std::vector<int32_t> blk;
   int32_t nblocks = 0;
 };
@@ -138,7 +139,8 @@ Schedule make_schedule(const Csr& M, int force_kind = -1) {
   const double mean = rows ? double(M.nnz()) / double(rows) : 0.0;
   s.kind = force_kind >= 0 ? force_kind : (mean <= kVectorMinMean ? 0 : 1);
   if (s.kind == 0) {
-    constexpr int64_t cap = stream_cap<T>();
+    s.small = M.nnz() * static_cast<int64_t>(sizeof(T)) < kStreamSmallMatrix;
+    const int64_t cap = s.small ? stream_nnz<T, kStreamSmallBytes>() : stream_nnz<T>();
     s.lanes = stream_lanes(mean);
     s.blk.push_back(0);
     int64_t r = 0;
@@ -175,18 +177,17 @@ DevCsr<T> upload_csr(DevArena& ar, const Csr& M, int force_kind = -1) {
   std::vector<int32_t> p32(M.ptr.begin(), M.ptr.end());
   if (p32.empty()) p32.assign(1, 0);
   d.ptr = ar.upload(p32.data(), p32.size());
-  // col and val carry 4 zero entries of padding: the stream kernel's aligned
-  // 4-entry loads may read up to 3 entries past the last one.
   const size_t nz = M.col.size();
-  std::vector<int32_t> c(nz + 4, 0);
-  std::copy(M.col.begin(), M.col.end(), c.begin());
+  std::vector<int32_t> c(M.col.begin(), M.col.end());
+  if (c.empty()) c.assign(1, 0);
   d.col = ar.upload(c.data(), c.size());
-  std::vector<T> v(nz + 4, T(0));
+  std::vector<T> v(std::max<size_t>(nz, 1), T(0));
   for (size_t k = 0; k < nz; ++k) v[k] = static_cast<T>(M.val[k]);  // FP32: round to nearest
   d.val = ar.upload(v.data(), v.size());
   Schedule s = make_schedule<T>(M, force_kind);
   d.kind = s.kind;
   d.lanes = s.lanes;
+  d.small = s.small;
   d.nblocks = s.nblocks;
   if (s.kind == 0) d.blk = ar.upload(s.blk.data(), s.blk.size());
   // upload uses pageable host buffers: finish before they go out of scope
@@ -200,11 +201,18 @@ template <class T, class G, class E>
 int launch_spmv(const DevCsr<T>& M, G g, E e, double* partials, const int* skip, hipStream_t s) {
   if (M.rows == 0) return 0;
   if (M.kind == 0) {
-    switch (M.lanes) {
-      case 1: csr_stream_kernel<1, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
-      case 4: csr_stream_kernel<4, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
-      case 16: csr_stream_kernel<16, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
-      default: csr_stream_kernel<64, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip); break;
+    constexpr int NS = kStreamSmallBytes, NL = AMG_STREAM_BYTES;
+    const CsrView<T> A = M.view();
+    const int n = M.nblocks;
+    switch (M.lanes * 2 + M.small) {
+      case 2: csr_stream_kernel<1, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 3: csr_stream_kernel<1, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 8: csr_stream_kernel<4, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 9: csr_stream_kernel<4, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 32: csr_stream_kernel<16, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 33: csr_stream_kernel<16, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 128: csr_stream_kernel<64, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      default: csr_stream_kernel<64, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
     }
   } else {
     csr_vector_kernel<64, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip);

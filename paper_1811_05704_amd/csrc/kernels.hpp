@@ -220,117 +220,64 @@ struct EpiSmooth {
 
 // ---------------------------------------------------------------- SpMV kernels
 
-// Entries staged in LDS per stream block: AMG_STREAM_BYTES of products
-// (16 KB: 2048 FP64 or 4096 FP32 values, 8 or 16 per thread).
+// Products staged in LDS per stream block: AMG_STREAM_BYTES (16 KB: 2048
+// FP64 or 4096 FP32 values, 8 or 16 per thread) for large matrices, and
+// kStreamSmallBytes (4 KB) for matrices below kStreamSmallMatrix bytes of
+// values, where the larger blocks would leave too few workgroups to hide
+// memory latency (measured on the level matrices of the 150^3 hierarchy:
+// 15-40% faster below 32 MB, no gain above).
 #ifndef AMG_STREAM_BYTES
 #define AMG_STREAM_BYTES 16384
 #endif
-// Entries per lane and load instruction in the stream kernel (1 or 4).
-#ifndef AMG_STREAM_VEC
-#define AMG_STREAM_VEC 1
-#endif
-constexpr int kStreamVec = AMG_STREAM_VEC;
+constexpr int kStreamSmallBytes = 4096;
+constexpr int64_t kStreamSmallMatrix = int64_t(32) << 20;
 
-template <class T>
+template <class T, int NB = AMG_STREAM_BYTES>
 constexpr int stream_nnz() {
-  return AMG_STREAM_BYTES / static_cast<int>(sizeof(T));
+  return NB / static_cast<int>(sizeof(T));
 }
 
-// Most entries a stream block may hold: with 4-entry loads the aligned load
-// window starts up to 3 entries before the block.
-template <class T>
-constexpr int stream_cap() {
-  return stream_nnz<T>() - (kStreamVec - 1);
-}
-
-// Loads of 4 consecutive entries (16-byte aligned indices).
-typedef int v4i_t __attribute__((ext_vector_type(4)));
-typedef double v2d_t __attribute__((ext_vector_type(2)));
-typedef float v4f_t __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void load4(const int32_t* p, int (&c)[4]) {
-  const v4i_t v = __builtin_nontemporal_load(reinterpret_cast<const v4i_t*>(p));
-  c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
-}
-__device__ __forceinline__ void load4(const double* p, double (&c)[4]) {
-  const v2d_t a = __builtin_nontemporal_load(reinterpret_cast<const v2d_t*>(p));
-  const v2d_t b = __builtin_nontemporal_load(reinterpret_cast<const v2d_t*>(p) + 1);
-  c[0] = a.x; c[1] = a.y; c[2] = b.x; c[3] = b.y;
-}
-__device__ __forceinline__ void load4(const float* p, float (&c)[4]) {
-  const v4f_t v = __builtin_nontemporal_load(reinterpret_cast<const v4f_t*>(p));
-  c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
-}
 constexpr int kStreamMaxRows = 1024;  // rows per stream block
 
 // Stream variant.  Block vb covers rows [blk[vb], blk[vb+1]): either at most
-// kStreamMaxRows rows with at most stream_nnz<T>() entries, or a single longer
-// row.  Phase 1: every lane loads its share of the block's val/col (all loads
+// kStreamMaxRows rows with at most stream_nnz<T, NB>() entries, or a single
+// longer row.  Phase 1: every lane loads its share of the block's val/col (all loads
 // issued before any use; streamed with non-temporal hints so that L2 keeps x),
 // gathers x and stores the products in LDS.  Phase 2: G lanes per row sum the
 // row's products (strided, then a butterfly) and apply the epilogue.  The
 // block's dot-product partials go to partials[k * nparts + vb].  `prod` is the
-// caller's LDS buffer of stream_nnz<T>() + kBS entries.
-template <int G, class T, class Gth, class E>
+// caller's LDS buffer of at least stream_nnz<T, NB>() + kBS entries.
+template <int G, int NB, class T, class Gth, class E>
 __device__ __forceinline__ void stream_block(const CsrView<T>& A, const Gth& gather, const E& epi, int vb,
                                              double* partials, int nparts, T* prod) {
-  constexpr int NNZ = stream_nnz<T>();
+  constexpr int NNZ = stream_nnz<T, NB>();
   constexpr int PER = NNZ / kBS;
+  static_assert(PER * kBS == NNZ, "block entries must be a multiple of the workgroup size");
   const int r0 = A.blk[vb], r1 = A.blk[vb + 1];
   const int e0 = A.ptr[r0], e1 = A.ptr[r1];
   const int cnt = e1 - e0;
   const int tid = threadIdx.x;
   double d[E::K > 0 ? E::K : 1] = {};
-  if (cnt <= stream_cap<T>()) {
+  if (cnt <= NNZ) {
     if (cnt > 0) {
-      if constexpr (kStreamVec == 1) {
-        // All loads of a lane are issued before any is used, and nothing is
-        // predicated: surplus lanes re-read the block's last entry and park
-        // their product in the spare slots.
-        int c[PER];
-        T v[PER];
+      // All loads of a lane are issued before any is used, and nothing is
+      // predicated: surplus lanes re-read the block's last entry and park
+      // their product in the spare slots.
+      int c[PER];
+      T v[PER];
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-          const int e = min(e0 + k * kBS + tid, e1 - 1);
-          c[k] = __builtin_nontemporal_load(A.col + e);
-          v[k] = __builtin_nontemporal_load(A.val + e);
-        }
-        T x[PER];
+      for (int k = 0; k < PER; ++k) {
+        const int e = min(e0 + k * kBS + tid, e1 - 1);
+        c[k] = __builtin_nontemporal_load(A.col + e);
+        v[k] = __builtin_nontemporal_load(A.val + e);
+      }
+      T x[PER];
 #pragma unroll
-        for (int k = 0; k < PER; ++k) x[k] = gather(c[k]);
+      for (int k = 0; k < PER; ++k) x[k] = gather(c[k]);
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-          const int slot = k * kBS + tid;
-          prod[slot < cnt ? slot : NNZ + tid] = v[k] * x[k];
-        }
-      } else {
-        // Each lane loads 4 consecutive entries with 16-byte loads from a
-        // window aligned down to a multiple of 4; arrays are padded so the
-        // last window stays inside the allocation.
-        constexpr int PV = PER / 4;
-        const int a0 = e0 & ~3;
-        const int last = (e1 - 1) & ~3;
-        int c[PV][4];
-        T v[PV][4];
-#pragma unroll
-        for (int k = 0; k < PV; ++k) {
-          const int b = min(a0 + (k * kBS + tid) * 4, last);
-          load4(A.col + b, c[k]);
-          load4(A.val + b, v[k]);
-        }
-        T x[PV][4];
-#pragma unroll
-        for (int k = 0; k < PV; ++k)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) x[k][q] = gather(c[k][q]);
-#pragma unroll
-        for (int k = 0; k < PV; ++k) {
-          const int b = a0 + (k * kBS + tid) * 4;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int e = b + q;
-            prod[(e >= e0 && e < e1) ? e - e0 : NNZ + tid] = v[k][q] * x[k][q];
-          }
-        }
+      for (int k = 0; k < PER; ++k) {
+        const int slot = k * kBS + tid;
+        prod[slot < cnt ? slot : NNZ + tid] = v[k] * x[k];
       }
     }
     __syncthreads();
@@ -358,12 +305,12 @@ __device__ __forceinline__ void stream_block(const CsrView<T>& A, const Gth& gat
   if constexpr (E::K > 0) block_partials<E::K, kBS>(d, partials, nparts, vb);
 }
 
-template <int G, class T, class Gth, class E>
+template <int G, int NB, class T, class Gth, class E>
 static __global__ void __launch_bounds__(kBS) csr_stream_kernel(CsrView<T> A, Gth gather, E epi,
                                                          double* partials, const int* skip) {
   if (skip && *skip) return;
-  __shared__ T prod[stream_nnz<T>() + kBS];  // the last kBS slots take surplus lanes' products
-  stream_block<G>(A, gather, epi, xcd_remap(blockIdx.x, gridDim.x), partials, gridDim.x, prod);
+  __shared__ T prod[stream_nnz<T, NB>() + kBS];  // the last kBS slots take surplus lanes' products
+  stream_block<G, NB>(A, gather, epi, xcd_remap(blockIdx.x, gridDim.x), partials, gridDim.x, prod);
 }
 
 // Vector variant: L lanes per row, kBS / L rows per workgroup.
@@ -747,6 +694,7 @@ struct SpmvItem {
   double* partials;
   const int* skip;
   int lanes;
+  int small;  // 4 KB stream blocks
 };
 
 template <class T, class Gth, class E>
@@ -758,11 +706,16 @@ __global__ void __launch_bounds__(kBS) batched_spmv_kernel(const Batch<SpmvItem<
     const SpmvItem<T, Gth, E> it = B->it[i];
     if (!*it.skip) {
       const int vb = w - B->off[i], nb = B->off[i + 1] - B->off[i];
-      switch (it.lanes) {
-        case 1: stream_block<1>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 4: stream_block<4>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 16: stream_block<16>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        default: stream_block<64>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+      constexpr int NS = kStreamSmallBytes, NL = AMG_STREAM_BYTES;
+      switch (it.lanes * 2 + it.small) {
+        case 2: stream_block<1, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 3: stream_block<1, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 8: stream_block<4, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 9: stream_block<4, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 32: stream_block<16, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 33: stream_block<16, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 128: stream_block<64, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        default: stream_block<64, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
       }
     }
     __syncthreads();

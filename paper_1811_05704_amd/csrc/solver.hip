@@ -355,13 +355,18 @@ amg_status amg_csr_spmv(amg_matrix m, const void* x_dev, void* y_dev, void* hip_
   });
 }
 
-amg_status amg_csr_kernel_info(amg_matrix m, int32_t* kind, int32_t* lanes, int32_t* blocks) {
+amg_status amg_csr_kernel_info(amg_matrix m, int32_t* kind, int32_t* lanes, int32_t* blocks, int32_t* block_bytes) {
   return guarded([&]() -> amg_status {
     if (!m) throw SetupError{-1, "NULL matrix"};
     const bool f64 = m->precision == AMG_FP64;
     if (kind) *kind = f64 ? m->d64.kind : m->d32.kind;
     if (lanes) *lanes = f64 ? m->d64.lanes : m->d32.lanes;
     if (blocks) *blocks = f64 ? m->d64.nblocks : m->d32.nblocks;
+    if (block_bytes) {
+      const int k = f64 ? m->d64.kind : m->d32.kind;
+      const int sm = f64 ? m->d64.small : m->d32.small;
+      *block_bytes = k != 0 ? 0 : sm ? kStreamSmallBytes : AMG_STREAM_BYTES;
+    }
     return AMG_OK;
   });
 }

@@ -1,8 +1,9 @@
 """Device SpMV kernels vs a plain CPU product (GPU).
 
 Covers the SpMV variants the library selects by mean row length (LDS-staged
-stream blocks whose rows are reduced by G = 1, 4, 16 or 64 lanes, including
-rows longer than one LDS block; 64 lanes per row straight from memory for
+stream blocks of 4 KB or, for matrices with at least 32 MiB of values, 16 KB,
+whose rows are reduced by G = 1, 4, 16 or 64 lanes, including rows longer
+than one LDS block; 64 lanes per row straight from memory for
 very long rows), empty rows, a ragged tail, rectangular shapes, FP64 and
 FP32, and sampled rows of the full-size 150^3 Poisson operator.
 """
@@ -57,6 +58,9 @@ CASES = [
     ("stream_g64_300", 503, 5000, lambda r: r.integers(200, 401, 503)),
     ("stream_g64_mixed_long", 203, 20000, lambda r: np.where(np.arange(203) % 50 == 7, 6000, r.integers(200, 400, 203))),
     ("vector_long_rows", 300, 20000, lambda r: r.integers(1000, 9000, 300)),
+    # at least 32 MiB of values in both precisions: 16 KB stream blocks
+    ("large_blocks_g1", 1400000, 1400000, lambda r: r.integers(1, 13, 1400000)),
+    ("large_blocks_g4", 300000, 300000, lambda r: r.integers(20, 41, 300000)),
 ]
 
 
@@ -74,6 +78,8 @@ def test_spmv_matches_cpu(name, rows, cols, gen, precision):
     if info["kind"] == "stream":
         expect = 1 if mean <= 12 else 4 if mean <= 48 else 16 if mean <= 192 else 64
         assert info["lanes"] == expect
+        vbytes = int(rp[-1]) * (8 if precision == "fp64" else 4)
+        assert info["block_bytes"] == (16384 if vbytes >= 32 << 20 else 4096)
     # worst case grows with the row length (per-lane partial sums + a tree)
     tol = 5e-14 if precision == "fp64" else 2e-5
     err = np.abs(y - yr)
