@@ -26,5 +26,7 @@ from .sa_amg import (  # noqa: F401
     vcycle_fp32,
     pcg,
     bicgstab,
+    arnoldi_cgs2,
+    gmres,
     solve,
 )

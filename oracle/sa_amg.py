@@ -69,7 +69,7 @@ ISOLATED = -1
 class Params:
     """Method parameters (the paper's nested ``params``, section 3.1, flattened)."""
 
-    solver: str = "cg"  # "cg" | "bicgstab"
+    solver: str = "cg"  # "cg" | "bicgstab" | "gmres"
     relax: str = "spai0"  # "spai0" | "jacobi" | "chebyshev"
     eps_strong: float = 0.08  # strength threshold on level 1, halved per level
     jacobi_omega: float = 0.72
@@ -82,6 +82,7 @@ class Params:
     max_coarse: int = 20000  # a coarsest level above this is refused
     max_iter: int = 500
     tol: float = 1e-8
+    gmres_m: int = 30  # GMRES restart length
 
 
 @dataclass
@@ -587,6 +588,101 @@ def bicgstab(A, f, precond, tol=1e-8, max_iter=500, x0=None):
     return x, SolveInfo(it, rel, true_rel, converged and true_rel <= tol, restarts, hist)
 
 
+def arnoldi_cgs2(A, precond, V, j):
+    """One Arnoldi step of flexible GMRES from the orthonormal basis V[0..j]:
+    z = M v_j, w = A z, orthogonalised against every v_i by classical
+    Gram-Schmidt applied twice (Giraud, Langou and Rozloznik 2005).  Returns
+    (z, h, hn, w): the preconditioned vector, the coefficients h_i (the two
+    passes added), hn = ||w|| and w (not normalised)."""
+    z = precond(V[j])
+    w = A @ z
+    h = np.zeros(j + 1)
+    for _ in range(2):
+        c = np.array([float(V[i] @ w) for i in range(j + 1)])  # against the same w
+        for i in range(j + 1):
+            w = w - c[i] * V[i]
+        h = h + c
+    return z, h, float(np.sqrt(w @ w)), w
+
+
+def gmres(A, f, precond, m=30, tol=1e-8, max_iter=500, x0=None):
+    """Flexible restarted GMRES(m) (Saad 1993; Saad 2003, Alg. 9.6, restarted
+    as in section 6.5.5), Arnoldi by :func:`arnoldi_cgs2`, Givens rotations
+    for the least-squares problem.  The preconditioned vectors z_j = M v_j
+    are kept, so the update x += Z_k y is exact also when M is linear only up
+    to rounding (the FP32 V-cycle); for a fixed linear M this is right-
+    preconditioned GMRES (Saad 2003, Alg. 9.5).
+
+    One iteration is one Arnoldi step (one preconditioner application and
+    one product with A).  After each step the least-squares residual |g_{j+1}|
+    is tested against tol ||f||; a cycle ends on that test, on h_{j+1,j} = 0
+    or after m steps, and then x += Z_k y.  Every cycle starts from the true
+    residual f - A x, whose norm decides convergence, so a cycle whose
+    estimate met tol but whose true residual does not simply continues.
+    """
+    A = _as_csr(A)
+    f = np.asarray(f, dtype=np.float64)
+    x = np.zeros_like(f) if x0 is None else np.array(x0, dtype=np.float64)
+    nf = float(np.linalg.norm(f))
+    if nf == 0.0:
+        return np.zeros_like(f), SolveInfo(0, 0.0, 0.0, True)
+    it = 0
+    hist = []
+    cycles = 0
+    rel = 0.0
+    converged = False
+    while True:
+        r = f - A @ x
+        beta = float(np.sqrt(r @ r))
+        rel = beta / nf
+        if rel <= tol:
+            converged = True
+            break
+        if it >= max_iter:
+            break
+        cycles += 1
+        V = [r / beta]
+        Z = []
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        k = 0
+        for j in range(m):
+            z, h, hn, w = arnoldi_cgs2(A, precond, V, j)
+            Z.append(z)
+            H[: j + 1, j] = h
+            H[j + 1, j] = hn
+            for i in range(j):  # earlier rotations
+                a, b = H[i, j], H[i + 1, j]
+                H[i, j] = cs[i] * a + sn[i] * b
+                H[i + 1, j] = -sn[i] * a + cs[i] * b
+            a, b = H[j, j], H[j + 1, j]
+            d = float(np.sqrt(a * a + b * b))
+            cs[j], sn[j] = a / d, b / d
+            H[j, j], H[j + 1, j] = d, 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            k = j + 1
+            rel = abs(g[j + 1]) / nf
+            hist.append(rel)
+            if rel <= tol or hn == 0.0 or it >= max_iter:
+                break
+            V.append(w / hn)
+        y = np.zeros(k)  # back substitution, H[:k, :k] upper triangular
+        for i in range(k - 1, -1, -1):
+            s_ = g[i]
+            for c in range(i + 1, k):
+                s_ = s_ - H[i, c] * y[c]
+            y[i] = s_ / H[i, i]
+        for i in range(k):
+            x = x + y[i] * Z[i]
+    true_rel = float(np.linalg.norm(f - A @ x)) / nf
+    return x, SolveInfo(it, rel, true_rel, converged, max(cycles - 1, 0), hist)
+
+
 def solve(A, f, params: Params | None = None, mixed: bool = False, h: Hierarchy | None = None):
     """Setup (unless ``h`` is given) and AMG-preconditioned Krylov solve.
 
@@ -603,6 +699,9 @@ def solve(A, f, params: Params | None = None, mixed: bool = False, h: Hierarchy 
     else:
         def M(r):
             return vcycle(h, r)
-    krylov = pcg if prm.solver == "cg" else bicgstab
-    x, info = krylov(h.levels[0].A, f, M, tol=prm.tol, max_iter=prm.max_iter)
+    if prm.solver == "gmres":
+        x, info = gmres(h.levels[0].A, f, M, m=prm.gmres_m, tol=prm.tol, max_iter=prm.max_iter)
+    else:
+        krylov = pcg if prm.solver == "cg" else bicgstab
+        x, info = krylov(h.levels[0].A, f, M, tol=prm.tol, max_iter=prm.max_iter)
     return x, info, h

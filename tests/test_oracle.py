@@ -297,6 +297,9 @@ def _tiny_cases():
     out.append(("diffusion-bicg", 8, problems.diffusion3d(8, g), "bicgstab", "jacobi"))
     out.append(("convection", 8, problems.diffusion3d(8, g, velocity=(50.0, 25.0, 12.5)),
                 "bicgstab", "jacobi"))
+    out.append(("convection-gmres", 8, problems.diffusion3d(8, g, velocity=(50.0, 25.0, 12.5)),
+                "gmres", "jacobi"))
+    out.append(("poisson-gmres", 5, problems.poisson3d(5), "gmres", "spai0"))
     return out
 
 
@@ -420,3 +423,82 @@ def test_chebyshev_vcycle_symmetric_spd_linear_and_solve():
     z64 = oracle.vcycle(h, x)
     z32 = oracle.vcycle_fp32(h, x)
     assert 1e-10 < np.linalg.norm(z32 - z64) / np.linalg.norm(z64) < 1e-5
+
+
+# ------------------------------------------------------------------ GMRES
+
+
+def _nonsym_small(n=40, seed=7):
+    """Dense-backed nonsymmetric test matrix 3 I + B / sqrt(n), B Gaussian."""
+    rng = np.random.default_rng(seed)
+    return sp.csr_matrix(3.0 * np.eye(n) + rng.standard_normal((n, n)) / np.sqrt(n))
+
+
+def test_gmres_minimal_residual_over_krylov_space():
+    # k steps of one cycle minimise ||f - A x|| over x = M u, u in the Krylov
+    # space K_k(A M, f): compare with a dense least-squares problem on an
+    # orthonormal basis of that space (QR of [f, B f, ..., B^(k-1) f], B = A M)
+    A = _nonsym_small()
+    n = A.shape[0]
+    dM = 1.0 + np.random.default_rng(8).random(n)  # a fixed diagonal preconditioner
+    f = np.random.default_rng(9).standard_normal(n)
+    B = A.toarray() * dM[None, :]
+    nf = np.linalg.norm(f)
+    for k in range(1, 9):
+        x, info = oracle.gmres(A, f, lambda v: dM * v, m=50, tol=1e-300, max_iter=k)
+        assert info.iters == k
+        K = np.column_stack([np.linalg.matrix_power(B, i) @ f for i in range(k)])
+        Q, _ = np.linalg.qr(K)
+        c = np.linalg.lstsq(B @ Q, f, rcond=None)[0]
+        best = np.linalg.norm(f - B @ (Q @ c))
+        got = np.linalg.norm(f - A @ x)
+        assert abs(got - best) <= 1e-10 * nf, (k, got, best)
+        # the least-squares estimate of the last step is the true residual
+        assert abs(info.history[-1] - got / nf) <= 1e-11
+
+
+def test_gmres_arnoldi_relation_and_orthonormal_basis():
+    A = _nonsym_small()
+    n, k = A.shape[0], 10
+    dM = 1.0 + np.random.default_rng(8).random(n)
+    f = np.random.default_rng(10).standard_normal(n)
+    V, Z = [f / np.linalg.norm(f)], []
+    Hb = np.zeros((k + 1, k))
+    for j in range(k):
+        z, h, hn, w = oracle.arnoldi_cgs2(A, lambda v: dM * v, V, j)
+        np.testing.assert_array_equal(z, dM * V[j])
+        Z.append(z)
+        Hb[: j + 1, j] = h
+        Hb[j + 1, j] = hn
+        V.append(w / hn)
+    Vm, Zm = np.column_stack(V), np.column_stack(Z)
+    assert np.abs(Vm.T @ Vm - np.eye(k + 1)).max() <= 1e-14
+    assert np.abs(A @ Zm - Vm @ Hb).max() <= 1e-13 * np.abs(A).max()
+
+
+def test_gmres_finite_termination_and_restarts():
+    A = _nonsym_small(12, 3)
+    f = np.random.default_rng(4).standard_normal(12)
+    nf = np.linalg.norm(f)
+    x, info = oracle.gmres(A, f, lambda v: v, m=12, tol=1e-12, max_iter=100)
+    assert info.converged and info.iters <= 12 and info.restarts == 0
+    assert np.linalg.norm(f - A @ x) <= 1e-12 * nf
+    x3, info3 = oracle.gmres(A, f, lambda v: v, m=3, tol=1e-10, max_iter=500)
+    assert info3.converged and info3.restarts > 0
+    assert np.linalg.norm(f - A @ x3) <= 1e-10 * nf
+    # each cycle minimises over a space that holds the zero correction, so
+    # the residual never grows, also across restarts
+    hist = np.array(info3.history)
+    assert np.all(np.diff(hist) <= 1e-12)
+
+
+def test_flexible_gmres_exact_with_fp32_vcycle():
+    # the stored z_j make the update exact for the FP32 V-cycle: the solve
+    # reaches tol in one cycle, like the FP64 one
+    A = problems.poisson3d(16)
+    f = problems.rhs_uniform(A.n, 0)
+    x, info, h = oracle.solve(A, f, oracle.Params(solver="gmres"), mixed=True)
+    x64, info64, _ = oracle.solve(A, f, oracle.Params(solver="gmres"), h=h)
+    assert info.converged and info64.converged
+    assert info.restarts == 0 and info64.restarts == 0
+    assert abs(info.iters - info64.iters) <= 1

@@ -29,6 +29,8 @@ def _pins_fail(golden):
         lambda: pins.test_whole_solve_vs_dense(*pins._tiny_cases()[-1]),
         lambda: pins.test_vcycle_operator_symmetric_spd_linear("spai0"),
         lambda: pins.test_chebyshev_residual_polynomial_closed_form(3),
+        lambda: pins.test_gmres_minimal_residual_over_krylov_space(),
+        lambda: pins.test_gmres_arnoldi_relation_and_orthonormal_basis(),
     ]
     for chk in checks:
         try:
@@ -123,6 +125,18 @@ def _chebyshev_wrong_recurrence(A, dinv, f, x, hi, lo, degree):
     return x, r
 
 
+def _arnoldi_skips_last_vector(A, precond, V, j):
+    z = precond(V[j])
+    w = A @ z
+    h = np.zeros(j + 1)
+    for _ in range(2):
+        c = np.array([float(V[i] @ w) for i in range(j + 1)])
+        for i in range(j):  # wrong: v_j itself is not projected out
+            w = w - c[i] * V[i]
+        h = h + c
+    return z, h, float(np.sqrt(w @ w)), w
+
+
 _orig = {"filtered_matrix": sa.filtered_matrix, "prolongator_damping": sa.prolongator_damping}
 
 
@@ -135,6 +149,7 @@ MUTATIONS = {
     "post_sweep_sign": ("vcycle", _vcycle_wrong_sign),
     "restriction_tentative": ("vcycle", _vcycle_restrict_tentative),
     "chebyshev_recurrence_sign": ("chebyshev_sweep", _chebyshev_wrong_recurrence),
+    "arnoldi_skips_last_vector": ("arnoldi_cgs2", _arnoldi_skips_last_vector),
 }
 
 
