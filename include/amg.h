@@ -45,7 +45,7 @@ typedef enum {
   AMG_ERR_NAN = -9              /* non-finite value in the iteration         */
 } amg_status;
 
-enum { AMG_CG = 0, AMG_BICGSTAB = 1 };         /* Krylov method (section 3) */
+enum { AMG_CG = 0, AMG_BICGSTAB = 1, AMG_GMRES = 2 }; /* Krylov method (section 3) */
 enum { AMG_SPAI0 = 0, AMG_JACOBI = 1, AMG_CHEBYSHEV = 2 }; /* relaxation (section 3) */
 enum { AMG_FP64 = 0, AMG_MIXED = 1 };          /* value type of the V-cycle */
 
@@ -56,13 +56,19 @@ enum { AMG_FP64 = 0, AMG_MIXED = 1 };          /* value type of the V-cycle */
  * amg_params_default() fills: CG, SPAI-0, FP64, eps_strong 0.08 (halved on
  * every coarser level), jacobi_omega 0.72, npre = npost = 1, coarse_enough
  * 3000, max_levels 30, max_iter 500, tol 1e-8 (relative to ||f||_2),
- * use_graph 1, check_every 4, cheb_degree 3, cheb_ratio 30.
+ * use_graph 1, check_every 4, cheb_degree 3, cheb_ratio 30, gmres_m 30.
  * AMG_CHEBYSHEV is the diagonally scaled Chebyshev iteration (Saad 2003,
  * cited in section 3) of cheb_degree steps per sweep on [hi/cheb_ratio, hi],
- * hi the Gershgorin bound of D^-1 A_l; it needs npre, npost >= 1.
+ * hi the Gershgorin bound of D^-1 A_l.
+ * AMG_GMRES is flexible restarted GMRES(gmres_m) (Saad 2003, Alg. 9.6; the
+ * paper lists GMRES among its solvers in section 3) with Arnoldi by
+ * classical Gram-Schmidt applied twice; one iteration is one Arnoldi step,
+ * every cycle restarts from the true residual, and its kernels are launched
+ * directly (use_graph does not apply).  Its device memory grows by
+ * (2 gmres_m + 1) n doubles.
  */
 typedef struct {
-  int32_t solver;        /* AMG_CG | AMG_BICGSTAB                               */
+  int32_t solver;        /* AMG_CG | AMG_BICGSTAB | AMG_GMRES                   */
   int32_t relax;         /* AMG_SPAI0 | AMG_JACOBI | AMG_CHEBYSHEV              */
   int32_t precision;     /* AMG_FP64 | AMG_MIXED (FP32 V-cycle, FP64 Krylov)    */
   int32_t npre;          /* pre-relaxation sweeps per level (>= 0)              */
@@ -79,6 +85,7 @@ typedef struct {
                             (1..64)                                            */
   int32_t cheb_degree;   /* AMG_CHEBYSHEV: steps per sweep (1..16)              */
   double cheb_ratio;     /* AMG_CHEBYSHEV: upper / lower end of the interval   */
+  int32_t gmres_m;       /* AMG_GMRES: restart length m (1..64)                 */
 } amg_params;
 
 /* Optional device allocator; NULL everywhere means hipMalloc / hipFree. */

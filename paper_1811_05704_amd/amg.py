@@ -25,7 +25,7 @@ AMG_ERR = {
     -4: "AMG_ERR_SINGULAR_COARSE", -5: "AMG_ERR_OOM", -6: "AMG_ERR_HIP",
     -7: "AMG_ERR_BREAKDOWN", -8: "AMG_ERR_TOO_LARGE", -9: "AMG_ERR_NAN",
 }
-SOLVERS = {"cg": 0, "bicgstab": 1}
+SOLVERS = {"cg": 0, "bicgstab": 1, "gmres": 2}
 RELAX = {"spai0": 0, "jacobi": 1, "chebyshev": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 
@@ -43,7 +43,7 @@ class Params(C.Structure):
         ("max_levels", C.c_int32), ("max_iter", C.c_int32),
         ("eps_strong", C.c_double), ("jacobi_omega", C.c_double), ("tol", C.c_double),
         ("use_graph", C.c_int32), ("check_every", C.c_int32),
-        ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
+        ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double), ("gmres_m", C.c_int32),
     ]
 
 
@@ -134,7 +134,7 @@ def make_params(**kw) -> Params:
     """Defaults of ``amg_params_default`` overridden by keyword arguments.
 
     Accepts the names of the struct fields and string values for ``solver``
-    ("cg" | "bicgstab"), ``relax`` ("spai0" | "jacobi" | "chebyshev") and ``precision``
+    ("cg" | "bicgstab" | "gmres"), ``relax`` ("spai0" | "jacobi" | "chebyshev") and ``precision``
     ("fp64" | "mixed").
     """
     p = Params()

@@ -23,6 +23,7 @@ void amg_params_default(amg_params* p) {
   p->check_every = 4;
   p->cheb_degree = 3;
   p->cheb_ratio = 30.0;
+  p->gmres_m = 30;
 }
 
 const char* amg_last_error(void) { return g_last_error.c_str(); }

@@ -34,6 +34,7 @@
 
 #include "chebyshev.hpp"
 #include "device.hpp"
+#include "gmres.hpp"
 
 namespace amg {
 
@@ -364,6 +365,13 @@ struct amg_solver {
   double *f = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr;
   double *rt = nullptr, *v = nullptr, *phat = nullptr, *s = nullptr, *shat = nullptr, *t = nullptr;
 
+  // flexible GMRES: bases V ((m+1) x ld) and Z (m x ld), state, partials
+  double *gmV = nullptr, *gmZ = nullptr, *gm_partials = nullptr;
+  amg::GState* gm = nullptr;
+  int32_t* gm_host = nullptr;  // pinned mirror of GState::k, GState::stop
+  int64_t gm_ld = 0;
+  int gm_nb = 0;
+
   hipGraphExec_t iter_exec = nullptr;
   hipGraph_t iter_graph = nullptr;
 
@@ -371,6 +379,7 @@ struct amg_solver {
     if (iter_exec) (void)hipGraphExecDestroy(iter_exec);
     if (iter_graph) (void)hipGraphDestroy(iter_graph);
     if (st_host) (void)hipHostFree(st_host);
+    if (gm_host) (void)hipHostFree(gm_host);
     arena.reset();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
@@ -389,7 +398,10 @@ inline SetupParams setup_params(const amg_params& p) {
 }
 
 inline void check_params(const amg_params& p) {
-  if (p.solver != AMG_CG && p.solver != AMG_BICGSTAB) throw SetupError{-1, "solver must be AMG_CG or AMG_BICGSTAB"};
+  if (p.solver != AMG_CG && p.solver != AMG_BICGSTAB && p.solver != AMG_GMRES)
+    throw SetupError{-1, "solver must be AMG_CG, AMG_BICGSTAB or AMG_GMRES"};
+  if (p.solver == AMG_GMRES && (p.gmres_m < 1 || p.gmres_m > kMaxGmresM))
+    throw SetupError{-1, "gmres_m must be in [1, 64]"};
   if (p.relax != AMG_SPAI0 && p.relax != AMG_JACOBI && p.relax != AMG_CHEBYSHEV)
     throw SetupError{-1, "relax must be AMG_SPAI0, AMG_JACOBI or AMG_CHEBYSHEV"};
   if (p.relax == AMG_CHEBYSHEV) {
@@ -646,6 +658,91 @@ inline KState poll(amg_solver& S, hipStream_t s) {
   return *S.st_host;
 }
 
+// ------------------------------------------------------------------ GMRES
+
+// r = f - A x and the opening of a cycle (first: the initial residual).
+inline void enqueue_gm_cycle_start(amg_solver& S, bool first, hipStream_t s) {
+  const int n = static_cast<int>(S.n);
+  int nb = launch_spmv(S.A0, GatherX<double, double>{S.x}, EpiResidNorms{S.r, S.f}, S.partials,
+                       first ? nullptr : skip_of(S), s);
+  gm_start_state_kernel<<<1, kFinBS, 0, s>>>(S.partials, nb, S.st, S.gm, first ? 1 : 0);
+  AMG_LAUNCHED();
+  gm_first_vector_kernel<<<vec_blocks(n), kVecBS, 0, s>>>(n, S.gmV, S.r, S.gm);
+  AMG_LAUNCHED();
+}
+
+// Arnoldi step j: z_j = M v_j, w = A z_j, two Gram-Schmidt passes, rotation,
+// v_{j+1} = w / ||w||.  Every kernel returns at once once the cycle stopped.
+inline void enqueue_gm_step(amg_solver& S, int j, hipStream_t s) {
+  const int n = static_cast<int>(S.n);
+  const int64_t ld = S.gm_ld;
+  double* vj = S.gmV + j * ld;
+  double* zj = S.gmZ + j * ld;
+  double* w = S.q;
+  const int* stop = &S.gm->stop;
+  with_vcycle(S, [&](auto& V) { return V.template run<0>(vj, zj, S.partials, stop, s); });
+  launch_spmv(S.A0, GatherX<double, double>{zj}, EpiStore<double, double>{w}, nullptr, stop, s);
+  const int nb = S.gm_nb;
+  for (int pass = 0; pass < 2; ++pass) {
+    gm_dots_kernel<<<dim3(nb, j + 1), kVecBS, 0, s>>>(n, S.gmV, ld, w, S.gm_partials, S.gm);
+    AMG_LAUNCHED();
+    gm_sum_kernel<<<j + 1, kFinBS, 0, s>>>(S.gm_partials, nb, S.gm, pass);
+    AMG_LAUNCHED();
+    if (pass == 0)
+      gm_subtract_kernel<0><<<nb, kVecBS, 0, s>>>(n, j + 1, S.gmV, ld, w, nullptr, S.gm);
+    else
+      gm_subtract_kernel<1><<<nb, kVecBS, 0, s>>>(n, j + 1, S.gmV, ld, w, S.gm_partials, S.gm);
+    AMG_LAUNCHED();
+  }
+  gm_givens_kernel<<<1, kFinBS, 0, s>>>(S.gm_partials, nb, S.gm, S.st, j, S.prm.gmres_m);
+  AMG_LAUNCHED();
+  gm_scale_kernel<<<vec_blocks(n), kVecBS, 0, s>>>(n, S.gmV + (j + 1) * ld, w, S.gm);
+  AMG_LAUNCHED();
+}
+
+// End of a cycle: y = R^-1 g, x += Z y, then the next cycle's start.
+inline void enqueue_gm_cycle_end(amg_solver& S, hipStream_t s) {
+  const int n = static_cast<int>(S.n);
+  gm_solve_kernel<<<1, 64, 0, s>>>(S.gm, S.st);
+  AMG_LAUNCHED();
+  gm_update_kernel<<<vec_blocks(n), kVecBS, 0, s>>>(n, S.x, S.gmZ, S.gm_ld, S.gm, S.st);
+  AMG_LAUNCHED();
+  enqueue_gm_cycle_start(S, false, s);
+}
+
+// Krylov state and the cycle's stop flag, read after the stream drains.
+inline KState gm_poll(amg_solver& S, hipStream_t s, int32_t* stop) {
+  AMG_HIP(hipMemcpyAsync(S.st_host, S.st, sizeof(KState), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipMemcpyAsync(S.gm_host, &S.gm->k, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  *stop = S.gm_host[1];
+  return *S.st_host;
+}
+
+// The whole GMRES solve with direct launches; the host polls every
+// check_every Arnoldi steps and at the end of each cycle.  Returns the final
+// state and the number of cycles run.
+inline KState run_gmres(amg_solver& S, hipStream_t s, int* cycles) {
+  int32_t stop = 0;
+  enqueue_gm_cycle_start(S, true, s);
+  KState k = gm_poll(S, s, &stop);
+  *cycles = 0;
+  const int m = S.prm.gmres_m;
+  while (k.done == kRunning) {
+    ++*cycles;
+    for (int j = 0; j < m; ++j) {
+      enqueue_gm_step(S, j, s);
+      if ((j + 1) % S.prm.check_every == 0 || j == m - 1) {
+        k = gm_poll(S, s, &stop);
+        if (stop) break;
+      }
+    }
+    enqueue_gm_cycle_end(S, s);
+    k = gm_poll(S, s, &stop);
+  }
+  return k;
+}
+
 inline amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, hipStream_t s, amg_info* info) {
   const double t0 = now_s();
   const int n = static_cast<int>(S.n);
@@ -658,11 +755,21 @@ inline amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, h
   init.first = 1;
   *S.st_host = init;
   AMG_HIP(hipMemcpyAsync(S.st, S.st_host, sizeof(KState), hipMemcpyHostToDevice, s));
-  if (S.prm.use_graph) build_graph(S);
+  if (S.prm.use_graph && S.prm.solver != AMG_GMRES) build_graph(S);
 
   int restarts = 0;
   KState k{};
-  for (;;) {
+  if (S.prm.solver == AMG_GMRES) {
+    int cycles = 0;
+    k = run_gmres(S, s, &cycles);
+    restarts = std::max(cycles - 1, 0);
+    if (k.done != kZeroRhs) {
+      int nb = launch_spmv(S.A0, GatherX<double, double>{S.x}, EpiResidNorms{S.tmp, S.f}, S.partials, nullptr, s);
+      fin(S, 2, nb, kFinTrue, s);
+      k = poll(S, s);
+    }
+  }
+  for (; S.prm.solver != AMG_GMRES;) {
     if (S.prm.solver == AMG_CG) enqueue_pcg_start(S, s);
     else enqueue_bicg_start(S, s);
     k = poll(S, s);
@@ -757,6 +864,17 @@ inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t 
   S.p = ar.get<double>(n);
   S.q = ar.get<double>(n);
   S.tmp = ar.get<double>(n);
+  if (S.prm.solver == AMG_GMRES) {
+    const int m = S.prm.gmres_m;
+    S.gm_ld = (n + 31) & ~int64_t(31);  // 256-byte aligned basis vectors
+    S.gmV = ar.get<double>(static_cast<size_t>(m + 1) * S.gm_ld);
+    S.gmZ = ar.get<double>(static_cast<size_t>(m) * S.gm_ld);
+    S.gm = ar.get<GState>(1);
+    S.gm_nb = static_cast<int>(std::min<int64_t>(vec_blocks(n), kGmDotBlocks));
+    S.gm_partials = ar.get<double>(static_cast<size_t>(m + 1) * S.gm_nb);
+    if (opts.standalone)
+      AMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.gm_host), 2 * sizeof(int32_t), hipHostMallocDefault));
+  }
   if (S.prm.solver == AMG_BICGSTAB) {
     S.rt = ar.get<double>(n);
     S.v = ar.get<double>(n);

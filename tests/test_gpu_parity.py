@@ -49,7 +49,7 @@ def _problem(name):
 
 def _oracle_params(kw):
     keys = ("solver", "relax", "npre", "npost", "coarse_enough", "max_iter", "tol", "max_levels",
-            "cheb_degree", "cheb_ratio")
+            "cheb_degree", "cheb_ratio", "gmres_m")
     return oracle.Params(**{k: v for k, v in kw.items() if k in keys})
 
 
@@ -149,6 +149,13 @@ SOLVE_CASES = [
     ("poisson32", "uniform", {"relax": "chebyshev"}),
     ("diffusion24", "ones", {"relax": "chebyshev", "precision": "mixed"}),
     ("diffusion24", "ones", {"relax": "chebyshev", "solver": "bicgstab"}),
+    # flexible GMRES(m)
+    ("poisson32", "uniform", {"solver": "gmres"}),
+    ("convection24", "ones", {"solver": "gmres"}),
+    ("convection24", "ones", {"solver": "gmres", "precision": "mixed"}),
+    ("convection24", "ones", {"solver": "gmres", "gmres_m": 4}),
+    ("diffusion24", "ones", {"solver": "gmres", "gmres_m": 2}),
+    ("diffusion24", "uniform", {"solver": "gmres", "relax": "chebyshev", "check_every": 1}),
 ]
 
 
@@ -208,9 +215,10 @@ def test_solve_with_coarsest_order_895():
         S.release()
 
 
-def test_zero_rhs_gives_zero():
+@pytest.mark.parametrize("solver", ["cg", "bicgstab", "gmres"])
+def test_zero_rhs_gives_zero(solver):
     A, _ = _problem("poisson20")
-    S = amg.Solver(A)
+    S = amg.Solver(A, solver=solver)
     x, info = S.solve(dev(np.zeros(A.n)), x0=dev(np.ones(A.n)))
     assert info["iters"] == 0 and info["status"] == 0
     assert not host(x).any()
@@ -219,7 +227,7 @@ def test_zero_rhs_gives_zero():
 
 def test_single_level_is_exact():
     A = problems.poisson3d(10)
-    for solver in ("cg", "bicgstab"):
+    for solver in ("cg", "bicgstab", "gmres"):
         S = amg.Solver(A, solver=solver)
         assert S.nlevels == 1
         f = problems.rhs_ones(A.n)
@@ -229,21 +237,23 @@ def test_single_level_is_exact():
         S.release()
 
 
-def test_exact_initial_guess_needs_no_iteration():
+@pytest.mark.parametrize("solver", ["cg", "gmres"])
+def test_exact_initial_guess_needs_no_iteration(solver):
     A, _ = _problem("poisson20")
     f = problems.rhs_ones(A.n)
     xs = np.linalg.solve(A.to_scipy().toarray(), f)
-    S = amg.Solver(A)
+    S = amg.Solver(A, solver=solver)
     x, info = S.solve(dev(f), x0=dev(xs))
     assert info["iters"] == 0 and info["status"] == 0
     S.release()
 
 
-def test_iteration_limit_reports_not_converged():
+@pytest.mark.parametrize("solver,limit", [("cg", 1), ("gmres", 1), ("gmres", 3)])
+def test_iteration_limit_reports_not_converged(solver, limit):
     A, _ = _problem("poisson32")
-    S = amg.Solver(A, max_iter=1)
-    x, info = S.solve(dev(problems.rhs_ones(A.n)))
-    assert info["status"] == amg.AMG_NOT_CONVERGED and info["iters"] == 1
+    S = amg.Solver(A, max_iter=limit, solver=solver)
+    x, info = S.solve(dev(problems.rhs_ones(A.n)), raise_on_error=False)
+    assert info["status"] == amg.AMG_NOT_CONVERGED and info["iters"] == limit
     S.release()
 
 
@@ -326,7 +336,7 @@ def test_full_size_poisson150(precision):
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("variant", ["sym-cg-spai0", "sym-bicgstab-jacobi", "nonsym-bicgstab-jacobi",
-                                     "sym-cg-chebyshev"])
+                                     "sym-cg-chebyshev", "nonsym-gmres-jacobi"])
 def test_full_size_diffusion128(variant):
     """128^3 variable-coefficient diffusion, k = exp(g), sigma 2, length 8
     (field seed 1), f = 1; the nonsymmetric form adds upwind convection
