@@ -113,14 +113,14 @@ struct DevCsr {
   T* val = nullptr;
   int kind = 0;   // 0 stream, 1 vector
   int lanes = 1;  // lanes per row (stream: in the LDS reduction phase)
-  int small = 0;  // stream: 4 KB blocks instead of 16 KB
+  int bclass = 0;  // stream block size class: 0 = 16 KB, 1 = 4 KB, 2 = 8 KB
   int32_t nblocks = 0;
   int32_t* blk = nullptr;
   CsrView<T> view() const { return CsrView<T>{ptr, col, val, blk, rows, nblocks}; }
 };
 
 struct Schedule {
-  int kind = 0, lanes = 1, small = 0;
+  int kind = 0, lanes = 1, bclass = 0;
   std::vector<int32_t> blk;
   int32_t nblocks = 0;
 };
@@ -139,9 +139,12 @@ Schedule make_schedule(const Csr& M, int force_kind = -1) {
   const double mean = rows ? double(M.nnz()) / double(rows) : 0.0;
   s.kind = force_kind >= 0 ? force_kind : (mean <= kVectorMinMean ? 0 : 1);
   if (s.kind == 0) {
-    s.small = M.nnz() * static_cast<int64_t>(sizeof(T)) < kStreamSmallMatrix;
-    const int64_t cap = s.small ? stream_nnz<T, kStreamSmallBytes>() : stream_nnz<T>();
     s.lanes = stream_lanes(mean);
+    if (M.nnz() * static_cast<int64_t>(sizeof(T)) < kStreamSmallMatrix) s.bclass = 1;
+    else if (s.lanes == 1 && sizeof(T) == 8) s.bclass = 2;
+    const int64_t cap = s.bclass == 1   ? stream_nnz<T, kStreamSmallBytes>()
+                        : s.bclass == 2 ? stream_nnz<T, kStreamMidBytes>()
+                                        : stream_nnz<T>();
     s.blk.push_back(0);
     int64_t r = 0;
     while (r < rows) {
@@ -187,7 +190,7 @@ DevCsr<T> upload_csr(DevArena& ar, const Csr& M, int force_kind = -1) {
   Schedule s = make_schedule<T>(M, force_kind);
   d.kind = s.kind;
   d.lanes = s.lanes;
-  d.small = s.small;
+  d.bclass = s.bclass;
   d.nblocks = s.nblocks;
   if (s.kind == 0) d.blk = ar.upload(s.blk.data(), s.blk.size());
   // upload uses pageable host buffers: finish before they go out of scope
@@ -201,17 +204,18 @@ template <class T, class G, class E>
 int launch_spmv(const DevCsr<T>& M, G g, E e, double* partials, const int* skip, hipStream_t s) {
   if (M.rows == 0) return 0;
   if (M.kind == 0) {
-    constexpr int NS = kStreamSmallBytes, NL = AMG_STREAM_BYTES;
+    constexpr int NS = kStreamSmallBytes, NM = kStreamMidBytes, NL = AMG_STREAM_BYTES;
     const CsrView<T> A = M.view();
     const int n = M.nblocks;
-    switch (M.lanes * 2 + M.small) {
-      case 2: csr_stream_kernel<1, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 3: csr_stream_kernel<1, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 8: csr_stream_kernel<4, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 9: csr_stream_kernel<4, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 32: csr_stream_kernel<16, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 33: csr_stream_kernel<16, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 128: csr_stream_kernel<64, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+    switch (M.lanes * 4 + M.bclass) {
+      case 4: csr_stream_kernel<1, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 5: csr_stream_kernel<1, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 6: csr_stream_kernel<1, NM, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 16: csr_stream_kernel<4, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 17: csr_stream_kernel<4, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 64: csr_stream_kernel<16, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 65: csr_stream_kernel<16, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 256: csr_stream_kernel<64, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
       default: csr_stream_kernel<64, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
     }
   } else {

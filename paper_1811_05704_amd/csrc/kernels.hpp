@@ -225,11 +225,15 @@ struct EpiSmooth {
 // kStreamSmallBytes (4 KB) for matrices below kStreamSmallMatrix bytes of
 // values, where the larger blocks would leave too few workgroups to hide
 // memory latency (measured on the level matrices of the 150^3 hierarchy:
-// 15-40% faster below 32 MB, no gain above).
+// 15-40% faster below 32 MB, no gain above).  Large FP64 matrices reduced by
+// one lane per row use kStreamMidBytes (8 KB): their ~146 rows per block fit
+// one pass of the 256 threads (3-4% faster than 16 KB on the 7-point and
+// prolongation matrices).
 #ifndef AMG_STREAM_BYTES
 #define AMG_STREAM_BYTES 16384
 #endif
 constexpr int kStreamSmallBytes = 4096;
+constexpr int kStreamMidBytes = 8192;
 constexpr int64_t kStreamSmallMatrix = int64_t(32) << 20;
 
 template <class T, int NB = AMG_STREAM_BYTES>
@@ -694,7 +698,7 @@ struct SpmvItem {
   double* partials;
   const int* skip;
   int lanes;
-  int small;  // 4 KB stream blocks
+  int bclass;  // stream block size class: 0 = 16 KB, 1 = 4 KB, 2 = 8 KB
 };
 
 template <class T, class Gth, class E>
@@ -706,15 +710,16 @@ __global__ void __launch_bounds__(kBS) batched_spmv_kernel(const Batch<SpmvItem<
     const SpmvItem<T, Gth, E> it = B->it[i];
     if (!*it.skip) {
       const int vb = w - B->off[i], nb = B->off[i + 1] - B->off[i];
-      constexpr int NS = kStreamSmallBytes, NL = AMG_STREAM_BYTES;
-      switch (it.lanes * 2 + it.small) {
-        case 2: stream_block<1, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 3: stream_block<1, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 8: stream_block<4, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 9: stream_block<4, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 32: stream_block<16, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 33: stream_block<16, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 128: stream_block<64, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+      constexpr int NS = kStreamSmallBytes, NM = kStreamMidBytes, NL = AMG_STREAM_BYTES;
+      switch (it.lanes * 4 + it.bclass) {
+        case 4: stream_block<1, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 5: stream_block<1, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 6: stream_block<1, NM>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 16: stream_block<4, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 17: stream_block<4, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 64: stream_block<16, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 65: stream_block<16, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 256: stream_block<64, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         default: stream_block<64, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
       }
     }

@@ -173,7 +173,7 @@ void batch_add(Batch<Item>& b, const Item& it, int blocks) {
 
 template <class T, class G, class E>
 SpmvItem<T, G, E> spmv_item(const DevCsr<T>& M, G g, E e, double* partials, const int* skip) {
-  return SpmvItem<T, G, E>{M.view(), g, e, partials, skip, M.lanes, M.small};
+  return SpmvItem<T, G, E>{M.view(), g, e, partials, skip, M.lanes, M.bclass};
 }
 
 template <class T, class G, class E>

@@ -365,8 +365,8 @@ amg_status amg_csr_kernel_info(amg_matrix m, int32_t* kind, int32_t* lanes, int3
     if (blocks) *blocks = f64 ? m->d64.nblocks : m->d32.nblocks;
     if (block_bytes) {
       const int k = f64 ? m->d64.kind : m->d32.kind;
-      const int sm = f64 ? m->d64.small : m->d32.small;
-      *block_bytes = k != 0 ? 0 : sm ? kStreamSmallBytes : AMG_STREAM_BYTES;
+      const int bc = f64 ? m->d64.bclass : m->d32.bclass;
+      *block_bytes = k != 0 ? 0 : bc == 1 ? kStreamSmallBytes : bc == 2 ? kStreamMidBytes : AMG_STREAM_BYTES;
     }
     return AMG_OK;
   });

@@ -1,7 +1,7 @@
 """Device SpMV kernels vs a plain CPU product (GPU).
 
 Covers the SpMV variants the library selects by mean row length (LDS-staged
-stream blocks of 4 KB or, for matrices with at least 32 MiB of values, 16 KB,
+stream blocks of 4 KB or, for matrices with at least 32 MiB of values, 8 or 16 KB,
 whose rows are reduced by G = 1, 4, 16 or 64 lanes, including rows longer
 than one LDS block; 64 lanes per row straight from memory for
 very long rows), empty rows, a ragged tail, rectangular shapes, FP64 and
@@ -79,7 +79,10 @@ def test_spmv_matches_cpu(name, rows, cols, gen, precision):
         expect = 1 if mean <= 12 else 4 if mean <= 48 else 16 if mean <= 192 else 64
         assert info["lanes"] == expect
         vbytes = int(rp[-1]) * (8 if precision == "fp64" else 4)
-        assert info["block_bytes"] == (16384 if vbytes >= 32 << 20 else 4096)
+        if vbytes < 32 << 20:
+            assert info["block_bytes"] == 4096
+        else:
+            assert info["block_bytes"] == (8192 if expect == 1 and precision == "fp64" else 16384)
     # worst case grows with the row length (per-lane partial sums + a tree)
     tol = 5e-14 if precision == "fp64" else 2e-5
     err = np.abs(y - yr)
