@@ -428,7 +428,7 @@ std::vector<double> smoother_diagonal(const Csr& A, const SetupParams& prm) {
 
 }  // namespace
 
-HostHierarchy build_hierarchy(Csr A, const SetupParams& prm) {
+HostHierarchy build_hierarchy(Csr A, const SetupParams& prm, const GalerkinFn& galerkin) {
   HostHierarchy H;
   while (true) {
     const int64_t n = A.rows;
@@ -445,8 +445,8 @@ HostHierarchy build_hierarchy(Csr A, const SetupParams& prm) {
     L.R = transpose(L.P);
     L.m = smoother_diagonal(A, prm);
     if (prm.relax == 2) L.cheb_hi = gershgorin_dinv(A);
-    Csr AP = spgemm(A, L.P);
-    Csr Ac = spgemm(L.R, AP);
+    Csr Ac;
+    if (!galerkin || !galerkin(L.R, A, L.P, Ac)) Ac = spgemm(L.R, spgemm(A, L.P));
     L.agg = std::move(agg);
     L.A = std::move(A);
     H.levels.push_back(std::move(L));

@@ -5,6 +5,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -52,8 +53,13 @@ void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const doubl
 // Limit the worker threads the setup of the calling thread uses (0 = default).
 void set_setup_threads(int n);
 
-// Full hierarchy; throws SetupError.
-HostHierarchy build_hierarchy(Csr A, const SetupParams& prm);
+// Galerkin product A_c = R (A P) of one level.  Must give exactly what
+// spgemm(R, spgemm(A, P)) gives; may return false to leave it to the host.
+using GalerkinFn = std::function<bool(const Csr& R, const Csr& A, const Csr& P, Csr& Ac)>;
+
+// Full hierarchy; throws SetupError.  `galerkin` (optional) forms the
+// Galerkin products elsewhere (on the device).
+HostHierarchy build_hierarchy(Csr A, const SetupParams& prm, const GalerkinFn& galerkin = nullptr);
 
 // Steps, exposed for tests of the host logic.
 struct Graph {

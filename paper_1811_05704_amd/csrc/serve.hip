@@ -21,6 +21,7 @@
 #include <thread>
 #include <unordered_map>
 
+#include "galerkin.hpp"
 #include "solver.hpp"
 
 namespace amg {
@@ -370,6 +371,53 @@ void capture_graph(amg_server_s& V, int depth) {
 }
 
 // Host worker: build the hierarchy, place it in the pool, upload f.
+// Allocator for setup temporaries (the Galerkin products): memory from the
+// pool, reserved against the budget without waiting.  An allocation the
+// unreserved budget cannot cover fails at once, and that product is then
+// formed on the host; so no worker waits for memory while holding some.
+class TransientAlloc {
+ public:
+  explicit TransientAlloc(amg_server_s* V) : V_(V) {}
+  amg_allocator handle() { return amg_allocator{&TransientAlloc::alloc_cb, &TransientAlloc::free_cb, this}; }
+
+ private:
+  static void* alloc_cb(size_t bytes, void*, void* ctx) {
+    auto* t = static_cast<TransientAlloc*>(ctx);
+    amg_server_s* V = t->V_;
+    bytes = (bytes + 255) & ~size_t(255);
+    {
+      std::lock_guard<std::mutex> lk(V->mu);
+      if (V->reserved + bytes > V->pool->size()) return nullptr;
+      V->reserved += bytes;
+    }
+    void* p = V->pool->alloc(bytes);
+    if (!p) {
+      t->release(bytes);
+      return nullptr;
+    }
+    t->sizes_[p] = bytes;
+    return p;
+  }
+  static void free_cb(void* p, void*, void* ctx) {
+    auto* t = static_cast<TransientAlloc*>(ctx);
+    auto it = t->sizes_.find(p);
+    if (it == t->sizes_.end()) return;
+    const size_t bytes = it->second;
+    t->sizes_.erase(it);
+    t->V_->pool->free(p);
+    t->release(bytes);
+  }
+  void release(size_t bytes) {
+    {
+      std::lock_guard<std::mutex> lk(V_->mu);
+      V_->reserved -= bytes;
+    }
+    V_->cv_mem.notify_all();
+  }
+  amg_server_s* V_;
+  std::unordered_map<void*, size_t> sizes_;  // used by one worker thread only
+};
+
 void worker_main(amg_server_s* V, int threads) {
   set_setup_threads(threads);
   (void)hipSetDevice(V->device);
@@ -397,7 +445,17 @@ void worker_main(amg_server_s* V, int threads) {
       q->S = std::make_unique<amg_solver>();
       amg_solver& S = *q->S;
       S.prm = V->prm;
-      S.host = build_hierarchy(std::move(q->A), setup_params(V->prm));
+      TransientAlloc scratch(V);
+      const amg_allocator scratch_alloc = scratch.handle();
+      GalerkinFn galerkin = [&](const Csr& R, const Csr& A, const Csr& P, Csr& Ac) {
+        try {
+          return device_galerkin(R, A, P, Ac, &scratch_alloc, ws);
+        } catch (const DevError& e) {
+          if (e.code == AMG_ERR_OOM) return false;
+          throw;
+        }
+      };
+      S.host = build_hierarchy(std::move(q->A), setup_params(V->prm), galerkin);
       if (S.host.levels.size() < 2) throw SetupError{-1, "served systems need at least two levels"};
       if (S.host.levels.size() > static_cast<size_t>(kMaxLevels))
         throw SetupError{-8, "hierarchy deeper than the serving limit"};

@@ -215,6 +215,27 @@ def test_solve_with_coarsest_order_895():
         S.release()
 
 
+@pytest.mark.parametrize("name", ["poisson32", "diffusion24", "convection24", "convection40"])
+def test_device_galerkin_matches_host_setup(name):
+    """The device setup forms the Galerkin products on the GPU; every level
+    must be bit-identical to the host setup's (same products, same order)."""
+    if name == "convection40":
+        g = problems.gaussian_field(40, 2.0, 8.0, 3)
+        A, kw = problems.diffusion3d(40, g, velocity=(50.0, 25.0, 12.5)), {"relax": "jacobi"}
+    else:
+        A, kw = _problem(name)
+    S = amg.Solver(A, **kw)
+    H = amg.HostHierarchy(A, **kw)
+    announce("device galerkin", name, "levels", S.nlevels)
+    assert S.nlevels == H.nlevels >= 2
+    for l in range(S.nlevels):
+        Ad, Ah = S.level_scipy(l, "A"), H.level_scipy(l, "A")
+        assert np.array_equal(Ad.indptr, Ah.indptr) and np.array_equal(Ad.indices, Ah.indices)
+        assert np.array_equal(Ad.data, Ah.data), l
+    S.release()
+    H.release()
+
+
 @pytest.mark.parametrize("solver", ["cg", "bicgstab", "gmres"])
 def test_zero_rhs_gives_zero(solver):
     A, _ = _problem("poisson20")
@@ -318,6 +339,9 @@ def test_full_size_poisson150(precision):
     assert S.nlevels == h.nlevels
     for l in range(S.nlevels - 1):
         assert np.array_equal(S.aggregates(l), h.levels[l].agg)
+    # coarse operators from the device Galerkin products: equal to the oracle's
+    for l in range(1, S.nlevels):
+        assert abs(S.level_scipy(l, "A") - h.levels[l].A).max() == 0.0, l
     announce("full size 150^3 vcycle", precision)
     z = host(S.vcycle(dev(f)))
     if precision == "fp64":
