@@ -1,4 +1,5 @@
-// Galerkin products on the device (section 2, "AMG setup": A_{l+1} = R_l A_l P_l).
+// Setup steps on the device (section 2, "AMG setup"): the Galerkin products
+// A_{l+1} = R_l A_l P_l, the smoothed prolongator and the strength graph.
 //
 // C = A B by expansion and sort, one workgroup per block of consecutive rows
 // of A holding at most kGCap products:
@@ -12,11 +13,15 @@
 //      product.
 // A symbolic pass counts the distinct columns of every row (C's row
 // pointers); the numeric pass writes C in place.
+//
+// The same product forms the smoothed prolongator: P = P_hat - omega D_F^-1
+// (A_F P_hat), where A_F P_hat sums, in column order, the filtered entries of
+// a row by aggregate, which is what the host does.  The strength graph is a
+// per-entry test; only the greedy aggregation (sequential by its definition),
+// the transpose and the smoother diagonal stay on the host.
 
 #include <rocprim/block/block_radix_sort.hpp>
 #include <rocprim/block/block_scan.hpp>
-
-#include <climits>
 
 #include "device.hpp"
 #include "galerkin.hpp"
@@ -217,8 +222,8 @@ DMat upload_mat(DevArena& ar, const Csr& M, hipStream_t s) {
 
 // C = A B with A's host row pointers (Ahost) for the block schedule; C's row
 // pointers are returned on the host too.  False: a row does not fit a block.
-bool spgemm_dev(DevArena& ar, const std::vector<int64_t>& Aptr_host, const DMat& A, const DMat& B, DMat& C,
-                std::vector<int64_t>& Cptr, hipStream_t s) {
+bool spgemm_dev(DevArena& ar, DevArena& out, const std::vector<int64_t>& Aptr_host, const DMat& A, const DMat& B,
+                DMat& C, std::vector<int64_t>& Cptr, hipStream_t s) {
   const int colbits = bits_for(B.cols);
   if (colbits > kGMaxColBits) return false;
   const int m = A.rows;
@@ -250,9 +255,9 @@ bool spgemm_dev(DevArena& ar, const std::vector<int64_t>& Aptr_host, const DMat&
   const int nb = static_cast<int>(blk.size()) - 1;
   if (nb <= 0) {
     C.nnz = 0;
-    C.ptr = ar.get<int32_t>(m + 1);
-    C.col = ar.get<int32_t>(1);
-    C.val = ar.get<double>(1);
+    C.ptr = out.get<int32_t>(m + 1);
+    C.col = out.get<int32_t>(1);
+    C.val = out.get<double>(1);
     std::vector<int32_t> z(m + 1, 0);
     AMG_HIP(hipMemcpyAsync(C.ptr, z.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, s));
     AMG_HIP(hipStreamSynchronize(s));
@@ -269,40 +274,334 @@ bool spgemm_dev(DevArena& ar, const std::vector<int64_t>& Aptr_host, const DMat&
   if (Cptr[m] >= (int64_t(1) << 31)) return false;
   C.nnz = Cptr[m];
   std::vector<int32_t> p32(Cptr.begin(), Cptr.end());
-  C.ptr = ar.upload(p32.data(), p32.size());
-  C.col = ar.get<int32_t>(std::max<int64_t>(C.nnz, 1));
-  C.val = ar.get<double>(std::max<int64_t>(C.nnz, 1));
+  C.ptr = out.upload(p32.data(), p32.size());
+  C.col = out.get<int32_t>(std::max<int64_t>(C.nnz, 1));
+  C.val = out.get<double>(std::max<int64_t>(C.nnz, 1));
   spgemm_block_kernel<1><<<nb, kGBS, 0, s>>>(A, B, blk_d, colbits, nullptr, C.ptr, C.col, C.val);
   AMG_LAUNCHED();
   AMG_HIP(hipStreamSynchronize(s));  // p32 and blk are pageable temporaries
   return true;
 }
 
+// ------------------------------------------------------------------ strength, prolongator
+
+// d_i = a_ii (0 when not stored)
+__global__ void __launch_bounds__(256) diag_kernel(DMat A, double* d) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < A.rows; i += gridDim.x * 256) {
+    double v = 0.0;
+    for (int e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
+      if (A.col[e] == i) v = A.val[e];
+    d[i] = v;
+  }
+}
+
+// Strength test of every stored entry, made symmetric by union: entry (i, j)
+// is strong when a_ij^2 > eps^2 |a_ii a_jj| or a_ji^2 > eps^2 |a_jj a_ii|
+// (the reverse entry found by binary search in row j).  A missing reverse
+// entry (structurally nonsymmetric A) or a row without a stored diagonal
+// raises *unsupported: the union would then hold entries A does not store,
+// and the filtered matrix's layout assumes the diagonal.
+__global__ void __launch_bounds__(256) strength_kernel(DMat A, const double* d, double eps2, uint8_t* strong,
+                                                       int32_t* cnt, int32_t* unsupported) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < A.rows; i += gridDim.x * 256) {
+    int c = 0;
+    bool diag = false;
+    for (int e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+      const int j = A.col[e];
+      if (j == i) {
+        strong[e] = 0;
+        diag = true;
+        continue;
+      }
+      const double v = A.val[e];
+      bool st = v * v > eps2 * fabs(d[i] * d[j]);
+      int lo = A.ptr[j], hi = A.ptr[j + 1] - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (A.col[mid] < i) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo <= hi && A.col[lo] == i) {
+        const double w = A.val[lo];
+        st = st || (w * w > eps2 * fabs(d[j] * d[i]));
+      } else {
+        *unsupported = 1;
+      }
+      strong[e] = st ? 1 : 0;
+      c += st ? 1 : 0;
+    }
+    if (!diag) *unsupported = 1;
+    cnt[i] = c;
+  }
+}
+
+// Columns of the strong entries of each row, in column order.
+__global__ void __launch_bounds__(256) strong_fill_kernel(DMat A, const uint8_t* strong, const int32_t* Sp,
+                                                          int32_t* Si) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < A.rows; i += gridDim.x * 256) {
+    int p = Sp[i];
+    for (int e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
+      if (strong[e]) Si[p++] = A.col[e];
+  }
+}
+
+// Filtered matrix A_F (strong entries kept, weak ones lumped into the
+// diagonal, in column order; a non-isolated row whose lumped diagonal is not
+// positive keeps a_ii), written with the diagonal in place: row i of A_F has
+// the diagonal and the strong entries, starting at AFp[i] = Sp[i] + i.  Also
+// dF and the Gershgorin ratio sum_j |a^F_ij| / |a^F_ii| (0 for isolated rows).
+__global__ void __launch_bounds__(256) filtered_kernel(DMat A, const uint8_t* strong, const int32_t* Sp,
+                                                       double* dF, double* ratio, uint8_t* iso, int32_t* AFc,
+                                                       double* AFv) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < A.rows; i += gridDim.x * 256) {
+    double aii = 0.0, lumped = 0.0;
+    for (int e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+      if (A.col[e] == i) aii = A.val[e];
+      else if (!strong[e]) lumped += A.val[e];
+    }
+    const bool isolated = Sp[i] == Sp[i + 1];
+    double dd = aii + lumped;
+    if (!isolated && dd <= 0.0) dd = aii;
+    double row = 0.0;
+    int p = Sp[i] + i;
+    for (int e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+      const int j = A.col[e];
+      if (j == i) {
+        row += fabs(dd);
+        AFc[p] = i;
+        AFv[p] = dd;
+        ++p;
+      } else if (strong[e]) {
+        row += fabs(A.val[e]);
+        AFc[p] = j;
+        AFv[p] = A.val[e];
+        ++p;
+      }
+    }
+    dF[i] = dd;
+    ratio[i] = isolated ? 0.0 : row / fabs(dd);
+    iso[i] = isolated ? 1 : 0;
+  }
+}
+
+// Per-workgroup maximum of the ratio over non-isolated rows (-1: none).
+__global__ void __launch_bounds__(256) ratio_max_kernel(int n, const double* ratio, const uint8_t* iso,
+                                                        double* partial) {
+  __shared__ double sh[256];
+  double m = -1.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    if (!iso[i]) m = fmax(m, ratio[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// P = P_hat - omega D_F^-1 (A_F P_hat), in place on the product's values.
+__global__ void __launch_bounds__(256) prolongator_finish_kernel(DMat C, const int32_t* agg, const double* dF,
+                                                                 double omega) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < C.rows; i += gridDim.x * 256) {
+    const double inv_d = 1.0 / dF[i];
+    for (int e = C.ptr[i]; e < C.ptr[i + 1]; ++e) {
+      const double smoothed = omega * (inv_d * C.val[e]);
+      C.val[e] = (C.col[e] == agg[i] ? 1.0 : 0.0) - smoothed;
+    }
+  }
+}
+
+int grid_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096))); }
+
+template <class T>
+void download(std::vector<T>& h, const T* d, size_t n, hipStream_t s) {
+  h.resize(n);
+  if (n) AMG_HIP(hipMemcpyAsync(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+}
+
+class DeviceSetupAccel final : public SetupAccel {
+ public:
+  DeviceSetupAccel(const amg_allocator* alloc, hipStream_t s) : stream_(s) {
+    if (alloc) {
+      alloc_ = *alloc;
+      has_alloc_ = true;
+    }
+  }
+
+  void begin_level(const Csr& A, bool from_galerkin) override {
+    s_ok_ = p_ok_ = have_A_ = false;
+    work_ = arena();
+    try {
+      if (from_galerkin && next_) {
+        a_ = std::move(next_);
+        dA_ = dAc_;
+      } else {
+        next_.reset();
+        a_ = arena();
+        dA_ = upload_mat(*a_, A, stream_);
+      }
+      have_A_ = true;
+    } catch (const DevError& e) {
+      if (e.code != AMG_ERR_OOM) throw;
+    }
+  }
+
+  bool strength(const Csr& A, double eps, Graph& S) override {
+    if (!have_A_) return false;
+    return guard([&] {
+      const int n = dA_.rows;
+      d_ = work_->get<double>(n);
+      strong_ = work_->get<uint8_t>(std::max<int64_t>(dA_.nnz, 1));
+      int32_t* cnt = work_->get<int32_t>(n);
+      int32_t* unsupported = work_->get<int32_t>(1);
+      AMG_HIP(hipMemsetAsync(unsupported, 0, sizeof(int32_t), stream_));
+      diag_kernel<<<grid_for(n), 256, 0, stream_>>>(dA_, d_);
+      AMG_LAUNCHED();
+      strength_kernel<<<grid_for(n), 256, 0, stream_>>>(dA_, d_, eps * eps, strong_, cnt, unsupported);
+      AMG_LAUNCHED();
+      std::vector<int32_t> ch, ah;
+      download(ch, cnt, n, stream_);
+      download(ah, unsupported, 1, stream_);
+      AMG_HIP(hipStreamSynchronize(stream_));
+      if (ah[0]) return false;
+      S.ptr.assign(n + 1, 0);
+      for (int i = 0; i < n; ++i) S.ptr[i + 1] = S.ptr[i] + ch[i];
+      std::vector<int32_t> p32(S.ptr.begin(), S.ptr.end());
+      Sp_ = work_->upload(p32.data(), p32.size());
+      int32_t* Si = work_->get<int32_t>(std::max<int64_t>(S.ptr[n], 1));
+      strong_fill_kernel<<<grid_for(n), 256, 0, stream_>>>(dA_, strong_, Sp_, Si);
+      AMG_LAUNCHED();
+      download(S.idx, Si, S.ptr[n], stream_);
+      AMG_HIP(hipStreamSynchronize(stream_));  // p32 is a pageable temporary
+      (void)A;
+      s_ok_ = true;
+      return true;
+    });
+  }
+
+  bool prolongator(const Csr& A, const Graph& S, const std::vector<int32_t>& agg, int32_t nc, Csr& P,
+                   double* omega) override {
+    if (!s_ok_) return false;
+    return guard([&] {
+      const int n = dA_.rows;
+      // A_F on the device, dF, ratio, isolated flags
+      std::vector<int64_t> AFp(n + 1);
+      for (int i = 0; i <= n; ++i) AFp[i] = S.ptr[i] + i;
+      std::vector<int32_t> afp32(AFp.begin(), AFp.end());
+      DMat AF;
+      AF.rows = n;
+      AF.cols = n;
+      AF.nnz = AFp[n];
+      AF.ptr = work_->upload(afp32.data(), afp32.size());
+      AF.col = work_->get<int32_t>(std::max<int64_t>(AF.nnz, 1));
+      AF.val = work_->get<double>(std::max<int64_t>(AF.nnz, 1));
+      dF_ = work_->get<double>(n);
+      double* ratio = work_->get<double>(n);
+      uint8_t* iso = work_->get<uint8_t>(n);
+      filtered_kernel<<<grid_for(n), 256, 0, stream_>>>(dA_, strong_, Sp_, dF_, ratio, iso, AF.col, AF.val);
+      AMG_LAUNCHED();
+      const int nbm = grid_for(n);
+      double* part = work_->get<double>(nbm);
+      ratio_max_kernel<<<nbm, 256, 0, stream_>>>(n, ratio, iso, part);
+      AMG_LAUNCHED();
+      std::vector<double> ph;
+      download(ph, part, nbm, stream_);
+      // P_hat: one entry 1 per aggregated row
+      std::vector<int32_t> php(n + 1, 0), phc;
+      for (int i = 0; i < n; ++i) {
+        php[i + 1] = php[i] + (agg[i] >= 0 ? 1 : 0);
+        if (agg[i] >= 0) phc.push_back(agg[i]);
+      }
+      std::vector<double> phv(phc.size(), 1.0);
+      DMat Ph;
+      Ph.rows = n;
+      Ph.cols = nc;
+      Ph.nnz = static_cast<int64_t>(phc.size());
+      Ph.ptr = work_->upload(php.data(), php.size());
+      Ph.col = work_->upload(phc.data(), std::max<size_t>(phc.size(), 1));
+      Ph.val = work_->upload(phv.data(), std::max<size_t>(phv.size(), 1));
+      int32_t* agg_d = work_->upload(agg.data(), agg.size());
+      AMG_HIP(hipStreamSynchronize(stream_));  // temporaries above are pageable
+      double rho = -1.0;
+      for (double v : ph) rho = std::max(rho, v);
+      if (rho < 0.0) rho = 1.0;  // no non-isolated row
+      const double om = (4.0 / 3.0) / rho;
+      std::vector<int64_t> Pptr;
+      if (!spgemm_dev(*work_, *work_, AFp, AF, Ph, dP_, Pptr, stream_)) return false;
+      prolongator_finish_kernel<<<grid_for(n), 256, 0, stream_>>>(dP_, agg_d, dF_, om);
+      AMG_LAUNCHED();
+      Csr out;
+      out.rows = n;
+      out.cols = nc;
+      out.ptr = std::move(Pptr);
+      download(out.col, dP_.col, dP_.nnz, stream_);
+      download(out.val, dP_.val, dP_.nnz, stream_);
+      AMG_HIP(hipStreamSynchronize(stream_));
+      (void)A;
+      P = std::move(out);
+      *omega = om;
+      p_ok_ = true;
+      return true;
+    });
+  }
+
+  bool galerkin(const Csr& R, const Csr& A, const Csr& P, Csr& Ac) override {
+    if (!have_A_) return false;
+    return guard([&] {
+      const DMat dP = p_ok_ ? dP_ : upload_mat(*work_, P, stream_);
+      const DMat dR = upload_mat(*work_, R, stream_);
+      DMat AP;
+      std::vector<int64_t> APptr, Cptr;
+      if (!spgemm_dev(*work_, *work_, A.ptr, dA_, dP, AP, APptr, stream_)) return false;
+      next_ = arena();
+      if (!spgemm_dev(*work_, *next_, R.ptr, dR, AP, dAc_, Cptr, stream_)) {
+        next_.reset();
+        return false;
+      }
+      Csr out;
+      out.rows = dAc_.rows;
+      out.cols = dAc_.cols;
+      out.ptr = std::move(Cptr);
+      download(out.col, dAc_.col, dAc_.nnz, stream_);
+      download(out.val, dAc_.val, dAc_.nnz, stream_);
+      AMG_HIP(hipStreamSynchronize(stream_));
+      Ac = std::move(out);
+      return true;
+    });
+  }
+
+ private:
+  std::unique_ptr<DevArena> arena() { return std::make_unique<DevArena>(has_alloc_ ? &alloc_ : nullptr, stream_); }
+
+  // Runs a step; an allocation failure leaves the step to the host.
+  template <class F>
+  bool guard(F fn) {
+    try {
+      return fn();
+    } catch (const DevError& e) {
+      if (e.code != AMG_ERR_OOM) throw;
+      next_.reset();
+      return false;
+    }
+  }
+
+  hipStream_t stream_;
+  amg_allocator alloc_{};
+  bool has_alloc_ = false;
+  std::unique_ptr<DevArena> a_, next_, work_;  // A of the level, next level's A, level scratch
+  DMat dA_, dAc_, dP_;
+  double* d_ = nullptr;
+  double* dF_ = nullptr;
+  uint8_t* strong_ = nullptr;
+  int32_t* Sp_ = nullptr;
+  bool have_A_ = false, s_ok_ = false, p_ok_ = false;
+};
+
 }  // namespace
 
-bool device_galerkin(const Csr& R, const Csr& A, const Csr& P, Csr& Ac, const amg_allocator* alloc,
-                     hipStream_t stream) {
-  DevArena ar(alloc, stream);
-  const DMat dA = upload_mat(ar, A, stream);
-  const DMat dP = upload_mat(ar, P, stream);
-  const DMat dR = upload_mat(ar, R, stream);
-  DMat AP, C;
-  std::vector<int64_t> APptr, Cptr;
-  if (!spgemm_dev(ar, A.ptr, dA, dP, AP, APptr, stream)) return false;
-  if (!spgemm_dev(ar, R.ptr, dR, AP, C, Cptr, stream)) return false;
-  Csr out;
-  out.rows = C.rows;
-  out.cols = C.cols;
-  out.ptr = std::move(Cptr);
-  out.col.resize(C.nnz);
-  out.val.resize(C.nnz);
-  if (C.nnz) {
-    AMG_HIP(hipMemcpyAsync(out.col.data(), C.col, sizeof(int32_t) * C.nnz, hipMemcpyDeviceToHost, stream));
-    AMG_HIP(hipMemcpyAsync(out.val.data(), C.val, sizeof(double) * C.nnz, hipMemcpyDeviceToHost, stream));
-  }
-  AMG_HIP(hipStreamSynchronize(stream));
-  Ac = std::move(out);
-  return true;
+std::unique_ptr<SetupAccel> make_device_setup_accel(const amg_allocator* alloc, hipStream_t stream) {
+  return std::make_unique<DeviceSetupAccel>(alloc, stream);
 }
 
 }  // namespace amg

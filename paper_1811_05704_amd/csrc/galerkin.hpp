@@ -1,5 +1,6 @@
 #pragma once
-// Galerkin products on the device (section 2, "AMG setup": A_{l+1} = R_l A_l P_l).
+// Setup steps on the device (section 2, "AMG setup": strength graph, smoothed
+// prolongator, A_{l+1} = R_l A_l P_l).
 //
 // The sparse products run on the GPU with the host's arithmetic: every entry
 // of C = A B is the sum of its products a_ik b_kj taken in the order the host
@@ -8,18 +9,20 @@
 
 #include <hip/hip_runtime.h>
 
+#include <memory>
+
 #include "../../include/amg.h"
 #include "host_setup.hpp"
 
 namespace amg {
 
-// Ac = R (A P) with both products on the device (the intermediate A P stays
-// there); device memory comes from `alloc` (NULL: hipMalloc) and is released
-// before returning.  Returns false, leaving Ac untouched, when a row has more
-// products than one workgroup sorts or the column count does not fit the
-// sort keys; the caller then forms the product on the host.  Throws DevError
-// on HIP errors or when the allocator fails.
-bool device_galerkin(const Csr& R, const Csr& A, const Csr& P, Csr& Ac, const amg_allocator* alloc,
-                     hipStream_t stream);
+// Accelerator of the setup's data-parallel steps on the device: strength
+// graph, smoothed prolongator and Galerkin products, each bit-identical to
+// the host step; the coarse operator a level produces stays on the device
+// for the next level.  Device memory comes from `alloc` (NULL: hipMalloc);
+// a step whose allocation fails, whose rows do not fit the sort blocks, or
+// (strength graph) whose matrix is structurally nonsymmetric is left to the
+// host.  Other HIP errors throw DevError.
+std::unique_ptr<SetupAccel> make_device_setup_accel(const amg_allocator* alloc, hipStream_t stream);
 
 }  // namespace amg

@@ -428,25 +428,30 @@ std::vector<double> smoother_diagonal(const Csr& A, const SetupParams& prm) {
 
 }  // namespace
 
-HostHierarchy build_hierarchy(Csr A, const SetupParams& prm, const GalerkinFn& galerkin) {
+HostHierarchy build_hierarchy(Csr A, const SetupParams& prm, SetupAccel* accel) {
   HostHierarchy H;
+  bool from_galerkin = false;
   while (true) {
     const int64_t n = A.rows;
     const int lvl_no = static_cast<int>(H.levels.size()) + 1;  // 1-based
     if (n <= prm.coarse_enough || lvl_no >= prm.max_levels) break;
     const double eps = prm.eps_strong * std::ldexp(1.0, -(lvl_no - 1));
-    Graph S = strength_graph(A, eps);
+    if (accel) accel->begin_level(A, from_galerkin);
+    Graph S;
+    if (!accel || !accel->strength(A, eps, S)) S = strength_graph(A, eps);
     int32_t nc = 0;
     std::vector<int32_t> agg = aggregate(S, &nc);
     if (nc == 0 || nc >= n) break;
     HostLevel L;
     L.eps = eps;
-    L.P = smoothed_prolongator(A, S, agg, nc, &L.omega);
+    if (!accel || !accel->prolongator(A, S, agg, nc, L.P, &L.omega))
+      L.P = smoothed_prolongator(A, S, agg, nc, &L.omega);
     L.R = transpose(L.P);
     L.m = smoother_diagonal(A, prm);
     if (prm.relax == 2) L.cheb_hi = gershgorin_dinv(A);
     Csr Ac;
-    if (!galerkin || !galerkin(L.R, A, L.P, Ac)) Ac = spgemm(L.R, spgemm(A, L.P));
+    from_galerkin = accel && accel->galerkin(L.R, A, L.P, Ac);
+    if (!from_galerkin) Ac = spgemm(L.R, spgemm(A, L.P));
     L.agg = std::move(agg);
     L.A = std::move(A);
     H.levels.push_back(std::move(L));

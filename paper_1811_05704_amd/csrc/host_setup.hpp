@@ -5,7 +5,6 @@
 #pragma once
 
 #include <cstdint>
-#include <functional>
 #include <string>
 #include <vector>
 
@@ -53,13 +52,26 @@ void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const doubl
 // Limit the worker threads the setup of the calling thread uses (0 = default).
 void set_setup_threads(int n);
 
-// Galerkin product A_c = R (A P) of one level.  Must give exactly what
-// spgemm(R, spgemm(A, P)) gives; may return false to leave it to the host.
-using GalerkinFn = std::function<bool(const Csr& R, const Csr& A, const Csr& P, Csr& Ac)>;
+struct Graph;
 
-// Full hierarchy; throws SetupError.  `galerkin` (optional) forms the
-// Galerkin products elsewhere (on the device).
-HostHierarchy build_hierarchy(Csr A, const SetupParams& prm, const GalerkinFn& galerkin = nullptr);
+// Optional accelerator for the data-parallel steps of one level (the device).
+// Every step must give exactly what the host step gives, or return false to
+// leave that step to the host.  The steps of a level are called in order:
+// begin_level, strength, prolongator, galerkin; `from_galerkin` tells that A
+// is the product the accelerator returned for the previous level.
+class SetupAccel {
+ public:
+  virtual ~SetupAccel() = default;
+  virtual void begin_level(const Csr& A, bool from_galerkin) = 0;
+  virtual bool strength(const Csr& A, double eps, Graph& S) = 0;
+  virtual bool prolongator(const Csr& A, const Graph& S, const std::vector<int32_t>& agg, int32_t nc, Csr& P,
+                           double* omega) = 0;
+  virtual bool galerkin(const Csr& R, const Csr& A, const Csr& P, Csr& Ac) = 0;
+};
+
+// Full hierarchy; throws SetupError.  `accel` (optional) runs the
+// data-parallel steps elsewhere (on the device).
+HostHierarchy build_hierarchy(Csr A, const SetupParams& prm, SetupAccel* accel = nullptr);
 
 // Steps, exposed for tests of the host logic.
 struct Graph {

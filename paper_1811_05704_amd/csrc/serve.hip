@@ -447,15 +447,9 @@ void worker_main(amg_server_s* V, int threads) {
       S.prm = V->prm;
       TransientAlloc scratch(V);
       const amg_allocator scratch_alloc = scratch.handle();
-      GalerkinFn galerkin = [&](const Csr& R, const Csr& A, const Csr& P, Csr& Ac) {
-        try {
-          return device_galerkin(R, A, P, Ac, &scratch_alloc, ws);
-        } catch (const DevError& e) {
-          if (e.code == AMG_ERR_OOM) return false;
-          throw;
-        }
-      };
-      S.host = build_hierarchy(std::move(q->A), setup_params(V->prm), galerkin);
+      std::unique_ptr<SetupAccel> accel = make_device_setup_accel(&scratch_alloc, ws);
+      S.host = build_hierarchy(std::move(q->A), setup_params(V->prm), accel.get());
+      accel.reset();  // its device memory goes back to the budget
       if (S.host.levels.size() < 2) throw SetupError{-1, "served systems need at least two levels"};
       if (S.host.levels.size() > static_cast<size_t>(kMaxLevels))
         throw SetupError{-8, "hierarchy deeper than the serving limit"};

@@ -41,20 +41,12 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
     else amg_params_default(&S->prm);
     check_params(S->prm);
     validate_csr(n, row_ptr, col, val);
-    GalerkinFn galerkin;
-    if (device) {
-      // Galerkin products on the device (bit-identical to the host's); a
-      // product that does not fit the device path stays on the host.
-      galerkin = [&](const Csr& R, const Csr& A, const Csr& P, Csr& Ac) {
-        try {
-          return device_galerkin(R, A, P, Ac, alloc, static_cast<hipStream_t>(stream));
-        } catch (const DevError& e) {
-          if (e.code == AMG_ERR_OOM) return false;
-          throw;
-        }
-      };
-    }
-    S->host = build_hierarchy(to_csr(n, row_ptr, col, val), setup_params(S->prm), galerkin);
+    // Data-parallel setup steps on the device (bit-identical to the host's);
+    // a step that does not fit the device path stays on the host.
+    std::unique_ptr<SetupAccel> accel;
+    if (device) accel = make_device_setup_accel(alloc, static_cast<hipStream_t>(stream));
+    S->host = build_hierarchy(to_csr(n, row_ptr, col, val), setup_params(S->prm), accel.get());
+    accel.reset();
     if (device) device_setup(*S, alloc, static_cast<hipStream_t>(stream));
     S->setup_s = now_s() - t0;
     *out = S.release();

@@ -217,8 +217,9 @@ def test_solve_with_coarsest_order_895():
 
 @pytest.mark.parametrize("name", ["poisson32", "diffusion24", "convection24", "convection40"])
 def test_device_galerkin_matches_host_setup(name):
-    """The device setup forms the Galerkin products on the GPU; every level
-    must be bit-identical to the host setup's (same products, same order)."""
+    """The device setup runs the strength graph, the smoothed prolongator and
+    the Galerkin products on the GPU; every level must be bit-identical to
+    the host setup's (same arithmetic, same order)."""
     if name == "convection40":
         g = problems.gaussian_field(40, 2.0, 8.0, 3)
         A, kw = problems.diffusion3d(40, g, velocity=(50.0, 25.0, 12.5)), {"relax": "jacobi"}
@@ -232,6 +233,44 @@ def test_device_galerkin_matches_host_setup(name):
         Ad, Ah = S.level_scipy(l, "A"), H.level_scipy(l, "A")
         assert np.array_equal(Ad.indptr, Ah.indptr) and np.array_equal(Ad.indices, Ah.indices)
         assert np.array_equal(Ad.data, Ah.data), l
+    for l in range(S.nlevels - 1):
+        assert np.array_equal(S.aggregates(l), H.aggregates(l))
+        Pd, Ph = S.level_scipy(l, "P"), H.level_scipy(l, "P")
+        assert np.array_equal(Pd.indptr, Ph.indptr) and np.array_equal(Pd.indices, Ph.indices)
+        assert np.array_equal(Pd.data, Ph.data), l
+        assert S.smoother(l)[1] == H.smoother(l)[1]  # prolongator damping omega
+    S.release()
+    H.release()
+
+
+def test_device_setup_structurally_nonsymmetric_falls_back():
+    """A pattern without its transpose (row i holds i+37, row i+37 not i): the
+    union of the strength graph then has entries A does not store, so that
+    step runs on the host while the other steps stay on the device; the
+    hierarchy must still equal the host setup's bit for bit."""
+    n = 6000
+    rp, cols, vals = [0], [], []
+    for i in range(n):
+        for j, v in ((i - 1, -1.0), (i, 4.0), (i + 37, -0.3)):
+            if 0 <= j < n:
+                cols.append(j)
+                vals.append(v)
+        rp.append(len(cols))
+    A = problems.CSR(n, np.array(rp, dtype=np.int64), np.array(cols, dtype=np.int32), np.array(vals))
+    S = amg.Solver(A, solver="bicgstab", relax="jacobi")
+    H = amg.HostHierarchy(A, solver="bicgstab", relax="jacobi")
+    announce("device setup nonsymmetric pattern, levels", S.nlevels)
+    assert S.nlevels == H.nlevels >= 2
+    for l in range(S.nlevels):
+        Ad, Ah = S.level_scipy(l, "A"), H.level_scipy(l, "A")
+        assert np.array_equal(Ad.indptr, Ah.indptr) and np.array_equal(Ad.indices, Ah.indices)
+        assert np.array_equal(Ad.data, Ah.data), l
+    for l in range(S.nlevels - 1):
+        assert np.array_equal(S.aggregates(l), H.aggregates(l))
+        assert abs(S.level_scipy(l, "P") - H.level_scipy(l, "P")).max() == 0.0
+    f = problems.rhs_ones(n)
+    x, info = S.solve(dev(f))
+    assert info["status"] == 0 and true_rel_residual(A, host(x), f) <= 1e-8
     S.release()
     H.release()
 
