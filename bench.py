@@ -53,7 +53,9 @@ def workload_matrix(kind, N):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_poisson150.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1811_05704_amd", "csrc", f) for f in ("kernels.hpp", "device.hpp")]
+# the kernels and the V-cycle driver that picks their gathers and epilogues
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1811_05704_amd", "csrc", f)
+                  for f in ("kernels.hpp", "device.hpp", "solver.hpp", "solver.hip")]
 
 
 def kernel_source_hash():

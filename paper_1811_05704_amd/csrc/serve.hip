@@ -128,6 +128,7 @@ size_t footprint(const HostHierarchy& H, const amg_params& p) {
     if (l > 0 || p.precision == AMG_MIXED) b += csr(L.A, vs);
     b += csr(L.P, vs) + csr(L.R, vs);
     b += L.A.rows * vs * 7;
+    if (l == 0) b += L.A.nnz() * vs + 4096;  // A diag(m) values of level 1
   }
   const size_t nL = H.levels.back().A.rows;
   b += nL * nL * 8 + nL * 64;
@@ -144,7 +145,7 @@ struct IterDesc {
   Batch<FinItem> fin_alpha;
   Batch<UpdItem> update;
   Batch<FinItem> fin_rr;
-  Batch<SpmvItem<T, GatherMF<T, double>, EpiResid<T, double>>> pre0;
+  Batch<SpmvItem<T, GatherX<T, double>, EpiResid<T, double>>> pre0;
   Batch<SpmvItem<T, GatherX<T, T>, EpiResid<T, T>>> pre[kMaxLevels];
   Batch<SpmvItem<T, GatherX<T, T>, EpiRestrict<T>>> restrict_mid[kMaxLevels];
   Batch<SpmvItem<T, GatherX<T, T>, EpiStore<T, T>>> restrict_last[kMaxLevels];
@@ -282,7 +283,7 @@ void build_desc(amg_server_s& V, IterDesc<T>& D) {
       DevLevel<T>& lv = H.lev[l];
       DevLevel<T>* next = (l + 1 < L - 1) ? &H.lev[l + 1] : nullptr;
       if (l == 0)
-        batch_add(D.pre0, spmv_item(lv.A, GatherMF<T, double>{lv.m, S.r}, EpiResid<T, double>{lv.r, S.r}, nullptr, skip),
+        batch_add(D.pre0, spmv_item(lv.As, GatherX<T, double>{S.r}, EpiResid<T, double>{lv.r, S.r}, nullptr, skip),
                   lv.A.nblocks);
       else
         batch_add(D.pre[l], spmv_item(lv.A, GatherX<T, T>{lv.mf}, EpiResid<T, T>{lv.r, lv.f}, nullptr, skip),

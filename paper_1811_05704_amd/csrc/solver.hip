@@ -153,7 +153,10 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
         launch_spmv(S.A0, GatherX<double, double>{S.p}, EpiStoreDot{S.q, S.p}, S.partials, nullptr, st);
         break;
       case 1:
-        launch_spmv(lv.A, GatherMF<T, double>{lv.m, S.r}, EpiResid<T, double>{lv.r, S.r}, nullptr, nullptr, st);
+        if (lv.As.val)
+          launch_spmv(lv.As, GatherX<T, double>{S.r}, EpiResid<T, double>{lv.r, S.r}, nullptr, nullptr, st);
+        else
+          launch_spmv(lv.A, GatherMF<T, double>{lv.m, S.r}, EpiResid<T, double>{lv.r, S.r}, nullptr, nullptr, st);
         break;
       case 2:
         launch_spmv(lv.A, GatherX<T, T>{lv.y}, EpiSmooth<T, double, double, 1>{S.z, lv.y, lv.m, S.r}, S.partials,
@@ -216,7 +219,7 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
       const double nl = L.n, ncl = L.nc;
       b += 2.0 * double(L.A.nnz) * (sz + 4) + 2.0 * double(L.P.nnz) * (sz + 4);
       b += 12.0 * (nl + 1) + 4.0 * (ncl + 1) + 2.0 * ncl * sz;
-      b += (l == 0) ? nl * (32.0 + 7.0 * sz) : 11.0 * nl * sz;
+      b += (l == 0) ? nl * (32.0 + 6.0 * sz) : 11.0 * nl * sz;  // level 1: m not read by the pre-sweep
     }
     b += 8.0 * double(S.nL) * double(S.nL) + 2.0 * double(S.nL) * sz;
     *bytes = b;
@@ -225,7 +228,7 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
   const double idx = 4.0;
   switch (which) {
     case 0: *bytes = zA * (8 + idx) + idx * (n + 1) + 16 * n; break;                    // p in, q out
-    case 1: *bytes = zA * (sz + idx) + idx * (n + 1) + n * 8 + 2 * n * sz; break;       // f, m in; r out
+    case 1: *bytes = zA * (sz + idx) + idx * (n + 1) + n * 8 + n * sz; break;           // A diag(m), f in; r out
     case 2: *bytes = zA * (sz + idx) + idx * (n + 1) + n * sz * 2 + n * 8 * 2; break;   // y, m, f in; z out
     case 3: *bytes = zP * (sz + idx) + idx * (nc + 1) + n * sz + nc * sz; break;        // r in; f_c out
     default: *bytes = zP * (sz + idx) + idx * (n + 1) + nc * sz + n * 8 + 2 * n * sz; break;  // z_c, f, m in; y out

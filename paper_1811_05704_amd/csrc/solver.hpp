@@ -53,6 +53,7 @@ template <class T>
 struct DevLevel {
   int32_t n = 0, nc = 0;
   DevCsr<T> A, P, R;
+  DevCsr<T> As;  // level 1: A diag(m), same pattern as A (its own values)
   T* m = nullptr;
   T* f = nullptr;  // right-hand side (unused on level 0: the caller's vector)
   T* r = nullptr;  // residual
@@ -144,7 +145,10 @@ class Vcycle {
       return;
     }
     if (o_.npre == 1) {
-      if constexpr (std::is_same<TF, T>::value) {
+      if (lv.As.val) {
+        // r = f - (A diag(m)) f: one gathered vector instead of m and f
+        launch_spmv(lv.As, GatherX<T, TF>{f}, EpiResid<T, TF>{lv.r, f}, nullptr, skip, s);
+      } else if constexpr (std::is_same<TF, T>::value) {
         if (lv.mf) {
           launch_spmv(lv.A, GatherX<T, T>{lv.mf}, EpiResid<T, TF>{lv.r, f}, nullptr, skip, s);
         } else {
@@ -515,6 +519,13 @@ inline void upload_levels(amg_solver& S, DevHierarchy<T>& H) {
     d.R = upload_csr<T>(ar, hl.R);
     std::vector<T> m(hl.m.begin(), hl.m.end());
     d.m = ar.upload(m.data(), m.size());
+    if (l == 0 && npre == 1 && !cheb) {
+      // the first pre-sweep from zero reads A (m .* f) = (A diag(m)) f
+      d.As = d.A;
+      std::vector<T> v(hl.A.val.size());
+      for (size_t k = 0; k < v.size(); ++k) v[k] = static_cast<T>(hl.A.val[k] * hl.m[hl.A.col[k]]);
+      d.As.val = ar.upload(v.data(), std::max<size_t>(v.size(), 1));
+    }
     AMG_HIP(hipStreamSynchronize(ar.stream()));
     if (l > 0) {
       d.f = ar.get<T>(d.n);
