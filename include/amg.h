@@ -203,8 +203,9 @@ amg_status amg_csr_spmv(amg_matrix m, const void* x_dev, void* y_dev, void* hip_
  * kind: 0 = LDS-staged stream kernel (short rows), 1 = sub-wavefront per row;
  * block_bytes: LDS bytes of products per stream block (4096 for matrices
  * with less than 32 MiB of values; otherwise 8192 for FP64 matrices reduced
- * by one lane per row and 16384 for the rest), 0 for kind 1.  Any output
- * pointer may be NULL.
+ * by one lane per row, else the smallest of 4096, 8192 and 16384 that holds
+ * 256 / lanes_per_row rows of mean length), 0 for kind 1.  Any output pointer
+ * may be NULL.
  */
 amg_status amg_csr_kernel_info(amg_matrix m, int32_t* kind, int32_t* lanes_per_row,
                                int32_t* blocks, int32_t* block_bytes);

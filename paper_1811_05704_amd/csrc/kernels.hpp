@@ -225,10 +225,9 @@ struct EpiSmooth {
 // kStreamSmallBytes (4 KB) for matrices below kStreamSmallMatrix bytes of
 // values, where the larger blocks would leave too few workgroups to hide
 // memory latency (measured on the level matrices of the 150^3 hierarchy:
-// 15-40% faster below 32 MB, no gain above).  Large FP64 matrices reduced by
-// one lane per row use kStreamMidBytes (8 KB): their ~146 rows per block fit
-// one pass of the 256 threads (3-4% faster than 16 KB on the 7-point and
-// prolongation matrices).
+// 15-40% faster below 32 MB).  Larger matrices take the smallest block that
+// holds one reduction pass (the schedule puts at most kBS / G rows in a
+// block), kStreamMidBytes (8 KB) or AMG_STREAM_BYTES.
 #ifndef AMG_STREAM_BYTES
 #define AMG_STREAM_BYTES 16384
 #endif
@@ -717,6 +716,7 @@ __global__ void __launch_bounds__(kBS) batched_spmv_kernel(const Batch<SpmvItem<
         case 6: stream_block<1, NM>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         case 16: stream_block<4, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         case 17: stream_block<4, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 18: stream_block<4, NM>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         case 64: stream_block<16, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         case 65: stream_block<16, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         case 256: stream_block<64, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;

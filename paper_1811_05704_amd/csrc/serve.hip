@@ -467,7 +467,7 @@ void worker_main(amg_server_s* V, int threads) {
       DeviceSetupOpts opts;
       opts.standalone = false;
       opts.blas = blas;
-      for (;;) {
+      for (bool failed_alone = false;;) {
         try {
           device_setup(S, &V->alloc, ws, opts);
           break;
@@ -477,7 +477,15 @@ void worker_main(amg_server_s* V, int threads) {
           S.h64 = DevHierarchy<double>{};
           S.h32 = DevHierarchy<float>{};
           std::unique_lock<std::mutex> lk(V->mu);
-          if (V->reserved == q->reserved) throw;  // alone in the pool and still no room
+          if (V->reserved == q->reserved) {
+            // Alone in the pool: the memory in the way may have belonged to
+            // another worker's setup that finished meanwhile (its temporaries
+            // come and go), so try once more; failing again alone, it cannot fit.
+            if (failed_alone) throw;
+            failed_alone = true;
+            continue;
+          }
+          failed_alone = false;
           V->cv_mem.wait_for(lk, std::chrono::milliseconds(20));
           if (V->stopping) throw DevError{-5, "server stopping"};
         }

@@ -78,11 +78,19 @@ def test_spmv_matches_cpu(name, rows, cols, gen, precision):
     if info["kind"] == "stream":
         expect = 1 if mean <= 12 else 4 if mean <= 48 else 16 if mean <= 192 else 64
         assert info["lanes"] == expect
-        vbytes = int(rp[-1]) * (8 if precision == "fp64" else 4)
+        sz = 8 if precision == "fp64" else 4
+        vbytes = int(rp[-1]) * sz
+        one_pass = (256 // expect) * mean  # entries of one reduction pass
         if vbytes < 32 << 20:
             assert info["block_bytes"] == 4096
+        elif expect == 1 and precision == "fp64":
+            assert info["block_bytes"] == 8192
+        elif one_pass <= 4096 // sz:
+            assert info["block_bytes"] == 4096
+        elif expect <= 4 and one_pass <= 8192 // sz:
+            assert info["block_bytes"] == 8192
         else:
-            assert info["block_bytes"] == (8192 if expect == 1 and precision == "fp64" else 16384)
+            assert info["block_bytes"] == 16384
     # worst case grows with the row length (per-lane partial sums + a tree)
     tol = 5e-14 if precision == "fp64" else 2e-5
     err = np.abs(y - yr)
