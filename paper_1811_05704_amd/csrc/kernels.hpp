@@ -8,16 +8,16 @@
 // kernels are built around coalesced streaming of the CSR arrays, gathers of
 // x that hit in L2, LDS-staged row sums and wave64 reductions.
 //
-// Two SpMV variants, chosen per matrix from its row lengths:
+// Two SpMV variants, chosen per matrix from its row lengths and size:
 //  * stream: a workgroup takes a precomputed block of consecutive rows whose
-//    entries fit in LDS, streams val/col of the whole block with consecutive
-//    lanes on consecutive entries (perfectly coalesced), stores the products
-//    in LDS, then each lane sums one row from LDS (short rows: fine-level
-//    operators and prolongators).  A row longer than the LDS block gets a
-//    block of its own and is reduced by the whole workgroup.
-//  * vector: G lanes (a power of two up to the 64-lane wavefront) per row,
-//    strided loads within the row and a butterfly reduction with lane
-//    shuffles (longer rows: coarse operators and restrictions).
+//    entries fit in LDS (4, 8 or 16 KB of products), streams val/col of the
+//    whole block with consecutive lanes on consecutive entries (perfectly
+//    coalesced), stores the products in LDS, then G = 1, 4, 16 or 64 lanes
+//    sum each row from LDS (every matrix of the hierarchy with mean row
+//    length up to 512).  A row longer than the LDS block gets a block of its
+//    own and is reduced by the whole workgroup.
+//  * vector: 64 lanes per row straight from memory, strided loads within the
+//    row and a butterfly reduction with lane shuffles (very long rows).
 // Workgroups are remapped so that each of the 8 XCDs (each with its own L2)
 // works on one contiguous range of rows, keeping x-gathers XCD-local.
 //

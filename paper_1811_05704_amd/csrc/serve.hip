@@ -1,11 +1,12 @@
 // Serving: a request loop over many independent linear systems with
 // continuous batching (C ABI amg_server_* in include/amg.h).
 //
-// Section 3 of the paper: the hierarchy depends only on the matrix, is built
-// on the CPU and then lives on the backend for the solve.  Here each request
-// (matrix + right-hand side) is set up on a host worker thread, placed in a
-// device memory pool under an HBM budget, and admitted into a slot of the
-// live set at an iteration boundary.  One step launches a captured hipGraph of
+// Section 3 of the paper: the hierarchy depends only on the matrix, is set
+// up once and then lives on the backend for the solve.  Here each request
+// (matrix + right-hand side) is set up by a worker thread (its data-parallel
+// steps on the device on the worker's own stream, with temporaries drawn from
+// the budget), placed in a device memory pool under an HBM budget, and
+// admitted into a slot of the live set at an iteration boundary.  One step launches a captured hipGraph of
 // `check_every` Krylov iterations in which every kernel is a persistent,
 // descriptor-driven launch covering the same operation of all live solves (the
 // outer SpMV of every solve, then the level-1 pre-sweeps of every solve, ...).

@@ -2,23 +2,27 @@
 // Solve phase on the device: V-cycle driver, Krylov drivers, solver object.
 //
 // Section 2 ("AMG solve") and its closing remark: one V-cycle is one
-// preconditioning step of a Krylov method.  Section 3: the hierarchy is built
-// on the CPU, transferred to the backend once, and reused for every right-hand
-// side; smoothers and Krylov methods are expressed with the backend's
-// primitives (here: fused HIP kernels on gfx950).
+// preconditioning step of a Krylov method.  Section 3: the hierarchy is set up
+// once (its data-parallel steps on the device, the rest on the CPU) and
+// reused for every right-hand side; smoothers and Krylov methods are
+// expressed with the backend's primitives (here: fused HIP kernels on gfx950).
 //
 // V-cycle, per level l < L (zero initial guess on every level; one pre- and
 // one post-sweep of the diagonal smoother m in the common configuration):
 //   r_l     = f_l - A_l (m .* f_l)      pre-sweep fused into the residual
-//   f_{l+1} = R_l r_l                   restriction
+//                                       (level 1: (A_1 diag(m)) f_1, stored once)
+//   f_{l+1} = R_l r_l                   restriction (also m .* f_{l+1})
 //   ... coarser levels, then z_L = A_L^-1 f_L (dense inverse, FP64) ...
 //   y_l     = m .* f_l + P_l z_{l+1}    prolongation + correction, pre-sweep recomputed
 //   z_l     = y_l + m .* (f_l - A_l y_l)  post-sweep (level 1 of PCG also forms r . z)
-// The Krylov loop (PCG or BiCGStab) is FP64; its scalars (alpha, beta, omega,
-// convergence flag) live on the device, so one iteration is a fixed sequence of
-// kernels that is captured once into a hipGraph and replayed; the host polls
-// the flag every few iterations.  Kernels early-exit once the flag is set, so
-// replays past convergence are no-ops and the iteration count stays exact.
+// Chebyshev sweeps replace the two smoothing steps (chebyshev.hpp).
+// The Krylov loop (PCG, BiCGStab or flexible GMRES) is FP64; its scalars
+// (alpha, beta, omega, convergence flag) live on the device.  For PCG and
+// BiCGStab one iteration is a fixed sequence of kernels that is captured once
+// into a hipGraph and replayed; the host polls the flag every few iterations.
+// Kernels early-exit once the flag is set, so replays past convergence are
+// no-ops and the iteration count stays exact.  GMRES launches its kernels
+// directly and polls a per-cycle stop flag (gmres.hpp).
 
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
