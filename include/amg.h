@@ -115,11 +115,14 @@ void amg_params_default(amg_params* p);
 /*
  * Build the hierarchy for the n x n CSR matrix (row_ptr int64[n+1], col
  * int32[nnz], val double[nnz]; host, caller-owned, copied) and upload it to
- * the current device.  Requirements: row_ptr[0] = 0, non-decreasing row_ptr,
- * 0 <= col < n, strictly ascending columns within a row, a stored diagonal
- * entry a_ii > 0 in every row, nnz < 2^31.  p = NULL means defaults.  On
- * success *out receives a handle owning all device memory; on error *out is
- * set to NULL.
+ * the current device (section 2, "AMG setup").  The strength graph, the
+ * smoothed prolongators and the Galerkin products run on the device on
+ * hip_stream, with temporaries from alloc; the greedy aggregation runs on the
+ * host; the result is bit-identical to amg_setup_host.  Requirements:
+ * row_ptr[0] = 0, non-decreasing row_ptr, 0 <= col < n, strictly ascending
+ * columns within a row, a stored diagonal entry a_ii > 0 in every row,
+ * nnz < 2^31.  p = NULL means defaults.  On success *out receives a handle
+ * owning all device memory; on error *out is set to NULL.
  */
 amg_status amg_setup(int64_t n, const int64_t* row_ptr, const int32_t* col,
                      const double* val, const amg_params* p,
@@ -229,10 +232,13 @@ amg_status amg_time_kernel(amg_handle h, int32_t which, int32_t reps, void* hip_
 
 /*
  * A request loop over independent systems A u = f of uneven sizes (section 3:
- * the hierarchy depends only on A, is built on the CPU and then lives on the
- * backend).  Submitted requests are set up by `setup_threads` host worker
- * threads, placed in a device pool of hbm_budget_bytes (allocated once here;
- * a request whose footprint exceeds the budget fails with AMG_ERR_OOM) and
+ * the hierarchy depends only on A, is set up once and then lives on the
+ * backend).  Submitted requests are set up by `setup_threads` worker
+ * threads (device steps on each worker's own stream, their temporaries drawn
+ * from the budget without waiting; a step the budget cannot cover at that
+ * moment runs on the host), placed in a device pool of hbm_budget_bytes
+ * (allocated once here; a request whose footprint exceeds the budget fails
+ * with AMG_ERR_OOM) and
  * admitted into one of max_slots (1..64) live slots at an iteration
  * boundary.  Each amg_server_step admits what is ready, runs check_every PCG
  * iterations of every live solve in one captured graph of batched kernels
