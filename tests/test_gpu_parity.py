@@ -297,6 +297,23 @@ def test_single_level_is_exact():
         S.release()
 
 
+@pytest.mark.parametrize("n", [1, 2, 3])
+@pytest.mark.parametrize("solver", ["cg", "bicgstab", "gmres"])
+def test_tiny_systems(n, solver):
+    """Degenerate sizes: the whole matrix is the coarsest level (dense inverse);
+    every solver returns A^-1 f after one iteration."""
+    A = problems.tridiag1d(n)
+    f = np.arange(1.0, n + 1.0)
+    S = amg.Solver(A, solver=solver)
+    assert S.nlevels == 1
+    announce("tiny system", n, solver)
+    x, info = S.solve(dev(f))
+    xr = np.linalg.solve(A.to_scipy().toarray(), f)
+    assert info["status"] == 0 and info["iters"] == 1
+    assert np.max(np.abs(host(x) - xr)) <= 1e-14 * np.max(np.abs(xr))
+    S.release()
+
+
 @pytest.mark.parametrize("solver", ["cg", "gmres"])
 def test_exact_initial_guess_needs_no_iteration(solver):
     A, _ = _problem("poisson20")

@@ -28,10 +28,10 @@ def request(n, seed):
     return A, problems.rhs_ones(A.n)
 
 
-def serve(reqs, budget=2 << 30, slots=8, threads=4, timeout=120, together=False):
+def serve(reqs, budget=2 << 30, slots=8, threads=4, timeout=120, together=False, **params):
     """Serve the requests; with `together`, wait until all are set up so that
     they are admitted in one step and run in one batch."""
-    srv = amg.Server(budget, max_slots=slots, setup_threads=threads)
+    srv = amg.Server(budget, max_slots=slots, setup_threads=threads, **params)
     for rid, A, f in reqs:
         srv.submit(rid, A, f)
     if together:
@@ -51,8 +51,8 @@ def serve(reqs, budget=2 << 30, slots=8, threads=4, timeout=120, together=False)
     return got, max_live
 
 
-def single(A, f):
-    S = amg.Solver(A, precision="mixed")
+def single(A, f, **params):
+    S = amg.Solver(A, **{"precision": "mixed", **params})
     x, info = S.solve(torch.tensor(f, device="cuda"))
     S.release()
     return x.cpu().numpy(), info
@@ -103,3 +103,21 @@ def test_request_larger_than_budget_fails_cleanly():
     got, _ = serve([(1, *small), (2, *big)], budget=24 << 20, slots=2, threads=2)
     assert got[1][3] == 0
     assert got[2][3] == -5  # AMG_ERR_OOM: can never fit
+
+
+@pytest.mark.parametrize("params", [{"relax": "jacobi"}, {"precision": "fp64"}])
+def test_served_results_equal_single_solves_other_settings(params):
+    """Damped Jacobi smoothing and the FP64 V-cycle, served in one batch, give
+    bitwise the single-solve results."""
+    sizes = [18, 23, 16, 21]
+    reqs = [(i, *request(n, 10500 + i)) for i, n in enumerate(sizes)]
+    announce("serving", params)
+    got, max_live = serve(reqs, together=True, **params)
+    assert max_live == len(reqs)
+    for rid, A, f in reqs:
+        x_s, info_s = single(A, f, **params)
+        _, x, info, status, _ = got[rid]
+        assert status == 0, (rid, status)
+        assert info["iters"] == info_s["iters"]
+        assert np.array_equal(x, x_s), rid
+        assert true_rel_residual(A, x, f) <= 1e-8
