@@ -71,10 +71,16 @@ class DevArena {
   T* get(size_t count) {
     return static_cast<T*>(raw(count * sizeof(T)));
   }
+  // Copies count elements from host memory and waits for the copy: the source
+  // is usually a pageable temporary of the caller, which an exception from a
+  // later allocation (out of memory) would free while the copy still reads it.
   template <class T>
   T* upload(const T* host, size_t count) {
     T* d = get<T>(count);
-    if (count) AMG_HIP(hipMemcpyAsync(d, host, count * sizeof(T), hipMemcpyHostToDevice, stream_));
+    if (count) {
+      AMG_HIP(hipMemcpyAsync(d, host, count * sizeof(T), hipMemcpyHostToDevice, stream_));
+      AMG_HIP(hipStreamSynchronize(stream_));
+    }
     return d;
   }
   size_t bytes() const { return bytes_; }

@@ -414,10 +414,15 @@ __global__ void __launch_bounds__(256) prolongator_finish_kernel(DMat C, const i
 
 int grid_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096))); }
 
+// Waits for the copy: h may be a local of a step that a later allocation
+// failure unwinds, and a copy still pending would then write freed memory.
 template <class T>
 void download(std::vector<T>& h, const T* d, size_t n, hipStream_t s) {
   h.resize(n);
-  if (n) AMG_HIP(hipMemcpyAsync(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+  if (n) {
+    AMG_HIP(hipMemcpyAsync(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+  }
 }
 
 class DeviceSetupAccel final : public SetupAccel {

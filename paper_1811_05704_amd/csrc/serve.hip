@@ -227,6 +227,7 @@ struct amg_server_s {
   bool stopping = false;
   int setting_up = 0;
   size_t reserved = 0;  // budget bytes held by requests being placed, waiting or live
+  size_t transient = 0;  // part of `reserved` held by setup temporaries
 
   std::vector<amg::Request*> slots;
   amg::KState* states = nullptr;        // device, one per slot
@@ -373,10 +374,12 @@ void capture_graph(amg_server_s& V, int depth) {
 }
 
 // Host worker: build the hierarchy, place it in the pool, upload f.
-// Allocator for setup temporaries (the Galerkin products): memory from the
-// pool, reserved against the budget without waiting.  An allocation the
-// unreserved budget cannot cover fails at once, and that product is then
-// formed on the host; so no worker waits for memory while holding some.
+// Allocator for setup temporaries (the device setup steps): memory from the
+// pool, reserved against the budget without waiting.  An allocation that the
+// unreserved budget cannot cover, or that would take setup temporaries past a
+// quarter of the budget (placements keep the rest), fails at once, and that
+// step then runs on the host; so no worker waits for memory while holding
+// some.
 class TransientAlloc {
  public:
   explicit TransientAlloc(amg_server_s* V) : V_(V) {}
@@ -389,8 +392,9 @@ class TransientAlloc {
     bytes = (bytes + 255) & ~size_t(255);
     {
       std::lock_guard<std::mutex> lk(V->mu);
-      if (V->reserved + bytes > V->pool->size()) return nullptr;
+      if (V->reserved + bytes > V->pool->size() || V->transient + bytes > V->pool->size() / 4) return nullptr;
       V->reserved += bytes;
+      V->transient += bytes;
     }
     void* p = V->pool->alloc(bytes);
     if (!p) {
@@ -413,6 +417,7 @@ class TransientAlloc {
     {
       std::lock_guard<std::mutex> lk(V_->mu);
       V_->reserved -= bytes;
+      V_->transient -= bytes;
     }
     V_->cv_mem.notify_all();
   }
