@@ -227,7 +227,6 @@ struct amg_server_s {
   bool stopping = false;
   int setting_up = 0;
   size_t reserved = 0;  // budget bytes held by requests being placed, waiting or live
-  size_t transient = 0;  // part of `reserved` held by setup temporaries
 
   std::vector<amg::Request*> slots;
   amg::KState* states = nullptr;        // device, one per slot
@@ -376,10 +375,10 @@ void capture_graph(amg_server_s& V, int depth) {
 // Host worker: build the hierarchy, place it in the pool, upload f.
 // Allocator for setup temporaries (the device setup steps): memory from the
 // pool, reserved against the budget without waiting.  An allocation that the
-// unreserved budget cannot cover, or that would take setup temporaries past a
-// quarter of the budget (placements keep the rest), fails at once, and that
-// step then runs on the host; so no worker waits for memory while holding
-// some.
+// unreserved budget cannot cover fails at once, and that step then runs on
+// the host; so no worker waits for memory while holding some.  (Holding the
+// temporaries to a share of the budget was measured to slow serving: more
+// steps then run on the host.)
 class TransientAlloc {
  public:
   explicit TransientAlloc(amg_server_s* V) : V_(V) {}
@@ -392,9 +391,8 @@ class TransientAlloc {
     bytes = (bytes + 255) & ~size_t(255);
     {
       std::lock_guard<std::mutex> lk(V->mu);
-      if (V->reserved + bytes > V->pool->size() || V->transient + bytes > V->pool->size() / 4) return nullptr;
+      if (V->reserved + bytes > V->pool->size()) return nullptr;
       V->reserved += bytes;
-      V->transient += bytes;
     }
     void* p = V->pool->alloc(bytes);
     if (!p) {
@@ -417,7 +415,6 @@ class TransientAlloc {
     {
       std::lock_guard<std::mutex> lk(V_->mu);
       V_->reserved -= bytes;
-      V_->transient -= bytes;
     }
     V_->cv_mem.notify_all();
   }
