@@ -120,13 +120,16 @@ size_t coarse_transient(const HostHierarchy& H) {
 
 size_t footprint(const HostHierarchy& H, const amg_params& p) {
   const size_t vs = p.precision == AMG_MIXED ? 4 : 8;
-  auto csr = [&](const Csr& M, size_t v) { return (M.rows + 1) * 4 + M.nnz() * (4 + v) + 4096; };
+  // row pointers, columns, values, the stream schedule (at most one block per
+  // row) and the allocator's rounding
+  auto csr = [&](const Csr& M, size_t v) { return (M.rows + 1) * 4 + M.nnz() * (4 + v) + (M.rows + 2) * 4 + 1024; };
   size_t b = 0;
   const HostLevel& f = H.levels[0];
   b += csr(f.A, 8);
   for (size_t l = 0; l + 1 < H.levels.size(); ++l) {
     const HostLevel& L = H.levels[l];
-    if (l > 0 || p.precision == AMG_MIXED) b += csr(L.A, vs);
+    if (l > 0) b += csr(L.A, vs);
+    else if (p.precision == AMG_MIXED) b += L.A.nnz() * vs + (L.A.rows + 2) * 4 + 512;  // pattern shared with the FP64 copy
     b += csr(L.P, vs) + csr(L.R, vs);
     b += L.A.rows * vs * 7;
     if (l == 0) b += L.A.nnz() * vs + 4096;  // A diag(m) values of level 1

@@ -517,7 +517,8 @@ inline void upload_levels(amg_solver& S, DevHierarchy<T>& H) {
     if constexpr (std::is_same<T, double>::value) {
       d.A = (l == 0) ? S.A0 : upload_csr<T>(ar, hl.A);
     } else {
-      d.A = upload_csr<T>(ar, hl.A);
+      // level 1 shares its pattern with the FP64 fine operator
+      d.A = (l == 0) ? upload_values_like<T>(ar, S.A0, hl.A) : upload_csr<T>(ar, hl.A);
     }
     d.P = upload_csr<T>(ar, hl.P);
     d.R = upload_csr<T>(ar, hl.R);
