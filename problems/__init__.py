@@ -17,3 +17,9 @@ from .grids import (  # noqa: F401
     rhs_uniform,
     tridiag1d,
 )
+from .irregular import (  # noqa: F401
+    anisotropic3d,
+    decoupled_boundary,
+    poisson3d_27,
+    random_laplacian,
+)

@@ -44,12 +44,23 @@ def _problem(name):
     if name == "convection24":
         g = problems.gaussian_field(24, 2.0, 8.0, 1)
         return problems.diffusion3d(24, g, velocity=(50.0, 25.0, 12.5)), {"relax": "jacobi"}
+    # other structures: 27-point rows (4 lanes per row on level 1), weak
+    # z-couplings dropped by the strength test, isolated identity rows, and an
+    # irregular graph whose hub rows are longer than an FP64 stream block
+    if name == "poisson27-16":
+        return problems.poisson3d_27(16), {"eps_strong": 0.02}
+    if name == "aniso20":
+        return problems.anisotropic3d(20, 1e-3), {}
+    if name == "decoupled14":
+        return problems.decoupled_boundary(14), {}
+    if name == "graph60k":
+        return problems.random_laplacian(60000, seed=2), {}
     raise KeyError(name)
 
 
 def _oracle_params(kw):
     keys = ("solver", "relax", "npre", "npost", "coarse_enough", "max_iter", "tol", "max_levels",
-            "cheb_degree", "cheb_ratio", "gmres_m")
+            "cheb_degree", "cheb_ratio", "gmres_m", "eps_strong", "jacobi_omega")
     return oracle.Params(**{k: v for k, v in kw.items() if k in keys})
 
 
@@ -78,6 +89,12 @@ VCYCLE_CASES = [
     ("poisson20", {"relax": "chebyshev", "npre": 0, "npost": 1}),
     ("poisson20", {"relax": "chebyshev", "npre": 1, "npost": 0}),
     ("poisson20", {"relax": "chebyshev", "coarse_enough": 50}),
+    ("poisson27-16", {}),
+    ("aniso20", {}),
+    ("decoupled14", {}),
+    ("decoupled14", {"relax": "jacobi"}),
+    ("graph60k", {}),
+    ("graph60k", {"relax": "chebyshev"}),
 ]
 
 
@@ -115,6 +132,10 @@ MIXED_CASES = [
     ("poisson32", {"relax": "chebyshev"}),
     ("diffusion24", {"relax": "chebyshev", "cheb_degree": 2}),
     ("poisson20", {"relax": "chebyshev", "cheb_degree": 1, "npre": 2, "npost": 2}),
+    ("poisson27-16", {}),
+    ("aniso20", {}),
+    ("decoupled14", {}),
+    ("graph60k", {}),
 ]
 
 
@@ -156,6 +177,12 @@ SOLVE_CASES = [
     ("convection24", "ones", {"solver": "gmres", "gmres_m": 4}),
     ("diffusion24", "ones", {"solver": "gmres", "gmres_m": 2}),
     ("diffusion24", "uniform", {"solver": "gmres", "relax": "chebyshev", "check_every": 1}),
+    ("poisson27-16", "uniform", {}),
+    ("aniso20", "ones", {}),
+    ("aniso20", "uniform", {"solver": "gmres"}),
+    ("decoupled14", "ones", {"relax": "jacobi"}),
+    ("graph60k", "uniform", {}),
+    ("graph60k", "ones", {"solver": "bicgstab", "precision": "mixed"}),
 ]
 
 
@@ -215,7 +242,8 @@ def test_solve_with_coarsest_order_895():
         S.release()
 
 
-@pytest.mark.parametrize("name", ["poisson32", "diffusion24", "convection24", "convection40"])
+@pytest.mark.parametrize("name", ["poisson32", "diffusion24", "convection24", "convection40", "poisson27-16",
+                                  "aniso20", "decoupled14", "graph60k"])
 def test_device_galerkin_matches_host_setup(name):
     """The device setup runs the strength graph, the smoothed prolongator and
     the Galerkin products on the GPU; every level must be bit-identical to

@@ -52,13 +52,21 @@ def _cases():
         ("diffusion24-jacobi", problems.diffusion3d(24, g), "jacobi"),
         ("convection24", problems.diffusion3d(24, g, velocity=(50.0, 25.0, 12.5)), "jacobi"),
         ("diffusion24-chebyshev", problems.diffusion3d(24, g), "chebyshev"),
+        # other structures: 27-point rows, weak (dropped) couplings, isolated
+        # nodes, irregular rows with hubs longer than a stream block
+        ("poisson27-16", problems.poisson3d_27(16), "spai0", {"eps_strong": 0.02}),
+        ("anisotropic20", problems.anisotropic3d(20, 1e-3), "spai0"),
+        ("decoupled14", problems.decoupled_boundary(14), "jacobi"),
+        ("graph60k", problems.random_laplacian(60000, seed=2), "spai0"),
     ]
 
 
-@pytest.mark.parametrize("name,A,relax", _cases(), ids=[c[0] for c in _cases()])
-def test_hierarchy_matches_oracle(name, A, relax):
-    H = amg.HostHierarchy(A, relax=relax)
-    h = oracle.setup(A, oracle.Params(relax=relax))
+@pytest.mark.parametrize("case", _cases(), ids=[c[0] for c in _cases()])
+def test_hierarchy_matches_oracle(case):
+    name, A, relax = case[:3]
+    kw = case[3] if len(case) > 3 else {}
+    H = amg.HostHierarchy(A, relax=relax, **kw)
+    h = oracle.setup(A, oracle.Params(relax=relax, **kw))
     assert H.nlevels == h.nlevels
     for l in range(H.nlevels):
         Al = H.level_scipy(l, "A")

@@ -110,3 +110,80 @@ def test_rhs_generators():
     u = problems.rhs_uniform(1000, seed=0)
     assert np.array_equal(u, np.random.default_rng(0).random(1000))
     assert u.min() >= 0.0 and u.max() < 1.0
+
+
+def _check_csr_spd(A, dense=True):
+    """Sorted unique columns, diagonal stored and positive, exact symmetry,
+    weak diagonal dominance (with the matrices here: SPD)."""
+    assert A.row_ptr.dtype == np.int64 and A.col.dtype == np.int32
+    assert A.row_ptr[0] == 0 and np.all(np.diff(A.row_ptr) >= 1)
+    for i in range(A.n):
+        c = A.col[A.row_ptr[i]:A.row_ptr[i + 1]]
+        assert np.all(np.diff(c) > 0)
+        assert i in c
+    S = A.to_scipy()
+    assert (S != S.T).nnz == 0
+    d = S.diagonal()
+    assert np.all(d > 0)
+    off = np.asarray(abs(S).sum(axis=1)).ravel() - d
+    assert np.all(off <= d + 1e-12)
+    if dense:
+        assert np.linalg.eigvalsh(S.toarray()).min() > 0
+
+
+def test_poisson27_stencil():
+    N = 5
+    A = problems.poisson3d_27(N)
+    _check_csr_spd(A)
+    rl = np.diff(A.row_ptr)
+    # interior rows hold the full 3x3x3 box, corners 2x2x2
+    assert rl.max() == 27 and rl.min() == 8
+    assert A.nnz == (3 * N - 2) ** 3  # sum over axes of (3N - 2) per direction
+    D = A.to_scipy().toarray()
+    assert np.all(np.diag(D) == 26.0)
+    assert set(np.unique(D[D != 0]).tolist()) == {-1.0, 26.0}
+
+
+def test_anisotropic_couplings():
+    N, eps = 6, 1e-3
+    A = problems.anisotropic3d(N, eps)
+    _check_csr_spd(A)
+    D = A.to_scipy().toarray()
+    i, j = np.nonzero(D - np.diag(np.diag(D)))
+    gap = np.abs(i - j)
+    assert set(gap.tolist()) == {1, N, N * N}
+    assert np.all(D[i[gap == N * N], j[gap == N * N]] == -eps)
+    assert np.all(D[i[gap < N * N], j[gap < N * N]] == -1.0)
+    assert np.all(np.diag(D) == 4.0 + 2.0 * eps)
+
+
+def test_decoupled_boundary_rows_are_identity():
+    N = 4
+    A = problems.decoupled_boundary(N)
+    _check_csr_spd(A)
+    M = N + 2
+    assert A.n == M**3
+    rl = np.diff(A.row_ptr)
+    # (N+2)^3 - N^3 boundary rows hold only their unit diagonal
+    assert int(np.sum(rl == 1)) == M**3 - N**3
+    D = A.to_scipy().toarray()
+    idx = np.arange(A.n)
+    ii, jj, kk = idx % M, (idx // M) % M, idx // (M * M)
+    interior = (ii > 0) & (ii < M - 1) & (jj > 0) & (jj < M - 1) & (kk > 0) & (kk < M - 1)
+    assert np.all(np.diag(D)[~interior] == 1.0)
+    # the interior block is the 7-point Poisson matrix of N^3
+    P = problems.poisson3d(N).to_scipy().toarray()
+    assert np.array_equal(D[np.ix_(interior, interior)], P)
+
+
+def test_random_laplacian_structure():
+    A = problems.random_laplacian(3000, hub_degree=1200, seed=5)
+    _check_csr_spd(A, dense=False)
+    S = A.to_scipy()
+    rl = np.diff(A.row_ptr)
+    assert rl.max() > 1024  # some rows longer than an FP64 stream block
+    # row sums equal the shift exactly up to rounding (Laplacian + shift I)
+    assert np.allclose(np.asarray(S.sum(axis=1)).ravel(), 0.05, atol=1e-9)
+    B = problems.random_laplacian(3000, hub_degree=1200, seed=5)
+    assert np.array_equal(A.val, B.val) and np.array_equal(A.col, B.col)
+
