@@ -121,3 +121,29 @@ def test_served_results_equal_single_solves_other_settings(params):
         assert info["iters"] == info_s["iters"]
         assert np.array_equal(x, x_s), rid
         assert true_rel_residual(A, x, f) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_mix_of_structures_equals_single_solves(precision):
+    """Requests of different structure in one batch: 27-point rows (four lanes
+    per row), weak couplings dropped, isolated identity rows, and an irregular
+    graph with hub rows longer than an FP64 stream block.  Every result is
+    bitwise the single-solve result."""
+    reqs = [
+        (0, problems.poisson3d_27(16), problems.rhs_uniform(16**3, 1)),
+        (1, problems.anisotropic3d(20, 1e-3), problems.rhs_ones(20**3)),
+        (2, problems.decoupled_boundary(14), problems.rhs_ones(16**3)),
+        (3, problems.random_laplacian(60000, seed=2), problems.rhs_uniform(60000, 2)),
+        (4, *request(19, 10600)),
+    ]
+    params = {"precision": precision, "eps_strong": 0.02}
+    announce("serving mix of structures", precision)
+    got, max_live = serve(reqs, together=True, **params)
+    assert max_live == len(reqs)
+    for rid, A, f in reqs:
+        x_s, info_s = single(A, f, **params)
+        _, x, info, status, _ = got[rid]
+        assert status == 0, (rid, status)
+        assert info["iters"] == info_s["iters"], rid
+        assert np.array_equal(x, x_s), rid
+        assert true_rel_residual(A, x, f) <= 1e-8
