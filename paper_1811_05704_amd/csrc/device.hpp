@@ -196,12 +196,14 @@ DevCsr<T> upload_csr(DevArena& ar, const Csr& M, int force_kind = -1) {
   if (p32.empty()) p32.assign(1, 0);
   d.ptr = ar.upload(p32.data(), p32.size());
   const size_t nz = M.col.size();
-  std::vector<int32_t> c(M.col.begin(), M.col.end());
-  if (c.empty()) c.assign(1, 0);
-  d.col = ar.upload(c.data(), c.size());
-  std::vector<T> v(std::max<size_t>(nz, 1), T(0));
-  for (size_t k = 0; k < nz; ++k) v[k] = static_cast<T>(M.val[k]);  // FP32: round to nearest
-  d.val = ar.upload(v.data(), v.size());
+  d.col = ar.upload(M.col.data(), nz);  // an empty matrix still gets (unread) storage
+  if constexpr (std::is_same<T, double>::value) {
+    d.val = ar.upload(M.val.data(), nz);
+  } else {
+    std::vector<T> v(nz);
+    for (size_t k = 0; k < nz; ++k) v[k] = static_cast<T>(M.val[k]);  // FP32: round to nearest
+    d.val = ar.upload(v.data(), nz);
+  }
   Schedule s = make_schedule<T>(M, force_kind);
   d.kind = s.kind;
   d.lanes = s.lanes;
@@ -225,9 +227,9 @@ DevCsr<T> upload_values_like(DevArena& ar, const DevCsr<U>& like, const Csr& M) 
   d.ptr = like.ptr;
   d.col = like.col;
   const size_t nz = M.col.size();
-  std::vector<T> v(std::max<size_t>(nz, 1), T(0));
+  std::vector<T> v(nz);
   for (size_t k = 0; k < nz; ++k) v[k] = static_cast<T>(M.val[k]);  // FP32: round to nearest
-  d.val = ar.upload(v.data(), v.size());
+  d.val = ar.upload(v.data(), nz);
   Schedule s = make_schedule<T>(M, -1);
   d.kind = s.kind;
   d.lanes = s.lanes;

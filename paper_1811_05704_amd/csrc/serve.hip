@@ -112,10 +112,12 @@ class DevicePool {
 // Device bytes a request will occupy (hierarchy in the V-cycle's precision,
 // the FP64 fine matrix, dense coarse inverse, vectors, partials), rounded up
 // per allocation; used to reject requests that can never fit.
-// Device bytes held only during setup: the coarse LU factors and pivots.
+// Device bytes held only during setup: the coarse matrix in CSR form, its
+// dense LU factors and pivots.
 size_t coarse_transient(const HostHierarchy& H) {
-  const size_t nL = H.levels.back().A.rows;
-  return nL * nL * 8 + nL * 24 + 4 * 256;
+  const Csr& AL = H.levels.back().A;
+  const size_t nL = AL.rows;
+  return nL * nL * 8 + nL * 24 + (nL + 1) * 4 + static_cast<size_t>(AL.nnz()) * 12 + 8 * 256;
 }
 
 size_t footprint(const HostHierarchy& H, const amg_params& p) {

@@ -440,10 +440,23 @@ static __global__ void __launch_bounds__(kVecBS) identity_kernel(int n, double* 
     M[k] = (k / n == k % n) ? 1.0 : 0.0;
 }
 
+// Row i of the dense row-major n x n matrix M from row i of a CSR matrix:
+// zeros, then the stored entries (one workgroup per row; columns unique).
+static __global__ void __launch_bounds__(kVecBS) dense_rows_kernel(int n, const int32_t* ptr, const int32_t* col,
+                                                                   const double* val, double* M) {
+  const int i = blockIdx.x;
+  double* row = M + static_cast<int64_t>(i) * n;
+  for (int j = threadIdx.x; j < n; j += kVecBS) row[j] = 0.0;
+  __syncthreads();
+  for (int e = ptr[i] + threadIdx.x; e < ptr[i + 1]; e += kVecBS) row[col[e]] = val[e];
+}
+
 // Dense inverse of the coarsest operator on the device (FP64): LU with
 // partial pivoting of a transient copy (rocsolver getrf), then the n
-// triangular solves LU X = I (getrs).  The row-major host matrix read as
-// column-major is A^T, and inv(A^T) read back as row-major is inv(A).
+// triangular solves LU X = I (getrs).  The dense copy is expanded on the
+// device from the CSR matrix (the host never holds the n^2 array).  Its
+// row-major layout read as column-major is A^T, and inv(A^T) read back as
+// row-major is inv(A).
 // rocsolver's in-place getri is not used: on the ROCm 7.2 / gfx950 stack it
 // returns a wrong inverse for some orders (for example 255, 511, 895, 1023;
 // getrf and getrs are correct there), so the inverse is also checked once:
@@ -451,12 +464,17 @@ static __global__ void __launch_bounds__(kVecBS) identity_kernel(int n, double* 
 inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, const amg_allocator* alloc,
                            rocblas_handle shared = nullptr) {
   const int32_t n = static_cast<int32_t>(AL.rows);
-  std::vector<double> dense(static_cast<size_t>(n) * n, 0.0);
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t e = AL.ptr[i]; e < AL.ptr[i + 1]; ++e) dense[static_cast<size_t>(i) * n + AL.col[e]] = AL.val[e];
   S.Ainv = S.arena->get<double>(static_cast<size_t>(n) * n);
-  DevArena tmp(alloc, stream);  // LU factors, pivots: freed on return
-  double* lu = tmp.upload(dense.data(), dense.size());
+  DevArena tmp(alloc, stream);  // CSR copy, LU factors, pivots: freed on return
+  double* lu = tmp.get<double>(static_cast<size_t>(n) * n);
+  {
+    const std::vector<int32_t> p32(AL.ptr.begin(), AL.ptr.end());
+    const int32_t* dptr = tmp.upload(p32.data(), p32.size());
+    const int32_t* dcol = tmp.upload(AL.col.data(), AL.col.size());
+    const double* dval = tmp.upload(AL.val.data(), AL.val.size());
+    dense_rows_kernel<<<n, kVecBS, 0, stream>>>(n, dptr, dcol, dval, lu);
+    AMG_LAUNCHED();
+  }
   rocblas_int* ipiv = tmp.get<rocblas_int>(n);
   rocblas_int* dinfo = tmp.get<rocblas_int>(1);
   identity_kernel<<<std::min<int64_t>((static_cast<int64_t>(n) * n + kVecBS - 1) / kVecBS, 65536), kVecBS, 0,
