@@ -372,8 +372,8 @@ def main():
                          "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     if args.serving:
