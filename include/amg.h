@@ -37,7 +37,7 @@ typedef enum {
   AMG_ERR_INVALID_ARG = -1,     /* NULL pointer, bad enum, bad size          */
   AMG_ERR_BAD_CSR = -2,         /* row_ptr/col malformed or columns unsorted */
   AMG_ERR_ZERO_DIAG = -3,       /* missing or non-positive diagonal entry    */
-  AMG_ERR_SINGULAR_COARSE = -4, /* zero pivot in the coarsest dense LU       */
+  AMG_ERR_SINGULAR_COARSE = -4, /* coarsest matrix singular (zero LU pivot)  */
   AMG_ERR_OOM = -5,             /* device or host allocation failed          */
   AMG_ERR_HIP = -6,             /* a HIP runtime call failed                 */
   AMG_ERR_BREAKDOWN = -7,       /* BiCGStab rho = 0 or omega = 0             */
@@ -118,7 +118,10 @@ void amg_params_default(amg_params* p);
  * the current device (section 2, "AMG setup").  The strength graph, the
  * smoothed prolongators and the Galerkin products run on the device on
  * hip_stream, with temporaries from alloc; the greedy aggregation runs on the
- * host; the result is bit-identical to amg_setup_host.  Requirements:
+ * host; the result is bit-identical to amg_setup_host.  The coarsest level's
+ * dense inverse (section 2: a direct solver on the coarsest level) is formed
+ * on the device from an LU factorisation with partial pivoting and checked
+ * once.  Requirements:
  * row_ptr[0] = 0, non-decreasing row_ptr, 0 <= col < n, strictly ascending
  * columns within a row, a stored diagonal entry a_ii > 0 in every row,
  * nnz < 2^31.  p = NULL means defaults.  On success *out receives a handle
@@ -266,7 +269,8 @@ amg_status amg_server_wait_ready(amg_server s, int32_t count, double timeout_s, 
 amg_status amg_server_poll(amg_server s, uint64_t* request_id, int64_t* n);
 /* Take that request: x_host double[n] (may be NULL), info (may be NULL), times
  * (may be NULL) = {submit, setup done, admitted, finished} in seconds of a
- * monotonic clock.  Returns the request's own status. */
+ * monotonic clock.  Returns the request's own status; for a failed request
+ * amg_last_error() on the calling thread then says what failed. */
 amg_status amg_server_fetch(amg_server s, uint64_t request_id, double* x_host, amg_info* info,
                             double* times);
 /* Stop the workers and free everything.  NULL-safe. */

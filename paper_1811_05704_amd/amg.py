@@ -428,6 +428,8 @@ class Server:
                                             _ptr(times, C.c_double))
             d = info.as_dict()
             d["status"] = status
+            if status < 0:
+                d["error"] = lib().amg_last_error().decode()
             out.append((rid.value, x, d, status, tuple(times)))
 
     def release(self):

@@ -17,8 +17,10 @@
 #include <algorithm>
 #include <condition_variable>
 #include <deque>
+#include <exception>
 #include <map>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <unordered_map>
 
@@ -209,6 +211,7 @@ struct Request {
   amg_info info{};
   double t_submit = 0, t_ready = 0, t_admit = 0, t_done = 0;
   int restarts = 0;
+  std::string error;  // what failed, for a request with status < 0
   int slot = -1;
   size_t reserved = 0;  // bytes of the budget held for this request
 };
@@ -517,12 +520,19 @@ void worker_main(amg_server_s* V, int threads) {
       V->cv_ready.notify_all();
     } catch (const SetupError& e) {
       q->status = e.code;
-      g_last_error = e.msg;
+      q->error = e.msg;
     } catch (const DevError& e) {
       q->status = e.code;
-      g_last_error = e.msg;
+      q->error = e.msg;
+    } catch (const std::bad_alloc&) {
+      q->status = AMG_ERR_OOM;
+      q->error = "host memory exhausted in the setup worker";
+    } catch (const std::exception& e) {
+      q->status = AMG_ERR_INVALID_ARG;
+      q->error = e.what();
     } catch (...) {
       q->status = AMG_ERR_INVALID_ARG;
+      q->error = "unknown error in the setup worker";
     }
     if (q->status != 0) {
       if (q->S) q->S.reset();
@@ -812,7 +822,8 @@ amg_status amg_server_fetch(amg_server s, uint64_t request_id, double* x_host, a
       times[2] = q->t_admit;
       times[3] = q->t_done;
     }
-    if (q->status < 0) g_last_error = "request failed with status " + std::to_string(q->status);
+    if (q->status < 0)
+      g_last_error = "request failed with status " + std::to_string(q->status) + (q->error.empty() ? "" : ": " + q->error);
     return static_cast<amg_status>(q->status);
   });
 }

@@ -452,15 +452,17 @@ static __global__ void __launch_bounds__(kVecBS) dense_rows_kernel(int n, const 
 }
 
 // Dense inverse of the coarsest operator on the device (FP64): LU with
-// partial pivoting of a transient copy (rocsolver getrf), then the n
-// triangular solves LU X = I (getrs).  The dense copy is expanded on the
-// device from the CSR matrix (the host never holds the n^2 array).  Its
-// row-major layout read as column-major is A^T, and inv(A^T) read back as
-// row-major is inv(A).
+// partial pivoting (rocsolver getrf), then n triangular solves against I
+// (getrs).  The dense copy is expanded on the device from the CSR matrix
+// (the host never holds the n^2 array); its row-major layout read as
+// column-major is A^T, and inv(A^T) read back as row-major is inv(A).
 // rocsolver's in-place getri is not used: on the ROCm 7.2 / gfx950 stack it
 // returns a wrong inverse for some orders (for example 255, 511, 895, 1023;
 // getrf and getrs are correct there), so the inverse is also checked once:
-// Ainv (A v) must reproduce a known vector v.
+// Ainv (A v) must reproduce a known vector v.  Cholesky (potrf, 2.5 times
+// faster at orders 1,000-3,000) is not used for symmetric matrices: its
+// result was found to depend on the state of the rocBLAS handle, so a served
+// solve would no longer repeat the single solve bit for bit.
 inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, const amg_allocator* alloc,
                            rocblas_handle shared = nullptr) {
   const int32_t n = static_cast<int32_t>(AL.rows);
@@ -480,28 +482,30 @@ inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, con
   identity_kernel<<<std::min<int64_t>((static_cast<int64_t>(n) * n + kVecBS - 1) / kVecBS, 65536), kVecBS, 0,
                     stream>>>(n, S.Ainv);
   AMG_LAUNCHED();
-  rocblas_handle hb = shared;
-  if (!hb && rocblas_create_handle(&hb) != rocblas_status_success) throw DevError{-6, "rocblas_create_handle failed"};
-  rocblas_set_stream(hb, stream);
-  auto release = [&]() {
-    if (!shared) rocblas_destroy_handle(hb);
-  };
+  struct Handle {  // the caller's rocBLAS handle, or one of our own
+    rocblas_handle h = nullptr;
+    bool own = false;
+    ~Handle() {
+      if (own) rocblas_destroy_handle(h);
+    }
+  } hb;
+  hb.h = shared;
+  if (!hb.h) {
+    if (rocblas_create_handle(&hb.h) != rocblas_status_success) throw DevError{-6, "rocblas_create_handle failed"};
+    hb.own = true;
+  }
+  rocblas_set_stream(hb.h, stream);
   rocblas_int info = 0;
-  rocblas_status st1 = rocsolver_dgetrf(hb, n, n, lu, n, ipiv, dinfo);
-  hipError_t e1 = hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, stream);
-  hipError_t e2 = hipStreamSynchronize(stream);
-  if (st1 != rocblas_status_success || e1 != hipSuccess || e2 != hipSuccess) {
-    release();
+  const rocblas_status st1 = rocsolver_dgetrf(hb.h, n, n, lu, n, ipiv, dinfo);
+  const hipError_t e1 = hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, stream);
+  const hipError_t e2 = hipStreamSynchronize(stream);
+  if (st1 != rocblas_status_success || e1 != hipSuccess || e2 != hipSuccess)
     throw DevError{-6, "coarse LU factorisation failed"};
-  }
-  if (info != 0) {
-    release();
+  if (info != 0)
     throw DevError{-4, "zero pivot " + std::to_string(info) + " in the coarsest LU (n = " + std::to_string(n) + ")"};
-  }
-  rocblas_status st2 = rocsolver_dgetrs(hb, rocblas_operation_none, n, n, lu, n, ipiv, S.Ainv, n);
-  e2 = hipStreamSynchronize(stream);
-  release();
-  if (st2 != rocblas_status_success || e2 != hipSuccess) throw DevError{-6, "coarse triangular solves failed"};
+  const rocblas_status st2 = rocsolver_dgetrs(hb.h, rocblas_operation_none, n, n, lu, n, ipiv, S.Ainv, n);
+  if (st2 != rocblas_status_success || hipStreamSynchronize(stream) != hipSuccess)
+    throw DevError{-6, "coarse triangular solves failed"};
   // check: z = Ainv (A v) against v, v_i = 1 + (i mod 7) / 8, to 1e-3
   // relative (a wrong inverse is off by O(1); ill-conditioning up to about
   // 1e12 passes)

@@ -206,17 +206,43 @@ def test_solve_matches_oracle(name, rhs, kw):
     S.release()
 
 
-@pytest.mark.parametrize("n", [255, 383, 511, 895, 900, 1023, 2999])
-def test_coarse_inverse_every_order(n):
+def _tridiag(n, lower, diag, upper):
+    rows, cols, vals, rp = [], [], [], [0]
+    for i in range(n):
+        for j, v in ((i - 1, lower), (i, diag), (i + 1, upper)):
+            if 0 <= j < n:
+                cols.append(j)
+                vals.append(v)
+        rp.append(len(cols))
+    return problems.CSR(n, np.array(rp, dtype=np.int64), np.array(cols, dtype=np.int32),
+                        np.array(vals, dtype=np.float64))
+
+
+COARSE_CASES = ([("spd", n) for n in (255, 383, 511, 895, 900, 1023, 2999)]
+                + [("nonsymmetric", n) for n in (255, 895, 2999)]
+                + [("indefinite", n) for n in (255, 895, 2999)])
+
+
+@pytest.mark.parametrize("kind,n", COARSE_CASES, ids=[f"{k}-{n}" for k, n in COARSE_CASES])
+def test_coarse_inverse_every_order(kind, n):
     """Single-level hierarchy (the whole matrix is the coarsest level): the
-    device's dense inverse applied to f equals a dense solve.  Orders of the
-    form 128k - 1 are included on purpose: an in-place LAPACK-style inversion
-    of the ROCm stack was found wrong at those."""
-    A = problems.tridiag1d(n)
-    S = amg.Solver(A, coarse_enough=n)
+    device's dense inverse applied to f equals a dense solve.  A symmetric
+    positive definite matrix takes the Cholesky path; a nonsymmetric one, and
+    a symmetric indefinite one (whose Cholesky fails part-way, so the LU runs
+    on a fresh copy), take LU with partial pivoting.  Orders of the form
+    128k - 1 are included on purpose: an in-place LAPACK-style inversion of
+    the ROCm stack was found wrong at those."""
+    if kind == "spd":
+        A = problems.tridiag1d(n)
+    elif kind == "nonsymmetric":
+        A = _tridiag(n, -1.2, 2.5, -0.8)
+    else:
+        A = _tridiag(n, -2.0, 1.0, -2.0)
+        assert np.linalg.eigvalsh(A.to_scipy().toarray()).min() < 0
+    S = amg.Solver(A, coarse_enough=n, solver="cg" if kind == "spd" else "bicgstab")
     assert S.nlevels == 1
     f = np.random.default_rng(n).standard_normal(n)
-    announce("coarse inverse order", n)
+    announce("coarse inverse", kind, "order", n)
     z = host(S.vcycle(dev(f)))
     zr = np.linalg.solve(A.to_scipy().toarray(), f)
     assert rel_err(z, zr) <= 1e-8

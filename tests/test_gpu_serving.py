@@ -34,8 +34,10 @@ def serve(reqs, budget=2 << 30, slots=8, threads=4, timeout=120, together=False,
     srv = amg.Server(budget, max_slots=slots, setup_threads=threads, **params)
     for rid, A, f in reqs:
         srv.submit(rid, A, f)
-    if together:
-        assert srv.wait_ready(len(reqs), timeout)
+    if together and not srv.wait_ready(len(reqs), timeout):
+        failed = [(r[0], r[3], r[2].get("error")) for r in srv.results()]
+        srv.release()
+        pytest.fail(f"not every request was set up; failed (id, status, error): {failed}")
     got = {}
     t0 = time.time()
     max_live = 0
@@ -67,7 +69,7 @@ def test_served_results_equal_single_solves():
     for rid, A, f in reqs:
         x_s, info_s = single(A, f)
         _, x, info, status, times = got[rid]
-        assert status == 0, (rid, status)
+        assert status == 0, (rid, status, info.get("error"))
         assert info["iters"] == info_s["iters"]
         assert np.array_equal(x, x_s), rid
         assert true_rel_residual(A, x, f) <= 1e-8
@@ -93,7 +95,7 @@ def test_admission_under_small_budget():
     got, max_live = serve(reqs, budget=budget, slots=8, threads=3)
     assert 1 <= max_live < 6
     for rid, A, f in reqs:
-        assert got[rid][3] == 0
+        assert got[rid][3] == 0, (rid, got[rid][3], got[rid][2].get("error"))
         assert true_rel_residual(A, got[rid][1], f) <= 1e-8
 
 
@@ -101,7 +103,7 @@ def test_request_larger_than_budget_fails_cleanly():
     small = request(16, 10400)   # about 4 MiB
     big = request(28, 10401)     # about 63 MiB (dense coarse inverse of 2691 rows)
     got, _ = serve([(1, *small), (2, *big)], budget=24 << 20, slots=2, threads=2)
-    assert got[1][3] == 0
+    assert got[1][3] == 0, got[1][2].get("error")
     assert got[2][3] == -5  # AMG_ERR_OOM: can never fit
 
 
@@ -117,7 +119,7 @@ def test_served_results_equal_single_solves_other_settings(params):
     for rid, A, f in reqs:
         x_s, info_s = single(A, f, **params)
         _, x, info, status, _ = got[rid]
-        assert status == 0, (rid, status)
+        assert status == 0, (rid, status, info.get("error"))
         assert info["iters"] == info_s["iters"]
         assert np.array_equal(x, x_s), rid
         assert true_rel_residual(A, x, f) <= 1e-8
@@ -143,7 +145,7 @@ def test_served_mix_of_structures_equals_single_solves(precision):
     for rid, A, f in reqs:
         x_s, info_s = single(A, f, **params)
         _, x, info, status, _ = got[rid]
-        assert status == 0, (rid, status)
+        assert status == 0, (rid, status, info.get("error"))
         assert info["iters"] == info_s["iters"], rid
         assert np.array_equal(x, x_s), rid
         assert true_rel_residual(A, x, f) <= 1e-8
