@@ -120,8 +120,10 @@ void amg_params_default(amg_params* p);
  * hip_stream, with temporaries from alloc; the greedy aggregation runs on the
  * host; the result is bit-identical to amg_setup_host.  The coarsest level's
  * dense inverse (section 2: a direct solver on the coarsest level) is formed
- * on the device from an LU factorisation with partial pivoting and checked
- * once.  Requirements:
+ * on the device from an LU factorisation, without pivoting when that matrix
+ * is symmetric to rounding and every pivot comes out positive (positive
+ * definite), with partial pivoting otherwise, and checked once.
+ * Requirements:
  * row_ptr[0] = 0, non-decreasing row_ptr, 0 <= col < n, strictly ascending
  * columns within a row, a stored diagonal entry a_ii > 0 in every row,
  * nnz < 2^31.  p = NULL means defaults.  On success *out receives a handle

@@ -119,7 +119,7 @@ class DevicePool {
 size_t coarse_transient(const HostHierarchy& H) {
   const Csr& AL = H.levels.back().A;
   const size_t nL = AL.rows;
-  return nL * nL * 8 + nL * 24 + (nL + 1) * 4 + static_cast<size_t>(AL.nnz()) * 12 + 8 * 256;
+  return nL * nL * 8 + nL * 24 + (nL + 1) * 4 + static_cast<size_t>(AL.nnz()) * 12 + 10 * 256;
 }
 
 size_t footprint(const HostHierarchy& H, const amg_params& p) {

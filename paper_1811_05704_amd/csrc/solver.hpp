@@ -451,37 +451,86 @@ static __global__ void __launch_bounds__(kVecBS) dense_rows_kernel(int n, const 
   for (int e = ptr[i] + threadIdx.x; e < ptr[i + 1]; e += kVecBS) row[col[e]] = val[e];
 }
 
-// Dense inverse of the coarsest operator on the device (FP64): LU with
-// partial pivoting (rocsolver getrf), then n triangular solves against I
-// (getrs).  The dense copy is expanded on the device from the CSR matrix
-// (the host never holds the n^2 array); its row-major layout read as
-// column-major is A^T, and inv(A^T) read back as row-major is inv(A).
-// rocsolver's in-place getri is not used: on the ROCm 7.2 / gfx950 stack it
-// returns a wrong inverse for some orders (for example 255, 511, 895, 1023;
-// getrf and getrs are correct there), so the inverse is also checked once:
-// Ainv (A v) must reproduce a known vector v.  Cholesky (potrf, 2.5 times
-// faster at orders 1,000-3,000) is not used for symmetric matrices: its
-// result was found to depend on the state of the rocBLAS handle, so a served
-// solve would no longer repeat the single solve bit for bit.
+// Smallest diagonal entry of the dense n x n matrix M (one workgroup, fixed
+// order); a NaN on the diagonal gives -infinity.
+static __global__ void __launch_bounds__(kVecBS) min_diagonal_kernel(int n, const double* M, double* out) {
+  __shared__ double sh[kVecBS];
+  double m = INFINITY;
+  for (int k = threadIdx.x; k < n; k += kVecBS) {
+    const double x = M[static_cast<int64_t>(k) * (n + 1)];
+    m = (x == x) ? fmin(m, x) : -INFINITY;
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kVecBS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Symmetry up to rounding of a CSR matrix with ascending columns:
+// |a_ij - a_ji| <= 1e-12 sqrt(|a_ii a_jj|) for every stored entry (a missing
+// a_ji counts as 0).  A Galerkin product R A P of a symmetric A with R = P^T
+// is symmetric in exact arithmetic; its two triangles differ only by the
+// order in which their sums were rounded.
+inline bool symmetric_to_rounding(const Csr& M) {
+  std::vector<double> d(M.rows, 0.0);
+  for (int64_t i = 0; i < M.rows; ++i)
+    for (int64_t e = M.ptr[i]; e < M.ptr[i + 1]; ++e)
+      if (M.col[e] == i) d[i] = std::fabs(M.val[e]);
+  for (int64_t i = 0; i < M.rows; ++i)
+    for (int64_t e = M.ptr[i]; e < M.ptr[i + 1]; ++e) {
+      const int32_t j = M.col[e];
+      if (j == i) continue;
+      const auto b = M.col.begin() + M.ptr[j], en = M.col.begin() + M.ptr[j + 1];
+      const auto it = std::lower_bound(b, en, static_cast<int32_t>(i));
+      const double aji = (it != en && *it == i) ? M.val[it - M.col.begin()] : 0.0;
+      if (!(std::fabs(M.val[e] - aji) <= 1e-12 * std::sqrt(d[i] * d[j]))) return false;
+    }
+  return true;
+}
+
+// Dense inverse of the coarsest operator on the device (FP64), in two steps:
+// an LU factorisation, then n triangular solves against I (rocsolver getrs).
+// A matrix symmetric to rounding is first factored without pivoting
+// (getrf_npvt, about 3 times faster than getrf at orders 1,000-3,000); that
+// factorisation is kept only if every pivot is positive, which for a
+// symmetric matrix says it is positive definite, where elimination without
+// pivoting is backward stable.  Otherwise, and for every nonsymmetric
+// matrix, a fresh copy is factored with partial pivoting (getrf).  The dense
+// copy is expanded on the device from the CSR matrix (the host never holds
+// the n^2 array); its row-major layout read as column-major is A^T, and
+// inv(A^T) read back as row-major is inv(A).  rocsolver's in-place getri is
+// not used: on the ROCm 7.2 / gfx950 stack it returns a wrong inverse for
+// some orders (for example 255, 511, 895, 1023; getrf and getrs are correct
+// there), so the inverse is also checked once: Ainv (A v) must reproduce a
+// known vector v.  Cholesky (potrf) is not used: run from several threads at
+// once (the serving workers) it does not reproduce its own results.
 inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, const amg_allocator* alloc,
                            rocblas_handle shared = nullptr) {
   const int32_t n = static_cast<int32_t>(AL.rows);
   S.Ainv = S.arena->get<double>(static_cast<size_t>(n) * n);
   DevArena tmp(alloc, stream);  // CSR copy, LU factors, pivots: freed on return
   double* lu = tmp.get<double>(static_cast<size_t>(n) * n);
-  {
-    const std::vector<int32_t> p32(AL.ptr.begin(), AL.ptr.end());
-    const int32_t* dptr = tmp.upload(p32.data(), p32.size());
-    const int32_t* dcol = tmp.upload(AL.col.data(), AL.col.size());
-    const double* dval = tmp.upload(AL.val.data(), AL.val.size());
+  const std::vector<int32_t> p32(AL.ptr.begin(), AL.ptr.end());
+  const int32_t* dptr = tmp.upload(p32.data(), p32.size());
+  const int32_t* dcol = tmp.upload(AL.col.data(), AL.col.size());
+  const double* dval = tmp.upload(AL.val.data(), AL.val.size());
+  auto expand = [&]() {
     dense_rows_kernel<<<n, kVecBS, 0, stream>>>(n, dptr, dcol, dval, lu);
     AMG_LAUNCHED();
-  }
+  };
+  auto identity = [&]() {
+    identity_kernel<<<std::min<int64_t>((static_cast<int64_t>(n) * n + kVecBS - 1) / kVecBS, 65536), kVecBS, 0,
+                      stream>>>(n, S.Ainv);
+    AMG_LAUNCHED();
+  };
+  expand();
+  identity();
   rocblas_int* ipiv = tmp.get<rocblas_int>(n);
   rocblas_int* dinfo = tmp.get<rocblas_int>(1);
-  identity_kernel<<<std::min<int64_t>((static_cast<int64_t>(n) * n + kVecBS - 1) / kVecBS, 65536), kVecBS, 0,
-                    stream>>>(n, S.Ainv);
-  AMG_LAUNCHED();
+  double* dmin = tmp.get<double>(1);
   struct Handle {  // the caller's rocBLAS handle, or one of our own
     rocblas_handle h = nullptr;
     bool own = false;
@@ -495,6 +544,48 @@ inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, con
     hb.own = true;
   }
   rocblas_set_stream(hb.h, stream);
+  // the check vectors: w = A v on the host, z = Ainv w on the device
+  std::vector<double> v(n), w(n, 0.0), z(n);
+  for (int32_t i = 0; i < n; ++i) v[i] = 1.0 + (i % 7) / 8.0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t e = AL.ptr[i]; e < AL.ptr[i + 1]; ++e) w[i] += AL.val[e] * v[AL.col[e]];
+  double* wd = tmp.upload(w.data(), w.size());
+  double* zd = tmp.get<double>(n);
+  // largest relative error of z against v (a wrong inverse is off by O(1);
+  // ill-conditioning up to about 1e12 stays below 1e-3)
+  auto check_error = [&]() {
+    coarse_gemv_kernel<double, double><<<n, kBS, 0, stream>>>(n, S.Ainv, wd, zd, nullptr);
+    AMG_LAUNCHED();
+    AMG_HIP(hipMemcpyAsync(z.data(), zd, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+    AMG_HIP(hipStreamSynchronize(stream));
+    double err = 0.0;
+    for (int32_t i = 0; i < n; ++i) err = std::max(err, std::fabs(z[i] - v[i]) / v[i]);
+    return err;
+  };
+  // the solves against I with pivots ipiv
+  auto solve_identity = [&]() {
+    const rocblas_status st = rocsolver_dgetrs(hb.h, rocblas_operation_none, n, n, lu, n, ipiv, S.Ainv, n);
+    if (st != rocblas_status_success || hipStreamSynchronize(stream) != hipSuccess)
+      throw DevError{-6, "coarse triangular solves failed"};
+  };
+  if (symmetric_to_rounding(AL)) {
+    const rocblas_status st = rocsolver_dgetrf_npvt(hb.h, n, n, lu, n, dinfo);
+    min_diagonal_kernel<<<1, kVecBS, 0, stream>>>(n, lu, dmin);
+    AMG_LAUNCHED();
+    double pmin = 0.0;
+    AMG_HIP(hipMemcpyAsync(&pmin, dmin, sizeof(double), hipMemcpyDeviceToHost, stream));
+    AMG_HIP(hipStreamSynchronize(stream));
+    if (st == rocblas_status_success && pmin > 0.0) {
+      std::vector<rocblas_int> unit(n);  // no row interchanges
+      for (int32_t i = 0; i < n; ++i) unit[i] = i + 1;
+      AMG_HIP(hipMemcpyAsync(ipiv, unit.data(), sizeof(rocblas_int) * n, hipMemcpyHostToDevice, stream));
+      AMG_HIP(hipStreamSynchronize(stream));  // unit is a pageable temporary
+      solve_identity();
+      if (check_error() <= 1e-3) return;
+      identity();
+    }
+    expand();  // not positive definite (or not accurate enough): LU with pivoting of a fresh copy
+  }
   rocblas_int info = 0;
   const rocblas_status st1 = rocsolver_dgetrf(hb.h, n, n, lu, n, ipiv, dinfo);
   const hipError_t e1 = hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, stream);
@@ -503,24 +594,8 @@ inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, con
     throw DevError{-6, "coarse LU factorisation failed"};
   if (info != 0)
     throw DevError{-4, "zero pivot " + std::to_string(info) + " in the coarsest LU (n = " + std::to_string(n) + ")"};
-  const rocblas_status st2 = rocsolver_dgetrs(hb.h, rocblas_operation_none, n, n, lu, n, ipiv, S.Ainv, n);
-  if (st2 != rocblas_status_success || hipStreamSynchronize(stream) != hipSuccess)
-    throw DevError{-6, "coarse triangular solves failed"};
-  // check: z = Ainv (A v) against v, v_i = 1 + (i mod 7) / 8, to 1e-3
-  // relative (a wrong inverse is off by O(1); ill-conditioning up to about
-  // 1e12 passes)
-  std::vector<double> v(n), w(n, 0.0), z(n);
-  for (int32_t i = 0; i < n; ++i) v[i] = 1.0 + (i % 7) / 8.0;
-  for (int32_t i = 0; i < n; ++i)
-    for (int64_t e = AL.ptr[i]; e < AL.ptr[i + 1]; ++e) w[i] += AL.val[e] * v[AL.col[e]];
-  double* wd = tmp.upload(w.data(), w.size());
-  double* zd = tmp.get<double>(n);
-  coarse_gemv_kernel<double, double><<<n, kBS, 0, stream>>>(n, S.Ainv, wd, zd, nullptr);
-  AMG_LAUNCHED();
-  AMG_HIP(hipMemcpyAsync(z.data(), zd, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
-  AMG_HIP(hipStreamSynchronize(stream));
-  double err = 0.0;
-  for (int32_t i = 0; i < n; ++i) err = std::max(err, std::fabs(z[i] - v[i]) / v[i]);
+  solve_identity();
+  const double err = check_error();
   if (!(err <= 1e-3))
     throw DevError{-4, "coarse inverse check failed (max error " + std::to_string(err) + ", n = " + std::to_string(n) + ")"};
 }
