@@ -105,6 +105,7 @@ def test_request_larger_than_budget_fails_cleanly():
     got, _ = serve([(1, *small), (2, *big)], budget=24 << 20, slots=2, threads=2)
     assert got[1][3] == 0, got[1][2].get("error")
     assert got[2][3] == -5  # AMG_ERR_OOM: can never fit
+    assert "budget" in got[2][2].get("error", "")  # the worker's reason reaches the caller
 
 
 @pytest.mark.parametrize("params", [{"relax": "jacobi"}, {"precision": "fp64"}])
