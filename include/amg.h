@@ -41,7 +41,7 @@ typedef enum {
   AMG_ERR_OOM = -5,             /* device or host allocation failed          */
   AMG_ERR_HIP = -6,             /* a HIP runtime call failed                 */
   AMG_ERR_BREAKDOWN = -7,       /* BiCGStab rho = 0 or omega = 0             */
-  AMG_ERR_TOO_LARGE = -8,       /* nnz >= 2^31, or coarsest level > 20000    */
+  AMG_ERR_TOO_LARGE = -8,       /* n or nnz too large, coarsest level > 20000 */
   AMG_ERR_NAN = -9              /* non-finite value in the iteration         */
 } amg_status;
 
@@ -126,7 +126,8 @@ void amg_params_default(amg_params* p);
  * Requirements:
  * row_ptr[0] = 0, non-decreasing row_ptr, 0 <= col < n, strictly ascending
  * columns within a row, a stored diagonal entry a_ii > 0 in every row,
- * nnz < 2^31.  p = NULL means defaults.  On success *out receives a handle
+ * n and nnz below 2^31 - 2^25 (int32 device indices with headroom for
+ * grid-stride loops).  p = NULL means defaults.  On success *out receives a handle
  * owning all device memory; on error *out is set to NULL.
  */
 amg_status amg_setup(int64_t n, const int64_t* row_ptr, const int32_t* col,

@@ -81,11 +81,14 @@ void set_setup_threads(int n) { tl_max_threads = n; }
 
 void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val) {
   if (n <= 0 || !ptr || !col || !val) fail(-1, "null array or non-positive size");
-  if (n >= (int64_t(1) << 31)) fail(-8, "n must be below 2^31");
+  // int32 indices everywhere on the device; grid-stride loops step past the
+  // last index by up to 2^25 before they stop, so that much headroom is kept
+  constexpr int64_t kIndexLimit = (int64_t(1) << 31) - (int64_t(1) << 25);
+  if (n >= kIndexLimit) fail(-8, "n must be below 2^31 - 2^25");
   if (ptr[0] != 0) fail(-2, "row_ptr[0] must be 0");
   for (int64_t i = 0; i < n; ++i)
     if (ptr[i + 1] < ptr[i]) fail(-2, "row_ptr must be non-decreasing");
-  if (ptr[n] >= (int64_t(1) << 31)) fail(-8, "nnz must be below 2^31");
+  if (ptr[n] >= kIndexLimit) fail(-8, "nnz must be below 2^31 - 2^25");
   for (int64_t i = 0; i < n; ++i) {
     bool has_diag = false;
     for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
