@@ -20,6 +20,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -262,20 +263,40 @@ def run_serving(args):
         lat, iters, stat, setup_s, solve_s, queue_s = [], [], [], [], [], []
         failed = []
         t0 = time.perf_counter()
-        nxt = 0
-        inflight = 0
         sub_time = {}
         done = 0
         max_live = 0
+        sub_error = []
+        # Clients submit on their own thread while this thread drives the
+        # server.  Open loop: each request at its arrival time (latency counts
+        # from the arrival time).  Closed loop: a new request whenever fewer
+        # than `window` are in flight (latency counts from its submission).
+        permits = threading.Semaphore(window if arrivals is None else 0)
+        if arrivals is not None:
+            sub_time = {i: float(arrivals[i]) for i in range(count)}
+
+        def submitter():
+            try:
+                for i in range(count):
+                    if arrivals is None:
+                        permits.acquire()
+                        sub_time[i] = time.perf_counter() - t0
+                    else:
+                        wait = arrivals[i] - (time.perf_counter() - t0)
+                        if wait > 0:
+                            time.sleep(wait)
+                    srv.submit(i, req(i), ones[int(sizes[i])])
+            except Exception as e:  # reported by the driving loop
+                sub_error.append(e)
+
+        sub_thread = threading.Thread(target=submitter, daemon=True)
+        sub_thread.start()
+        last_progress = time.perf_counter()
         while done < count:
-            now = time.perf_counter() - t0
-            while nxt < count and ((arrivals is None and inflight < window) or
-                                   (arrivals is not None and arrivals[nxt] <= now)):
-                r = req(nxt)
-                srv.submit(nxt, r, ones[int(sizes[nxt])])
-                sub_time[nxt] = (arrivals[nxt] if arrivals is not None else now)
-                nxt += 1
-                inflight += 1
+            if sub_error:
+                raise sub_error[0]
+            if time.perf_counter() - last_progress > 120.0:
+                raise RuntimeError(f"serving made no progress for 120 s ({done}/{count} done)")
             live, waiting = srv.step()
             max_live = max(max_live, live)
             for rid, x, info, status, times in srv.results():
@@ -290,10 +311,12 @@ def run_serving(args):
                 solve_s.append(info["solve_s"])
                 queue_s.append(times[2] - times[1])  # set up, waiting for a slot
                 done += 1
-                inflight -= 1
+                permits.release()
+                last_progress = time.perf_counter()
             if live == 0:
                 time.sleep(0.0005)
         wall = time.perf_counter() - t0
+        sub_thread.join()
         srv.release()
         ok = sum(1 for s in stat if s == 0)
         res = {

@@ -252,8 +252,10 @@ amg_status amg_time_kernel(amg_handle h, int32_t which, int32_t reps, void* hip_
  * solves that stopped.  Parameters as for amg_setup, restricted to PCG with
  * npre = npost = 1; precision AMG_MIXED is the served configuration.  A
  * request's solution is bitwise identical to amg_solve's for the same system
- * and parameters, whatever else is in the batch.  Not thread-safe: one
- * thread drives a server.
+ * and parameters, whatever else is in the batch.  Threads: one thread drives
+ * a server (step, wait_ready, poll, fetch, destroy); amg_server_submit may be
+ * called from other threads at the same time (requests arriving from
+ * clients), but not during or after amg_server_destroy.
  */
 typedef struct amg_server_s* amg_server;
 amg_status amg_server_create(const amg_params* p, size_t hbm_budget_bytes, int32_t max_slots,
