@@ -150,3 +150,45 @@ def test_served_mix_of_structures_equals_single_solves(precision):
         assert info["iters"] == info_s["iters"], rid
         assert np.array_equal(x, x_s), rid
         assert true_rel_residual(A, x, f) <= 1e-8
+
+
+def test_submissions_from_a_client_thread():
+    """Requests submitted from another thread while this one drives the
+    server (amg_server_submit beside amg_server_step): every result is still
+    bitwise the single-solve result."""
+    import threading
+
+    sizes = [17, 22, 19, 25, 16, 21]
+    reqs = [(i, *request(n, 10700 + i)) for i, n in enumerate(sizes)]
+    srv = amg.Server(2 << 30, max_slots=8, setup_threads=3)
+    errors = []
+
+    def client():
+        try:
+            for rid, A, f in reqs:
+                srv.submit(rid, A, f)
+                time.sleep(0.003)
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    announce("serving, client thread submits")
+    th = threading.Thread(target=client)
+    th.start()
+    got = {}
+    t0 = time.time()
+    while len(got) < len(reqs):
+        assert not errors, errors
+        srv.step()
+        for r in srv.results():
+            got[r[0]] = r
+        assert time.time() - t0 < 120, "server did not finish"
+        time.sleep(0.001)
+    th.join()
+    srv.release()
+    assert not errors, errors
+    for rid, A, f in reqs:
+        x_s, info_s = single(A, f)
+        _, x, info, status, _ = got[rid]
+        assert status == 0, (rid, status, info.get("error"))
+        assert info["iters"] == info_s["iters"]
+        assert np.array_equal(x, x_s), rid
