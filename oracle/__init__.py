@@ -24,6 +24,7 @@ from .sa_amg import (  # noqa: F401
     setup,
     vcycle,
     vcycle_fp32,
+    hierarchy_fp32,
     pcg,
     bicgstab,
     arnoldi_cgs2,

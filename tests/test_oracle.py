@@ -502,3 +502,157 @@ def test_flexible_gmres_exact_with_fp32_vcycle():
     assert info.converged and info64.converged
     assert info.restarts == 0 and info64.restarts == 0
     assert abs(info.iters - info64.iters) <= 1
+
+
+# ------------------------------------------------------------------ Krylov recurrences
+#
+# PCG and BiCGStab are pinned by what their iterates are in exact arithmetic,
+# computed here by dense linear algebra on small systems with a fixed diagonal
+# preconditioner M (Saad 2003, Prop. 9.1 / Thm. 6.6 for CG; van der Vorst 1992
+# for BiCGStab's residual polynomial).
+
+
+def _orth_krylov(apply, v, k):
+    """Orthonormal basis (columns) of span{v, Bv, ..., B^(k-1) v}, B given by ``apply``:
+    each new vector is B times the last basis vector, orthogonalised twice."""
+    Q = []
+    w = np.array(v, dtype=np.float64)
+    for _ in range(k):
+        for _pass in range(2):
+            for q in Q:
+                w = w - (q @ w) * q
+        Q.append(w / np.linalg.norm(w))
+        w = apply(Q[-1])
+    return np.column_stack(Q)
+
+
+def test_pcg_iterate_minimises_energy_error_over_krylov_space():
+    # From x0 = 0, PCG's k-th iterate is the point of K_k(M A, M f) closest to
+    # A^-1 f in the A-norm: x_k = Q (Q^T A Q)^-1 Q^T f for any basis Q of it.
+    A = problems.poisson3d(4).to_scipy()
+    n = A.shape[0]
+    Ad = A.toarray()
+    rng = np.random.default_rng(11)
+    dM = 1.0 + rng.random(n)  # fixed SPD diagonal preconditioner
+    f = rng.standard_normal(n)
+    xs = np.linalg.solve(Ad, f)
+    enorm = np.sqrt(xs @ Ad @ xs)
+    nf = np.linalg.norm(f)
+    for k in range(1, 9):
+        x, info = oracle.pcg(A, f, lambda v: dM * v, tol=1e-300, max_iter=k)
+        assert info.iters == k
+        Q = _orth_krylov(lambda v: dM * (Ad @ v), dM * f, k)
+        best = Q @ np.linalg.solve(Q.T @ Ad @ Q, Q.T @ f)
+        e = x - best
+        assert np.sqrt(e @ Ad @ e) <= 1e-12 * enorm, k
+        # the recursively updated residual is the true one
+        assert abs(info.rel_resid - np.linalg.norm(f - Ad @ x) / nf) <= 1e-12
+
+
+def test_bicgstab_residual_is_product_of_stabilising_and_bicg_polynomials():
+    # Right preconditioning, B = A M, x0 = 0, shadow vector r~ = r0 = f.  After
+    # k steps r_k = psi_k(B) phi_k(B) r0, where phi_k(B) r0 is the BiCG
+    # residual (in r0 + B K_k(B, r0), orthogonal to K_k(B^T, r~)) and
+    # psi_k(t) = prod_j (1 - omega_j t), each omega_j minimising the 2-norm of
+    # (I - omega B) psi_{j-1}(B) phi_j(B) r0.
+    A = _nonsym_small()
+    n = A.shape[0]
+    Ad = A.toarray()
+    rng = np.random.default_rng(12)
+    dM = 1.0 + rng.random(n)
+    f = rng.standard_normal(n)
+    B = Ad * dM[None, :]
+    r0 = f.copy()
+    omegas = []
+    for k in range(1, 7):
+        Q = _orth_krylov(lambda v: B @ v, r0, k)
+        Qs = _orth_krylov(lambda v: B.T @ v, r0, k)
+        c = np.linalg.solve(Qs.T @ B @ Q, Qs.T @ r0)
+        s = r0 - B @ (Q @ c)  # phi_k(B) r0
+        for w in omegas:  # psi_{k-1}(B) phi_k(B) r0
+            s = s - w * (B @ s)
+        t = B @ s
+        omega = (t @ s) / (t @ t)
+        omegas.append(omega)
+        rk = s - omega * t
+        x, info = oracle.bicgstab(A, f, lambda v: dM * v, tol=1e-300, max_iter=k)
+        assert info.iters == k
+        assert np.linalg.norm((f - Ad @ x) - rk) <= 1e-12 * np.linalg.norm(f), k
+
+
+# ------------------------------------------------------------------ FP32 V-cycle
+
+
+def _is_nearest_fp32(v32, v64):
+    """Every entry of v32 (float32) is a float32 nearest to the FP64 value."""
+    v32 = np.asarray(v32)
+    assert v32.dtype == np.float32
+    up = np.nextafter(v32, np.float32(np.inf)).astype(np.float64)
+    dn = np.nextafter(v32, np.float32(-np.inf)).astype(np.float64)
+    d = np.abs(v32.astype(np.float64) - v64)
+    return bool(np.all(d <= np.abs(up - v64)) and np.all(d <= np.abs(dn - v64)))
+
+
+def test_hierarchy_fp32_is_the_rounded_fp64_hierarchy():
+    A = problems.poisson3d(10)
+    h = oracle.setup(A, oracle.Params(coarse_enough=100))
+    assert h.nlevels >= 3
+    h32 = oracle.hierarchy_fp32(h)
+    assert len(h32) == h.nlevels - 1
+    for lv, l32 in zip(h.levels[:-1], h32):
+        for key in "APR":
+            M64, M32 = getattr(lv, key), l32[key]
+            assert M32.dtype == np.float32, key
+            assert np.array_equal(M32.indptr, M64.indptr) and np.array_equal(M32.indices, M64.indices)
+            assert _is_nearest_fp32(M32.data, M64.data), key
+        assert l32["m"].dtype == np.float32 and _is_nearest_fp32(l32["m"], lv.m)
+
+
+def test_fp32_vcycle_single_level_is_the_fp64_solve_rounded_once():
+    # One level: the FP32 V-cycle is the FP64 direct solve of the FP32-rounded
+    # right-hand side, rounded to FP32 once, so each entry is within half a
+    # float32 ulp (<= 2^-24 |z|) of the dense FP64 solution (kappa ~ 1.6e4 here,
+    # so an FP32 factorisation would be off by ~1e-3).
+    A = problems.tridiag1d(200)
+    h = oracle.setup(A)
+    assert h.nlevels == 1
+    f = np.random.default_rng(13).standard_normal(A.n)
+    z = oracle.vcycle_fp32(h, f)
+    ex = np.linalg.solve(A.to_scipy().toarray(), f.astype(np.float32).astype(np.float64))
+    bound = 2.0 ** -24 * np.abs(ex) + 1e-10 * np.max(np.abs(ex))
+    assert np.all(np.abs(z - ex) <= bound)
+
+
+def test_fp32_two_grid_closed_form_within_rounding_bound():
+    # npre = npost = 0, two levels: V32(r) = P32 fl32(A_c^-1 (R32 r32)) with
+    # FP32 sums.  Against the same expression in exact arithmetic (FP64 dense,
+    # the FP32 matrices' values, the FP64 coarse matrix), every entry is within
+    # the componentwise rounding bound: gamma_k = k u / (1 - k u), u = 2^-24,
+    # on the restriction and prolongation sums of at most k terms, propagated
+    # through |A_c^-1|, plus one rounding of z_c.
+    A = problems.poisson3d(6).to_scipy()
+    h = oracle.setup(A, oracle.Params(coarse_enough=100, npre=0, npost=0))
+    assert h.nlevels == 2
+    h32 = oracle.hierarchy_fp32(h)
+    P = h32[0]["P"].astype(np.float64).toarray()
+    R = h32[0]["R"].astype(np.float64).toarray()
+    Ac = h.levels[1].A.toarray()
+    r = np.random.default_rng(14).standard_normal(A.shape[0])
+    r32 = r.astype(np.float32).astype(np.float64)
+    zc = np.linalg.solve(Ac, R @ r32)
+    expect = P @ zc
+    got = oracle.vcycle_fp32(h, r, h32)
+    u = 2.0 ** -24
+
+    def gamma(k):
+        return k * u / (1.0 - k * u)
+
+    kR = int(np.max(np.count_nonzero(R, axis=1)))
+    kP = int(np.max(np.count_nonzero(P, axis=1)))
+    dfc = gamma(kR) * (np.abs(R) @ np.abs(r32))
+    dzc = np.abs(np.linalg.inv(Ac)) @ dfc
+    dzc = dzc + u * (np.abs(zc) + dzc)
+    bound = np.abs(P) @ dzc + gamma(kP) * (np.abs(P) @ (np.abs(zc) + dzc))
+    assert np.all(np.abs(got - expect) <= bound + 1e-14 * np.max(np.abs(expect)))
+    # and it is an FP32 result, not the FP64 one
+    assert np.max(np.abs(got - oracle.vcycle(h, r))) > 1e-9 * np.max(np.abs(expect))

@@ -5,6 +5,9 @@ a wrong sign, index or exponent, a missing transpose or symmetrisation) and
 checks that at least one pin in ``test_oracle`` then fails.
 """
 
+import inspect
+import textwrap
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -31,6 +34,11 @@ def _pins_fail(golden):
         lambda: pins.test_chebyshev_residual_polynomial_closed_form(3),
         lambda: pins.test_gmres_minimal_residual_over_krylov_space(),
         lambda: pins.test_gmres_arnoldi_relation_and_orthonormal_basis(),
+        lambda: pins.test_pcg_iterate_minimises_energy_error_over_krylov_space(),
+        lambda: pins.test_bicgstab_residual_is_product_of_stabilising_and_bicg_polynomials(),
+        lambda: pins.test_hierarchy_fp32_is_the_rounded_fp64_hierarchy(),
+        lambda: pins.test_fp32_vcycle_single_level_is_the_fp64_solve_rounded_once(),
+        lambda: pins.test_fp32_two_grid_closed_form_within_rounding_bound(),
     ]
     for chk in checks:
         try:
@@ -137,6 +145,16 @@ def _arnoldi_skips_last_vector(A, precond, V, j):
     return z, h, float(np.sqrt(w @ w)), w
 
 
+def _one_edit(fn, old, new):
+    """``fn`` recompiled from its source with the single occurrence of ``old``
+    replaced by ``new`` (names resolve in the oracle module's namespace)."""
+    src = textwrap.dedent(inspect.getsource(fn))
+    assert src.count(old) == 1, (fn.__name__, old)
+    ns = dict(sa.__dict__)
+    exec(compile(src.replace(old, new), "<mutant of %s>" % fn.__name__, "exec"), ns)
+    return ns[fn.__name__]
+
+
 _orig = {"filtered_matrix": sa.filtered_matrix, "prolongator_damping": sa.prolongator_damping}
 
 
@@ -150,6 +168,17 @@ MUTATIONS = {
     "restriction_tentative": ("vcycle", _vcycle_restrict_tentative),
     "chebyshev_recurrence_sign": ("chebyshev_sweep", _chebyshev_wrong_recurrence),
     "arnoldi_skips_last_vector": ("arnoldi_cgs2", _arnoldi_skips_last_vector),
+    "pcg_beta_scaled": ("pcg", _one_edit(sa.pcg, "beta = rho_new / rho", "beta = 0.9 * rho_new / rho")),
+    "bicgstab_beta_without_alpha_omega": (
+        "bicgstab", _one_edit(sa.bicgstab, "beta = (rho / rho_old) * (alpha / omega)", "beta = rho / rho_old")),
+    "bicgstab_omega_over_s_s": (
+        "bicgstab", _one_edit(sa.bicgstab, "omega = float(t @ s) / float(t @ t)", "omega = float(t @ s) / float(s @ s)")),
+    "vcycle_fp32_coarse_lu_in_fp32": (
+        "vcycle_fp32", _one_edit(
+            sa.vcycle_fp32,
+            "return sla.lu_solve(h.lu, f32.astype(np.float64)).astype(np.float32)",
+            "return sla.lu_solve(sla.lu_factor(h.levels[-1].A.toarray().astype(np.float32)), f32)")),
+    "hierarchy_fp32_keeps_A_fp64": ("hierarchy_fp32", _one_edit(sa.hierarchy_fp32, "A=lv.A.astype(np.float32)", "A=lv.A")),
 }
 
 
