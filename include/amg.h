@@ -198,6 +198,19 @@ amg_status amg_get_smoother(amg_handle h, int32_t level, double* m_host, double*
                             double* cheb_hi);
 
 /*
+ * SpMV schedule (section 3: the backend's sparse matrix-vector product,
+ * variant chosen by row length) that the device path gives a level matrix:
+ * which = 0 for A_l, 1 for P_l, 2 for R_l; precision AMG_FP64 or AMG_MIXED
+ * (the value type of the copy: FP64, or FP32 for the mixed V-cycle; the
+ * Krylov loop's product with A_1 is always FP64).  Outputs as for
+ * amg_csr_kernel_info; any may be NULL.  Computed on the host from the
+ * level's CSR, so it also answers for handles of amg_setup_host.
+ */
+amg_status amg_level_kernel_info(amg_handle h, int32_t level, int32_t which, int32_t precision,
+                                 int32_t* kind, int32_t* lanes_per_row, int32_t* blocks,
+                                 int32_t* block_bytes);
+
+/*
  * Device SpMV y = A x for a standalone CSR matrix, using the same kernel
  * selection as the solver (by row length).  precision AMG_FP64: x, y double;
  * AMG_MIXED: FP32 copies of the values, x and y float.  rows x cols matrix;

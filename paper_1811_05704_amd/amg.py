@@ -92,6 +92,7 @@ def lib():
         "amg_get_aggregates": (i32, [vp, i32, P32]),
         "amg_get_level_csr": (i32, [vp, i32, i32, P64, P32, PD]),
         "amg_get_smoother": (i32, [vp, i32, PD, PD, PD]),
+        "amg_level_kernel_info": (i32, [vp, i32, i32, i32, P32, P32, P32, P32]),
         "amg_csr_upload": (i32, [i64, i64, P64, P32, PD, i32, vp, C.POINTER(vp)]),
         "amg_csr_spmv": (i32, [vp, vp, vp, vp]),
         "amg_csr_kernel_info": (i32, [vp, P32, P32, P32, P32]),
@@ -117,7 +118,7 @@ def exported_symbols():
     return [
         "amg_params_default", "amg_setup", "amg_setup_host", "amg_solve", "amg_release",
         "amg_last_error", "amg_vcycle", "amg_num_levels", "amg_level_info", "amg_get_aggregates",
-        "amg_get_level_csr", "amg_get_smoother", "amg_csr_upload", "amg_csr_spmv",
+        "amg_get_level_csr", "amg_get_smoother", "amg_level_kernel_info", "amg_csr_upload", "amg_csr_spmv",
         "amg_csr_kernel_info", "amg_csr_release", "amg_time_kernel",
         "amg_server_create", "amg_server_submit", "amg_server_step", "amg_server_wait_ready", "amg_server_poll",
         "amg_server_fetch", "amg_server_destroy",
@@ -214,6 +215,15 @@ class _Handle:
         hi = C.c_double()
         _check(lib().amg_get_smoother(self._h, level, _ptr(m, C.c_double), C.byref(om), C.byref(hi)))
         return m, om.value, hi.value
+
+    def level_kernel_info(self, level, which="A", precision="fp64"):
+        """SpMV schedule of A_l, P_l or R_l in the given value type (host query)."""
+        w = {"A": 0, "P": 1, "R": 2}[which]
+        p = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        k, l, b, nb = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().amg_level_kernel_info(self._h, level, w, p, C.byref(k), C.byref(l), C.byref(b), C.byref(nb)))
+        return {"kind": ("stream", "vector")[k.value], "lanes": l.value, "blocks": b.value,
+                "block_bytes": nb.value}
 
     def release(self):
         if self._h:

@@ -316,13 +316,13 @@ static __global__ void __launch_bounds__(kBS) csr_stream_kernel(CsrView<T> A, Gt
   stream_block<G, NB>(A, gather, epi, xcd_remap(blockIdx.x, gridDim.x), partials, gridDim.x, prod);
 }
 
-// Vector variant: L lanes per row, kBS / L rows per workgroup.
+// Vector variant: L lanes per row, kBS / L rows per workgroup.  Block vb
+// covers rows [vb * kBS / L, (vb + 1) * kBS / L); its dot-product partials go
+// to partials[k * nparts + vb].
 template <int L, class T, class G, class E>
-static __global__ void __launch_bounds__(kBS) csr_vector_kernel(CsrView<T> A, G gather, E epi,
-                                                         double* partials, const int* skip) {
-  if (skip && *skip) return;
+__device__ __forceinline__ void vector_block(const CsrView<T>& A, const G& gather, const E& epi, int vb,
+                                             double* partials, int nparts) {
   constexpr int RPB = kBS / L;
-  const int vb = xcd_remap(blockIdx.x, gridDim.x);
   const int i = vb * RPB + threadIdx.x / L;
   const int lane = threadIdx.x % L;
   double d[E::K > 0 ? E::K : 1] = {};
@@ -333,7 +333,14 @@ static __global__ void __launch_bounds__(kBS) csr_vector_kernel(CsrView<T> A, G 
   }
   s = group_sum<L>(s);
   if (i < A.rows && lane == 0) epi(i, s, d);
-  if constexpr (E::K > 0) block_partials<E::K, kBS>(d, partials, gridDim.x, vb);
+  if constexpr (E::K > 0) block_partials<E::K, kBS>(d, partials, nparts, vb);
+}
+
+template <int L, class T, class G, class E>
+static __global__ void __launch_bounds__(kBS) csr_vector_kernel(CsrView<T> A, G gather, E epi,
+                                                         double* partials, const int* skip) {
+  if (skip && *skip) return;
+  vector_block<L>(A, gather, epi, xcd_remap(blockIdx.x, gridDim.x), partials, gridDim.x);
 }
 
 // ---------------------------------------------------------------- Krylov scalars
@@ -696,9 +703,18 @@ struct SpmvItem {
   E e;
   double* partials;
   const int* skip;
+  int kind;    // 0 stream (block table A.blk), 1 vector (64 lanes per row)
   int lanes;
   int bclass;  // stream block size class: 0 = 16 KB, 1 = 4 KB, 2 = 8 KB
 };
+
+// (lanes, block class) pairs of the stream schedule that the batched kernel
+// dispatches; the host checks every item against it before a launch.
+__host__ __device__ constexpr bool stream_dispatchable(int lanes, int bclass) {
+  return (lanes == 1 || lanes == 4) ? (bclass >= 0 && bclass <= 2)
+         : (lanes == 16 || lanes == 64) ? (bclass == 0 || bclass == 1)
+                                        : false;
+}
 
 template <class T, class Gth, class E>
 __global__ void __launch_bounds__(kBS) batched_spmv_kernel(const Batch<SpmvItem<T, Gth, E>>* B) {
@@ -710,7 +726,8 @@ __global__ void __launch_bounds__(kBS) batched_spmv_kernel(const Batch<SpmvItem<
     if (!*it.skip) {
       const int vb = w - B->off[i], nb = B->off[i + 1] - B->off[i];
       constexpr int NS = kStreamSmallBytes, NM = kStreamMidBytes, NL = AMG_STREAM_BYTES;
-      switch (it.lanes * 4 + it.bclass) {
+      if (it.kind == 1) vector_block<64>(it.A, it.g, it.e, vb, it.partials, nb);
+      else switch (it.lanes * 4 + it.bclass) {
         case 4: stream_block<1, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         case 5: stream_block<1, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         case 6: stream_block<1, NM>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;

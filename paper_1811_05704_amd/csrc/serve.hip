@@ -181,9 +181,20 @@ void batch_add(Batch<Item>& b, const Item& it, int blocks) {
   b.n += 1;
 }
 
+// Descriptor of one solve's SpMV in a batch.  The batched kernel dispatches
+// the stream schedule (block table, (lanes, block class) of the single-solve
+// switch) and the vector schedule (matrices of mean row length above 512);
+// anything else is refused here, on the host, before it could reach a launch.
 template <class T, class G, class E>
 SpmvItem<T, G, E> spmv_item(const DevCsr<T>& M, G g, E e, double* partials, const int* skip) {
-  return SpmvItem<T, G, E>{M.view(), g, e, partials, skip, M.lanes, M.bclass};
+  if (M.rows > 0) {
+    if (M.kind == 0 && (!M.blk || !stream_dispatchable(M.lanes, M.bclass)))
+      throw DevError{-6, "served matrix has a stream schedule the batched kernel cannot run"};
+    if (M.kind == 1 && M.lanes != 64)
+      throw DevError{-6, "served matrix has a vector schedule the batched kernel cannot run"};
+    if (M.kind != 0 && M.kind != 1) throw DevError{-6, "served matrix has an unknown SpMV schedule"};
+  }
+  return SpmvItem<T, G, E>{M.view(), g, e, partials, skip, M.kind, M.lanes, M.bclass};
 }
 
 template <class T, class G, class E>

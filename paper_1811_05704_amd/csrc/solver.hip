@@ -307,6 +307,25 @@ amg_status amg_get_smoother(amg_handle h, int32_t level, double* m_host, double*
   });
 }
 
+amg_status amg_level_kernel_info(amg_handle h, int32_t level, int32_t which, int32_t precision, int32_t* kind,
+                                 int32_t* lanes, int32_t* blocks, int32_t* block_bytes) {
+  return guarded([&]() -> amg_status {
+    const HostLevel& L = level_of(h, level);
+    const Csr* M = which == 0 ? &L.A : which == 1 ? &L.P : which == 2 ? &L.R : nullptr;
+    if (!M) throw SetupError{-1, "which must be 0 (A), 1 (P) or 2 (R)"};
+    if (M->ptr.empty()) throw SetupError{-1, "matrix not present on this level"};
+    if (precision != AMG_FP64 && precision != AMG_MIXED) throw SetupError{-1, "bad precision"};
+    const Schedule sc = precision == AMG_FP64 ? make_schedule<double>(*M) : make_schedule<float>(*M);
+    if (kind) *kind = sc.kind;
+    if (lanes) *lanes = sc.lanes;
+    if (blocks) *blocks = sc.nblocks;
+    if (block_bytes)
+      *block_bytes = sc.kind != 0 ? 0 : sc.bclass == 1 ? kStreamSmallBytes : sc.bclass == 2 ? kStreamMidBytes
+                                                                                           : AMG_STREAM_BYTES;
+    return AMG_OK;
+  });
+}
+
 }  // extern "C"
 
 // --------------------------------------------------------------- standalone SpMV

@@ -19,6 +19,7 @@ from .grids import (  # noqa: F401
 )
 from .irregular import (  # noqa: F401
     anisotropic3d,
+    banded_spd,
     decoupled_boundary,
     poisson3d_27,
     random_laplacian,

@@ -15,6 +15,9 @@ symmetric positive definite, with sorted columns and the diagonal stored:
   connectivity, local random edges, and a few hub nodes joined to many
   others) turned into L + shift I: irregular row lengths, some rows longer
   than a stream block.
+* ``banded_spd``: the Laplacian of the band graph (i ~ j for 0 < |i - j| <= b)
+  plus shift * I: every row is long (up to 2b + 1 entries), so the mean row
+  length exceeds what the LDS-staged SpMV schedule is chosen for.
 """
 
 from __future__ import annotations
@@ -127,3 +130,20 @@ def random_laplacian(n: int, local_edges: int = 4, window: int = 64, hubs: int =
     deg = np.asarray(W.sum(axis=1)).ravel()
     A = sp.diags(deg + shift) - W
     return _to_csr(A)
+
+
+def banded_spd(n: int, bandwidth: int, shift: float = 0.05) -> CSR:
+    """Band-graph Laplacian plus shift * I: a_ij = -1 for 0 < |i - j| <= b,
+    a_ii = (number of off-diagonal entries of row i) + shift."""
+    offs = np.arange(-bandwidth, bandwidth + 1)
+    offs = offs[offs != 0]
+    rows, cols = [], []
+    for o in offs:
+        r = np.arange(max(0, -o), min(n, n - o))
+        rows.append(r)
+        cols.append(r + o)
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    W = sp.csr_matrix((np.ones(r.size), (r, c)), shape=(n, n))
+    deg = np.asarray(W.sum(axis=1)).ravel()
+    return _to_csr(sp.diags(deg + shift) - W)

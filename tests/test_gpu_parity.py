@@ -30,6 +30,11 @@ def dev(x):
     return torch.tensor(np.asarray(x, dtype=np.float64), device="cuda")
 
 
+def max_rel(a, b):
+    """Element-wise distance max|a - b| relative to max|b|."""
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
+
+
 def host(t):
     return t.detach().cpu().numpy()
 
@@ -109,7 +114,10 @@ def test_vcycle_fp64_matches_oracle(name, kw):
     announce("vcycle fp64", name, kw, "levels", S.nlevels)
     z = host(S.vcycle(dev(r)))
     zo = oracle.vcycle(h, r)
-    assert rel_err(z, zo) <= 1e-12
+    e, m = rel_err(z, zo), max_rel(z, zo)
+    print(f"[fp64 vcycle] {name} {kw}: rel {e:.2e}, max {m:.2e}", flush=True)
+    assert e <= 1e-12
+    assert m <= 1e-12
     S.release()
 
 
@@ -150,10 +158,12 @@ def test_vcycle_mixed_matches_fp32_oracle(name, extra):
     z = host(S.vcycle(dev(r)))
     z32 = oracle.vcycle_fp32(h, r)
     z64 = oracle.vcycle(h, r)
-    assert rel_err(z, z32) <= 1e-5
-    # stated, not gated: distance of the FP32 V-cycle from the FP64 one
-    print("mixed vs fp64 oracle V-cycle:", rel_err(z, z64))
-    assert rel_err(z, z64) <= 1e-4
+    e32, m32 = rel_err(z, z32), max_rel(z, z32)
+    e64, o64 = rel_err(z, z64), rel_err(z32, z64)
+    print(f"[mixed vcycle] {name} {extra}: vs FP32 oracle rel {e32:.2e} max {m32:.2e}; "
+          f"vs FP64 oracle {e64:.2e}; FP32 oracle vs FP64 oracle {o64:.2e}", flush=True)
+    assert e32 <= 1e-5
+    assert e64 <= 1e-4
     S.release()
 
 
@@ -227,9 +237,10 @@ COARSE_CASES = ([("spd", n) for n in (255, 383, 511, 895, 900, 1023, 2999)]
 def test_coarse_inverse_every_order(kind, n):
     """Single-level hierarchy (the whole matrix is the coarsest level): the
     device's dense inverse applied to f equals a dense solve.  A symmetric
-    positive definite matrix takes the Cholesky path; a nonsymmetric one, and
-    a symmetric indefinite one (whose Cholesky fails part-way, so the LU runs
-    on a fresh copy), take LU with partial pivoting.  Orders of the form
+    positive definite matrix is factored without pivoting (every pivot comes
+    out positive); a nonsymmetric one, and a symmetric indefinite one (whose
+    unpivoted factorisation meets a non-positive pivot, so the LU with
+    partial pivoting runs on a fresh copy), take LU with partial pivoting.  Orders of the form
     128k - 1 are included on purpose: an in-place LAPACK-style inversion of
     the ROCm stack was found wrong at those."""
     if kind == "spd":
@@ -454,10 +465,13 @@ def test_full_size_poisson150(precision):
         assert abs(S.level_scipy(l, "A") - h.levels[l].A).max() == 0.0, l
     announce("full size 150^3 vcycle", precision)
     z = host(S.vcycle(dev(f)))
+    zo = oracle.vcycle(h, f) if precision == "fp64" else oracle.vcycle_fp32(h, f)
+    e, m = rel_err(z, zo), max_rel(z, zo)
+    print(f"[full size vcycle] {precision}: vs oracle rel {e:.2e} max {m:.2e}", flush=True)
     if precision == "fp64":
-        assert rel_err(z, oracle.vcycle(h, f)) <= 1e-12
+        assert e <= 1e-12 and m <= 1e-12
     else:
-        assert rel_err(z, oracle.vcycle_fp32(h, f)) <= 1e-5
+        assert e <= 1e-5
     announce("full size 150^3 solve", precision)
     x, info = S.solve(dev(f))
     x = host(x)
@@ -488,7 +502,8 @@ def test_full_size_diffusion128(variant):
     h = oracle.setup(A, prm)
     assert S.nlevels == h.nlevels
     r = np.random.default_rng(13).standard_normal(A.n)
-    assert rel_err(host(S.vcycle(dev(r))), oracle.vcycle(h, r)) <= 1e-12
+    z, zo = host(S.vcycle(dev(r))), oracle.vcycle(h, r)
+    assert rel_err(z, zo) <= 1e-12 and max_rel(z, zo) <= 1e-12
     x, info = S.solve(dev(f))
     x = host(x)
     _, io, _ = oracle.solve(A, f, prm, h=h)

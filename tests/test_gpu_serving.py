@@ -2,8 +2,10 @@
 
 Every served result must be bitwise identical to the single-solve path
 (``amg_solve`` with the same parameters) and hence the same alone and in any
-mix; admission under a small HBM budget must still complete every request;
-a request that can never fit must fail cleanly.
+mix, and must match the oracle's solve of the same system (iterations within
+one, solution within 1e-6 relative; the distance to the FP64 oracle's
+solution is printed); admission under a small HBM budget must still complete
+every request; a request that can never fit must fail cleanly.
 """
 
 import time
@@ -11,7 +13,7 @@ import time
 import numpy as np
 import pytest
 
-from tests.gpu_util import announce, true_rel_residual
+from tests.gpu_util import announce, rel_err, true_rel_residual
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu,
@@ -19,6 +21,7 @@ pytestmark = [pytest.mark.gpu,
 
 from paper_1811_05704_amd import amg  # noqa: E402
 
+import oracle  # noqa: E402
 import problems  # noqa: E402
 
 
@@ -60,6 +63,21 @@ def single(A, f, **params):
     return x.cpu().numpy(), info
 
 
+def oracle_check(rid, A, f, x, info, **params):
+    """Served result vs the oracle's solve of the same system and parameters:
+    iterations within one, ||x - x_o|| / ||x_o|| <= 1e-6 against the oracle in
+    the served precision; the FP64 oracle's distance is printed as well."""
+    prm = oracle.Params(relax=params.get("relax", "spai0"), eps_strong=params.get("eps_strong", 0.08))
+    mixed = params.get("precision", "mixed") == "mixed"
+    xo, io, h = oracle.solve(A, f, prm, mixed=mixed)
+    err = rel_err(x, xo)
+    err64 = err if not mixed else rel_err(x, oracle.solve(A, f, prm, h=h)[0])
+    print(f"[oracle] request {rid} n={A.n}: iters {info['iters']} (oracle {io.iters}), "
+          f"vs oracle {err:.2e}, vs FP64 oracle {err64:.2e}", flush=True)
+    assert abs(info["iters"] - io.iters) <= 1, (rid, info["iters"], io.iters)
+    assert err <= 1e-6, (rid, err)
+
+
 def test_served_results_equal_single_solves():
     sizes = [16, 22, 18, 27, 20, 24, 17, 30]
     reqs = [(i, *request(n, 10000 + i)) for i, n in enumerate(sizes)]
@@ -75,6 +93,7 @@ def test_served_results_equal_single_solves():
         assert true_rel_residual(A, x, f) <= 1e-8
         submit, ready, admit, done = times
         assert submit <= ready <= admit <= done
+        oracle_check(rid, A, f, x, info)
 
 
 def test_result_same_alone_and_in_mix():
@@ -124,6 +143,7 @@ def test_served_results_equal_single_solves_other_settings(params):
         assert info["iters"] == info_s["iters"]
         assert np.array_equal(x, x_s), rid
         assert true_rel_residual(A, x, f) <= 1e-8
+        oracle_check(rid, A, f, x, info, **params)
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
@@ -150,6 +170,7 @@ def test_served_mix_of_structures_equals_single_solves(precision):
         assert info["iters"] == info_s["iters"], rid
         assert np.array_equal(x, x_s), rid
         assert true_rel_residual(A, x, f) <= 1e-8
+        oracle_check(rid, A, f, x, info, **params)
 
 
 def test_submissions_from_a_client_thread():
@@ -192,3 +213,30 @@ def test_submissions_from_a_client_thread():
         assert status == 0, (rid, status, info.get("error"))
         assert info["iters"] == info_s["iters"]
         assert np.array_equal(x, x_s), rid
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_long_rows_take_the_vector_schedule(precision):
+    """A band matrix with rows of about 1,200 entries (mean row length above
+    512: A_1 and R_1 get the 64-lanes-per-row schedule, which the host query
+    confirms before anything runs) served beside a diffusion request: both
+    results are bitwise the single-solve results and match the oracle."""
+    B = problems.banded_spd(6000, 600)
+    params = {"precision": precision, "eps_strong": 0.0005}
+    H = amg.HostHierarchy(B, **params)
+    assert H.nlevels == 2
+    assert H.level_kernel_info(0, "A", precision)["kind"] == "vector"
+    assert H.level_kernel_info(0, "R", precision)["kind"] == "vector"
+    H.release()
+    reqs = [(0, B, problems.rhs_ones(B.n)), (1, *request(18, 10800))]
+    announce("serving long rows", precision)
+    got, max_live = serve(reqs, together=True, **params)
+    assert max_live == len(reqs)
+    for rid, A, f in reqs:
+        x_s, info_s = single(A, f, **params)
+        _, x, info, status, _ = got[rid]
+        assert status == 0, (rid, status, info.get("error"))
+        assert info["iters"] == info_s["iters"], rid
+        assert np.array_equal(x, x_s), rid
+        assert true_rel_residual(A, x, f) <= 1e-8
+        oracle_check(rid, A, f, x, info, **params)

@@ -209,3 +209,29 @@ def test_null_safety_and_host_handle_rejects_solve():
     assert code == -1
     assert L.amg_vcycle(H._h, C.c_void_p(16), C.c_void_p(32), None) == -1
     assert L.amg_setup(4, None, None, None, None, None, None, None) == -1
+
+
+def test_level_schedules_by_row_length():
+    """Every level matrix of the 7-point hierarchy gets the LDS-staged stream
+    schedule; a band matrix whose rows are longer than 512 entries on average
+    gets the 64-lanes-per-row vector schedule for A_1 and R_1 (in both value
+    types), its prolongator (about two entries per row) the stream one.  The
+    served path runs both schedules in its batched kernel."""
+    H = amg.HostHierarchy(problems.poisson3d(32))
+    for l in range(H.nlevels - 1):
+        for which in "APR":
+            for prec in ("fp64", "mixed"):
+                k = H.level_kernel_info(l, which, prec)
+                assert k["kind"] == "stream" and k["blocks"] > 0 and k["block_bytes"] > 0, (l, which, k)
+    B = problems.banded_spd(6000, 600)
+    Hb = amg.HostHierarchy(B, eps_strong=0.0005)
+    assert Hb.nlevels == 2
+    for prec in ("fp64", "mixed"):
+        kA = Hb.level_kernel_info(0, "A", prec)
+        kR = Hb.level_kernel_info(0, "R", prec)
+        kP = Hb.level_kernel_info(0, "P", prec)
+        assert kA == {"kind": "vector", "lanes": 64, "blocks": 6000 // 4, "block_bytes": 0}
+        assert kR["kind"] == "vector" and kR["blocks"] == 2  # 5 rows, 4 per block
+        assert kP["kind"] == "stream" and kP["lanes"] == 1
+    with pytest.raises(amg.AmgError):
+        Hb.level_kernel_info(1, "P")  # the coarsest level has no prolongator
