@@ -384,6 +384,8 @@ def main():
     ap.add_argument("--reps", type=int, default=50, help="launches per kernel / V-cycle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--fuse-coarse", action="store_true",
+                    help="run the small levels and the coarse solve as one persistent launch")
     ap.add_argument("--serving", action="store_true",
                     help="serving benchmark: Poisson arrivals of diffusion systems, continuous batching")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -424,8 +426,9 @@ def main():
     precs = ["fp64"] if args.no_mixed else ["fp64", "mixed"]
     for prec in precs:
         log(f"setup {prec}")
-        S = amg.Solver(A, precision=prec, solver=solver, relax=relax)
+        S = amg.Solver(A, precision=prec, solver=solver, relax=relax, fuse_coarse=1 if args.fuse_coarse else 0)
         levels = [S.level_info(l) for l in range(S.nlevels)]
+        fused_from, fused_grid = S.tail_info()
         log(f"{prec}: levels {levels}")
         x, info, times, wall = run_solves(S, f, args.steps, args.warmup, torch)
         xs[prec] = x.cpu().numpy()
@@ -440,12 +443,15 @@ def main():
             "iters": info["iters"],
             "true_rel_resid": true_res,
             "setup_s": info["setup_s"],
+            "setup_profile_s": S.setup_profile(),
             "op_complexity": info["op_complexity"],
             "levels": [{"n": n, "nnz_A": a, "nnz_P": p} for n, a, p in levels],
             "vcycle_us": vc["us"],
             "vcycle_bytes": vc["bytes"],
             "vcycle_GBps": vc["GBps"],
             "vcycle_frac_of_peak": vc["frac"],
+            "fused_from_level": fused_from,
+            "fused_workgroups": fused_grid,
             "kernels": ktab,
         }
         S.release()

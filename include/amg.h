@@ -86,6 +86,13 @@ typedef struct {
   int32_t cheb_degree;   /* AMG_CHEBYSHEV: steps per sweep (1..16)              */
   double cheb_ratio;     /* AMG_CHEBYSHEV: upper / lower end of the interval   */
   int32_t gmres_m;       /* AMG_GMRES: restart length m (1..64)                 */
+  int32_t fuse_coarse;   /* 1: the levels below level 1 whose operator holds at
+                            most 32 MB of values, and the coarse solve, run as
+                            one persistent launch with grid-wide barriers
+                            (SPAI-0 or Jacobi with npre = npost = 1; other
+                            settings always launch per step); bitwise the
+                            same result as 0, one launch per step.  Served
+                            solves never fuse.  Default 0.                     */
 } amg_params;
 
 /* Optional device allocator; NULL everywhere means hipMalloc / hipFree. */
@@ -196,6 +203,35 @@ amg_status amg_get_level_csr(amg_handle h, int32_t level, int32_t which,
  */
 amg_status amg_get_smoother(amg_handle h, int32_t level, double* m_host, double* omega,
                             double* cheb_hi);
+
+/*
+ * Where the setup's wall time went: seconds[AMG_SETUP_PHASES] receives the
+ * time of each step of section 2's "AMG setup", summed over the levels, in
+ * this order: 0 copy and validation of the input CSR, 1 strength graph,
+ * 2 aggregation, 3 filtered matrix + damping + smoothed prolongator,
+ * 4 R = P^T, 5 smoother diagonals, 6 Galerkin products A_{l+1} = R A P,
+ * 7 uploads (fine operator to the device for the setup steps, then level
+ * matrices, vectors and SpMV schedules), 8 dense inverse of the coarsest
+ * operator, 9 everything else.  Their sum is amg_info.setup_s up to the
+ * handle's own allocation.
+ */
+#define AMG_SETUP_PHASES 10
+amg_status amg_setup_profile(amg_handle h, double* seconds);
+
+/*
+ * Fused coarse levels (the amg_params field fuse_coarse): *first_level =
+ * the 0-based first level run inside the single persistent launch (-1 when
+ * nothing is fused), *grid = its workgroup count.  Either pointer may be NULL.
+ */
+amg_status amg_tail_info(amg_handle h, int32_t* first_level, int32_t* grid);
+/*
+ * Test hook: the longest time (seconds, 0..60; default 0.25) one workgroup
+ * of the fused launch waits at a grid barrier before it gives up.  A wait
+ * that runs out makes every workgroup of that launch leave at once and the
+ * calling amg_solve / amg_vcycle return AMG_ERR_HIP ("ran out of time");
+ * the next call starts clean.  Used to check that path with seconds = 0.
+ */
+amg_status amg_tail_set_wait(amg_handle h, double seconds);
 
 /*
  * SpMV schedule (section 3: the backend's sparse matrix-vector product,

@@ -44,6 +44,7 @@ class Params(C.Structure):
         ("eps_strong", C.c_double), ("jacobi_omega", C.c_double), ("tol", C.c_double),
         ("use_graph", C.c_int32), ("check_every", C.c_int32),
         ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double), ("gmres_m", C.c_int32),
+        ("fuse_coarse", C.c_int32),
     ]
 
 
@@ -98,6 +99,9 @@ def lib():
         "amg_csr_kernel_info": (i32, [vp, P32, P32, P32, P32]),
         "amg_csr_release": (None, [vp]),
         "amg_time_kernel": (i32, [vp, i32, i32, vp, PD, PD]),
+        "amg_tail_info": (i32, [vp, P32, P32]),
+        "amg_setup_profile": (i32, [vp, PD]),
+        "amg_tail_set_wait": (i32, [vp, dbl]),
         "amg_server_create": (i32, [C.POINTER(Params), C.c_size_t, i32, i32, vp, C.POINTER(vp)]),
         "amg_server_submit": (i32, [vp, C.c_uint64, i64, P64, P32, PD, PD]),
         "amg_server_step": (i32, [vp, P32, P32]),
@@ -119,7 +123,8 @@ def exported_symbols():
         "amg_params_default", "amg_setup", "amg_setup_host", "amg_solve", "amg_release",
         "amg_last_error", "amg_vcycle", "amg_num_levels", "amg_level_info", "amg_get_aggregates",
         "amg_get_level_csr", "amg_get_smoother", "amg_level_kernel_info", "amg_csr_upload", "amg_csr_spmv",
-        "amg_csr_kernel_info", "amg_csr_release", "amg_time_kernel",
+        "amg_csr_kernel_info", "amg_csr_release", "amg_time_kernel", "amg_tail_info", "amg_tail_set_wait",
+        "amg_setup_profile",
         "amg_server_create", "amg_server_submit", "amg_server_step", "amg_server_wait_ready", "amg_server_poll",
         "amg_server_fetch", "amg_server_destroy",
     ]
@@ -215,6 +220,15 @@ class _Handle:
         hi = C.c_double()
         _check(lib().amg_get_smoother(self._h, level, _ptr(m, C.c_double), C.byref(om), C.byref(hi)))
         return m, om.value, hi.value
+
+    SETUP_PHASES = ("input", "strength", "aggregate", "prolongator", "transpose", "smoother", "galerkin",
+                    "upload", "coarse_inverse", "other")
+
+    def setup_profile(self):
+        """Seconds of the setup by step (names in SETUP_PHASES)."""
+        out = (C.c_double * len(self.SETUP_PHASES))()
+        _check(lib().amg_setup_profile(self._h, out))
+        return dict(zip(self.SETUP_PHASES, list(out)))
 
     def level_kernel_info(self, level, which="A", precision="fp64"):
         """SpMV schedule of A_l, P_l or R_l in the given value type (host query)."""
@@ -328,6 +342,16 @@ class Solver(_Handle):
         _check(lib().amg_time_kernel(self._h, k, reps, C.c_void_p(_torch_stream().cuda_stream),
                                      C.byref(us), C.byref(by)))
         return us.value, by.value
+
+    def tail_info(self):
+        """(first fused level or -1, workgroups of the fused launch)."""
+        first, grid = C.c_int32(), C.c_int32()
+        _check(lib().amg_tail_info(self._h, C.byref(first), C.byref(grid)))
+        return first.value, grid.value
+
+    def set_tail_wait(self, seconds):
+        """Test hook: longest grid-barrier wait of the fused launch."""
+        _check(lib().amg_tail_set_wait(self._h, float(seconds)))
 
     def vcycle(self, r):
         """z = V(r): one V-cycle on a float64 device tensor."""

@@ -27,6 +27,7 @@
 #include "host_setup.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <thread>
@@ -431,30 +432,47 @@ std::vector<double> smoother_diagonal(const Csr& A, const SetupParams& prm) {
 
 }  // namespace
 
+double setup_clock() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 HostHierarchy build_hierarchy(Csr A, const SetupParams& prm, SetupAccel* accel) {
   HostHierarchy H;
   bool from_galerkin = false;
+  double t = setup_clock();
+  auto lap = [&](int phase) {  // charge the time since the last lap to `phase`
+    const double now = setup_clock();
+    H.phase_s[phase] += now - t;
+    t = now;
+  };
   while (true) {
     const int64_t n = A.rows;
     const int lvl_no = static_cast<int>(H.levels.size()) + 1;  // 1-based
     if (n <= prm.coarse_enough || lvl_no >= prm.max_levels) break;
     const double eps = prm.eps_strong * std::ldexp(1.0, -(lvl_no - 1));
     if (accel) accel->begin_level(A, from_galerkin);
+    lap(kPhUpload);
     Graph S;
     if (!accel || !accel->strength(A, eps, S)) S = strength_graph(A, eps);
+    lap(kPhStrength);
     int32_t nc = 0;
     std::vector<int32_t> agg = aggregate(S, &nc);
+    lap(kPhAggregate);
     if (nc == 0 || nc >= n) break;
     HostLevel L;
     L.eps = eps;
     if (!accel || !accel->prolongator(A, S, agg, nc, L.P, &L.omega))
       L.P = smoothed_prolongator(A, S, agg, nc, &L.omega);
+    lap(kPhProlong);
     L.R = transpose(L.P);
+    lap(kPhTranspose);
     L.m = smoother_diagonal(A, prm);
     if (prm.relax == 2) L.cheb_hi = gershgorin_dinv(A);
+    lap(kPhSmoother);
     Csr Ac;
     from_galerkin = accel && accel->galerkin(L.R, A, L.P, Ac);
     if (!from_galerkin) Ac = spgemm(L.R, spgemm(A, L.P));
+    lap(kPhGalerkin);
     L.agg = std::move(agg);
     L.A = std::move(A);
     H.levels.push_back(std::move(L));

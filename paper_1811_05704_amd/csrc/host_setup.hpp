@@ -36,9 +36,29 @@ struct HostLevel {
   double eps = 0.0;           // strength threshold used on this level
 };
 
+// Wall time of the setup by step (seconds, summed over the levels); the
+// order is the one amg_setup_profile documents.
+enum SetupPhase : int {
+  kPhInput = 0,      // copy and validation of the caller's CSR
+  kPhStrength,       // strength graph
+  kPhAggregate,      // aggregation
+  kPhProlong,        // filtered matrix, omega and the smoothed prolongator
+  kPhTranspose,      // R = P^T
+  kPhSmoother,       // smoother diagonals (and Chebyshev bounds)
+  kPhGalerkin,       // A_{l+1} = R (A P)
+  kPhUpload,         // level matrices, vectors and SpMV schedules to the device
+  kPhCoarse,         // dense inverse of the coarsest operator
+  kPhOther,          // everything else (Krylov vectors, fused-launch plan)
+  kPhCount
+};
+
 struct HostHierarchy {
   std::vector<HostLevel> levels;  // the last one is the coarsest (A only)
+  double phase_s[kPhCount] = {};
 };
+
+// Seconds of a monotonic clock.
+double setup_clock();
 
 // Error raised by the setup; code is an amg_status value.
 struct SetupError {

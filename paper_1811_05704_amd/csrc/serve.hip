@@ -446,8 +446,12 @@ void worker_main(amg_server_s* V, int threads) {
   (void)hipSetDevice(V->device);
   hipStream_t ws = nullptr;
   rocblas_handle blas = nullptr;
-  if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess ||
-      rocblas_create_handle(&blas) != rocblas_status_success) {
+  bool blas_ok = false;
+  if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) == hipSuccess) {
+    auto lk = blas_lock();
+    blas_ok = rocblas_create_handle(&blas) == rocblas_status_success;
+  }
+  if (!blas_ok) {
     std::lock_guard<std::mutex> lk(V->mu);
     V->stopping = true;
     V->cv_work.notify_all();
@@ -557,7 +561,10 @@ void worker_main(amg_server_s* V, int threads) {
       V->cv_ready.notify_all();
     }
   }
-  if (blas) rocblas_destroy_handle(blas);
+  if (blas) {
+    auto lk = blas_lock();
+    rocblas_destroy_handle(blas);
+  }
   if (ws) (void)hipStreamDestroy(ws);
 }
 

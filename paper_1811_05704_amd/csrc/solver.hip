@@ -25,6 +25,7 @@ void amg_params_default(amg_params* p) {
   p->cheb_degree = 3;
   p->cheb_ratio = 30.0;
   p->gmres_m = 30;
+  p->fuse_coarse = 0;
 }
 
 const char* amg_last_error(void) { return g_last_error.c_str(); }
@@ -45,8 +46,13 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
     // a step that does not fit the device path stays on the host.
     std::unique_ptr<SetupAccel> accel;
     if (device) accel = make_device_setup_accel(alloc, static_cast<hipStream_t>(stream));
-    S->host = build_hierarchy(to_csr(n, row_ptr, col, val), setup_params(S->prm), accel.get());
+    Csr A = to_csr(n, row_ptr, col, val);
+    const double t_input = now_s() - t0;
+    S->host = build_hierarchy(std::move(A), setup_params(S->prm), accel.get());
+    S->host.phase_s[kPhInput] += t_input;
+    const double t1 = now_s();
     accel.reset();
+    S->host.phase_s[kPhOther] += now_s() - t1;
     if (device) device_setup(*S, alloc, static_cast<hipStream_t>(stream));
     S->setup_s = now_s() - t0;
     *out = S.release();
@@ -84,6 +90,41 @@ amg_status amg_vcycle(amg_handle h, const double* r_dev, double* z_dev, void* hi
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     with_vcycle(*h, [&](auto& V) { return V.template run<0>(r_dev, z_dev, h->partials, nullptr, s); });
     AMG_HIP(hipStreamSynchronize(s));
+    check_tail(h->h64, s);
+    check_tail(h->h32, s);
+    return AMG_OK;
+  });
+}
+
+static_assert(kPhCount == AMG_SETUP_PHASES, "setup phases of the C ABI");
+
+amg_status amg_setup_profile(amg_handle h, double* seconds) {
+  return guarded([&]() -> amg_status {
+    if (!h || !seconds) throw SetupError{-1, "NULL argument"};
+    for (int k = 0; k < kPhCount; ++k) seconds[k] = h->host.phase_s[k];
+    return AMG_OK;
+  });
+}
+
+amg_status amg_tail_info(amg_handle h, int32_t* first_level, int32_t* grid) {
+  return guarded([&]() -> amg_status {
+    if (!h) throw SetupError{-1, "NULL handle"};
+    const bool mixed = h->prm.precision == AMG_MIXED;
+    const int first = mixed ? h->h32.tail_first : h->h64.tail_first;
+    if (first_level) *first_level = first >= 1 ? first : -1;
+    if (grid) *grid = first >= 1 ? (mixed ? h->h32.tail_grid : h->h64.tail_grid) : 0;
+    return AMG_OK;
+  });
+}
+
+amg_status amg_tail_set_wait(amg_handle h, double seconds) {
+  return guarded([&]() -> amg_status {
+    if (!h || !(seconds >= 0.0) || seconds > 60.0) throw SetupError{-1, "bad argument"};
+    int khz = 0;
+    AMG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device));
+    const uint64_t ticks = static_cast<uint64_t>(seconds * 1000.0 * khz);
+    h->h64.tail_limit = ticks;
+    h->h32.tail_limit = ticks;
     return AMG_OK;
   });
 }
@@ -205,6 +246,7 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
   (void)hipEventDestroy(e1);
   (void)hipGraphExecDestroy(ge);
   (void)hipGraphDestroy(g);
+  check_tail(H, s);
   if (which == 5 && S.prm.relax == AMG_CHEBYSHEV) {
     *bytes = cheb_vcycle_bytes(S, H);
     return 1000.0 * ms / reps;

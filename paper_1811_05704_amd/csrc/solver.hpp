@@ -32,6 +32,7 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -39,6 +40,7 @@
 #include "chebyshev.hpp"
 #include "device.hpp"
 #include "gmres.hpp"
+#include "tail.hpp"
 
 namespace amg {
 
@@ -76,6 +78,12 @@ struct DevHierarchy {
   std::vector<DevLevel<T>> lev;  // levels 0 .. L-2
   T* fL = nullptr;               // coarsest right-hand side / solution
   T* zL = nullptr;
+  // Fused coarse tail: levels tail_first .. L-2 and the coarse solve in one
+  // launch of tail_grid workgroups (tail_first = 0: not fused).
+  int tail_first = 0;
+  int tail_grid = 0;
+  TailSync* tail_sync = nullptr;
+  uint64_t tail_limit = 0;
 };
 
 struct VcycleOpts {
@@ -107,18 +115,24 @@ class Vcycle {
       }
       return 0;
     }
+    // levels >= tail run fused in one launch (with the coarse solve)
+    const int tail = use_tail() ? h_->tail_first : L - 1;
     // down
-    for (int l = 0; l < L - 1; ++l) {
+    for (int l = 0; l < tail; ++l) {
       DevLevel<T>& lv = h_->lev[l];
       DevLevel<T>* next = (l + 1 < L - 1) ? &h_->lev[l + 1] : nullptr;
       if (l == 0) down<double>(lv, f0, next, skip, s);
       else down<T>(lv, lv.f, next, skip, s);
     }
-    coarse_gemv_kernel<T, T><<<nL_, kBS, 0, s>>>(nL_, Ainv_, h_->fL, h_->zL, skip);
-    AMG_LAUNCHED();
+    if (tail < L - 1) {
+      launch_tail(tail, skip, s);
+    } else {
+      coarse_gemv_kernel<T, T><<<nL_, kBS, 0, s>>>(nL_, Ainv_, h_->fL, h_->zL, skip);
+      AMG_LAUNCHED();
+    }
     // up
     int nparts = 0;
-    for (int l = L - 2; l >= 0; --l) {
+    for (int l = tail - 1; l >= 0; --l) {
       DevLevel<T>& lv = h_->lev[l];
       const T* zc = (l + 1 < L - 1) ? h_->lev[l + 1].z : h_->zL;
       if (l == 0) nparts = up<double, double, DOT>(lv, f0, zc, z0, partials, skip, s);
@@ -337,6 +351,45 @@ class Vcycle {
     return xi;
   }
 
+  // The fused tail applies to one pre- and one post-sweep of a diagonal
+  // smoother (the steps it reproduces); tail_first >= 1 was set at setup.
+  bool use_tail() const {
+    return h_->tail_first >= 1 && h_->tail_first < static_cast<int>(h_->lev.size()) && o_.npre == 1 &&
+           o_.npost == 1 && o_.relax != AMG_CHEBYSHEV;
+  }
+
+  void launch_tail(int first, const int* skip, hipStream_t s) {
+    const int nl = static_cast<int>(h_->lev.size());
+    TailPlan<T> P{};
+    P.nlev = nl - first;
+    auto mat = [](const DevCsr<T>& M) { return TailMat<T>{M.view(), M.kind, M.lanes, M.bclass}; };
+    for (int i = 0; i < P.nlev; ++i) {
+      DevLevel<T>& lv = h_->lev[first + i];
+      DevLevel<T>* next = (first + i + 1 < nl) ? &h_->lev[first + i + 1] : nullptr;
+      TailLevel<T>& t = P.lev[i];
+      t.A = mat(lv.A);
+      t.P = mat(lv.P);
+      t.R = mat(lv.R);
+      t.f = lv.f;
+      t.mf = lv.mf;
+      t.m = lv.m;
+      t.r = lv.r;
+      t.y = lv.y;
+      t.z = lv.z;
+      t.fnext = next ? next->f : h_->fL;
+      t.mfnext = next ? next->mf : nullptr;
+      t.mnext = next ? next->m : nullptr;
+    }
+    P.Ainv = Ainv_;
+    P.nL = nL_;
+    P.fL = h_->fL;
+    P.zL = h_->zL;
+    P.sync = h_->tail_sync;
+    P.limit = h_->tail_limit;
+    vcycle_tail_kernel<T><<<h_->tail_grid, kBS, 0, s>>>(P, skip);
+    AMG_LAUNCHED();
+  }
+
   DevHierarchy<T>* h_;
   const double* Ainv_;
   int32_t nL_;
@@ -421,6 +474,7 @@ inline void check_params(const amg_params& p) {
   if (p.coarse_enough < 1 || p.max_levels < 1 || p.max_iter < 1) throw SetupError{-1, "coarse_enough, max_levels, max_iter must be >= 1"};
   if (!(p.tol >= 0.0) || !(p.eps_strong >= 0.0)) throw SetupError{-1, "tol and eps_strong must be >= 0"};
   if (p.check_every < 1 || p.check_every > 64) throw SetupError{-1, "check_every must be in [1, 64]"};
+  if (p.fuse_coarse != 0 && p.fuse_coarse != 1) throw SetupError{-1, "fuse_coarse must be 0 or 1"};
 }
 
 inline Csr to_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val) {
@@ -491,6 +545,18 @@ inline bool symmetric_to_rounding(const Csr& M) {
   return true;
 }
 
+// rocBLAS and rocSOLVER are entered by one thread at a time.  The serving
+// workers set up requests side by side, each with its own handle; entered
+// from two workers at once, rocBLAS's kernel-library initialisation has
+// failed and aborted the process.  Every call into either library (handle
+// creation and destruction included) holds this lock, so its lazy
+// initialisation also runs under it.  The device work those calls enqueue
+// still runs asynchronously on each caller's stream.
+inline std::unique_lock<std::mutex> blas_lock() {
+  static std::mutex mu;
+  return std::unique_lock<std::mutex>(mu);
+}
+
 // Dense inverse of the coarsest operator on the device (FP64), in two steps:
 // an LU factorisation, then n triangular solves against I (rocsolver getrs).
 // A matrix symmetric to rounding is first factored without pivoting
@@ -535,15 +601,21 @@ inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, con
     rocblas_handle h = nullptr;
     bool own = false;
     ~Handle() {
-      if (own) rocblas_destroy_handle(h);
+      if (own) {
+        auto lk = blas_lock();
+        rocblas_destroy_handle(h);
+      }
     }
   } hb;
   hb.h = shared;
-  if (!hb.h) {
-    if (rocblas_create_handle(&hb.h) != rocblas_status_success) throw DevError{-6, "rocblas_create_handle failed"};
-    hb.own = true;
+  {
+    auto lk = blas_lock();
+    if (!hb.h) {
+      if (rocblas_create_handle(&hb.h) != rocblas_status_success) throw DevError{-6, "rocblas_create_handle failed"};
+      hb.own = true;
+    }
+    rocblas_set_stream(hb.h, stream);
   }
-  rocblas_set_stream(hb.h, stream);
   // the check vectors: w = A v on the host, z = Ainv w on the device
   std::vector<double> v(n), w(n, 0.0), z(n);
   for (int32_t i = 0; i < n; ++i) v[i] = 1.0 + (i % 7) / 8.0;
@@ -564,12 +636,20 @@ inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, con
   };
   // the solves against I with pivots ipiv
   auto solve_identity = [&]() {
-    const rocblas_status st = rocsolver_dgetrs(hb.h, rocblas_operation_none, n, n, lu, n, ipiv, S.Ainv, n);
+    rocblas_status st;
+    {
+      auto lk = blas_lock();
+      st = rocsolver_dgetrs(hb.h, rocblas_operation_none, n, n, lu, n, ipiv, S.Ainv, n);
+    }
     if (st != rocblas_status_success || hipStreamSynchronize(stream) != hipSuccess)
       throw DevError{-6, "coarse triangular solves failed"};
   };
   if (symmetric_to_rounding(AL)) {
-    const rocblas_status st = rocsolver_dgetrf_npvt(hb.h, n, n, lu, n, dinfo);
+    rocblas_status st;
+    {
+      auto lk = blas_lock();
+      st = rocsolver_dgetrf_npvt(hb.h, n, n, lu, n, dinfo);
+    }
     min_diagonal_kernel<<<1, kVecBS, 0, stream>>>(n, lu, dmin);
     AMG_LAUNCHED();
     double pmin = 0.0;
@@ -587,7 +667,11 @@ inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, con
     expand();  // not positive definite (or not accurate enough): LU with pivoting of a fresh copy
   }
   rocblas_int info = 0;
-  const rocblas_status st1 = rocsolver_dgetrf(hb.h, n, n, lu, n, ipiv, dinfo);
+  rocblas_status st1;
+  {
+    auto lk = blas_lock();
+    st1 = rocsolver_dgetrf(hb.h, n, n, lu, n, ipiv, dinfo);
+  }
   const hipError_t e1 = hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, stream);
   const hipError_t e2 = hipStreamSynchronize(stream);
   if (st1 != rocblas_status_success || e1 != hipSuccess || e2 != hipSuccess)
@@ -651,6 +735,52 @@ inline void upload_levels(amg_solver& S, DevHierarchy<T>& H) {
   if (L > 1) {
     H.fL = ar.get<T>(S.nL);
     H.zL = ar.get<T>(S.nL);
+  }
+}
+
+// Fused coarse tail (tail.hpp): the levels below level 1 whose operator
+// holds at most kTailMaxBytes of values join the launch, up to
+// kTailMaxLevels of them; kTailPerCu workgroups per compute unit (fewer if
+// fewer fit), so that every workgroup of the launch is resident at once.
+constexpr int64_t kTailMaxBytes = int64_t(32) << 20;
+constexpr int kTailPerCu = 2;
+constexpr double kTailWaitSeconds = 0.25;
+
+template <class T>
+inline void plan_tail(amg_solver& S, DevHierarchy<T>& H, hipStream_t s) {
+  if (!S.prm.fuse_coarse || S.prm.relax == AMG_CHEBYSHEV || S.prm.npre != 1 || S.prm.npost != 1) return;
+  const int nl = static_cast<int>(H.lev.size());
+  int first = nl;
+  while (first - 1 >= 1 && nl - (first - 1) <= kTailMaxLevels &&
+         H.lev[first - 1].A.nnz * static_cast<int64_t>(sizeof(T)) <= kTailMaxBytes)
+    --first;
+  if (first >= nl) return;
+  int occ = 0, cus = 0, khz = 0;
+  AMG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, vcycle_tail_kernel<T>, kBS, 0));
+  AMG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S.device));
+  AMG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, S.device));
+  if (occ < 1 || cus < 1 || khz < 1) return;
+  H.tail_grid = std::min(occ, kTailPerCu) * cus;
+  H.tail_sync = S.arena->get<TailSync>(1);
+  AMG_HIP(hipMemsetAsync(H.tail_sync, 0, sizeof(TailSync), s));
+  AMG_HIP(hipStreamSynchronize(s));
+  H.tail_limit = static_cast<uint64_t>(kTailWaitSeconds * 1000.0 * khz);
+  H.tail_first = first;
+}
+
+// Raises if a fused tail launch reported a barrier wait that ran out of
+// time (its results are then invalid); clears the flag for the next call.
+template <class T>
+inline void check_tail(DevHierarchy<T>& H, hipStream_t s) {
+  if (!H.tail_sync) return;
+  int err = 0;
+  AMG_HIP(hipMemcpyAsync(&err, &H.tail_sync->error, sizeof(int), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  if (err) {
+    tail_reset_kernel<<<1, 64, 0, s>>>(H.tail_sync);
+    AMG_LAUNCHED();
+    AMG_HIP(hipStreamSynchronize(s));
+    throw DevError{-6, "fused coarse levels: a grid barrier wait ran out of time; the result is invalid"};
   }
 }
 
@@ -911,6 +1041,8 @@ inline amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, h
   }
   AMG_HIP(hipMemcpyAsync(u_dev, S.x, bytes, hipMemcpyDeviceToDevice, s));
   AMG_HIP(hipStreamSynchronize(s));
+  check_tail(S.h64, s);
+  check_tail(S.h32, s);
 
   amg_status status = AMG_OK;
   switch (k.done) {
@@ -960,10 +1092,19 @@ inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t 
   S.n = fine.A.rows;
   const Csr& AL = S.host.levels.back().A;
   S.nL = static_cast<int32_t>(AL.rows);
+  double t = now_s();
   S.A0 = upload_csr<double>(ar, fine.A);
   if (S.prm.precision == AMG_MIXED) upload_levels<float>(S, S.h32);
   else upload_levels<double>(S, S.h64);
+  S.host.phase_s[kPhUpload] += now_s() - t;
+  t = now_s();
   coarse_inverse(S, AL, s, alloc, opts.blas);
+  S.host.phase_s[kPhCoarse] += now_s() - t;
+  t = now_s();
+  if (opts.standalone) {
+    if (S.prm.precision == AMG_MIXED) plan_tail<float>(S, S.h32, s);
+    else plan_tail<double>(S, S.h64, s);
+  }
   if (opts.standalone) {
     S.st = ar.get<KState>(1);
     AMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.st_host), sizeof(KState), hipHostMallocDefault));
@@ -997,6 +1138,7 @@ inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t 
     S.t = ar.get<double>(n);
   }
   AMG_HIP(hipStreamSynchronize(s));
+  S.host.phase_s[kPhOther] += now_s() - t;
   S.on_device = true;
 }
 

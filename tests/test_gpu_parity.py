@@ -1,7 +1,9 @@
 """Device solve phase vs the oracle (GPU).
 
-* One V-cycle on the same vector: relative error <= 1e-12 in FP64; the
-  FP32 V-cycle against the oracle's FP32 V-cycle within 1e-5.
+* One V-cycle on the same vector: relative error <= 1e-12 in FP64, also
+  element by element; the FP32 V-cycle against the oracle's FP32 V-cycle
+  (and against the FP64 one) within the FP32 rounding bound
+  `mixed_vcycle_tol` (2-norm), twice that element by element.
 * Whole solves: iteration counts within +-1 of the oracle and a true
   relative residual <= 1e-8, recomputed on the CPU from the returned x.
 * Edge cases: zero right-hand side, single-level hierarchy, exact initial
@@ -61,6 +63,27 @@ def _problem(name):
     if name == "graph60k":
         return problems.random_laplacian(60000, seed=2), {}
     raise KeyError(name)
+
+
+U32 = 2.0 ** -24  # FP32 unit roundoff
+
+
+def mixed_vcycle_tol(levels, kw):
+    """Rounding bound of an FP32 V-cycle against another evaluation of it.
+
+    Each level applies p sparse products in FP32 (pre-sweeps, residual,
+    restriction, prolongation, post-sweeps; a Chebyshev sweep is `degree`
+    products), each of which, with its fused vector update, rounds its
+    result to a relative error of a few u (u = 2^-24).  Both sides of a
+    comparison (device and oracle, or FP32 and FP64) differ from the exact
+    V-cycle by at most the sum over the levels, so the bound is
+    2 * p * L * u for the 2-norm relative distance (and twice that for the
+    largest element relative to the largest element).
+    """
+    sweeps = kw.get("npre", 1) + kw.get("npost", 1)
+    per = kw.get("cheb_degree", 3) if kw.get("relax") == "chebyshev" else 1
+    p = sweeps * per + 2
+    return 2.0 * p * levels * U32
 
 
 def _oracle_params(kw):
@@ -159,11 +182,13 @@ def test_vcycle_mixed_matches_fp32_oracle(name, extra):
     z32 = oracle.vcycle_fp32(h, r)
     z64 = oracle.vcycle(h, r)
     e32, m32 = rel_err(z, z32), max_rel(z, z32)
-    e64, o64 = rel_err(z, z64), rel_err(z32, z64)
+    e64, m64, o64 = rel_err(z, z64), max_rel(z, z64), rel_err(z32, z64)
+    tol = mixed_vcycle_tol(S.nlevels, kw)
     print(f"[mixed vcycle] {name} {extra}: vs FP32 oracle rel {e32:.2e} max {m32:.2e}; "
-          f"vs FP64 oracle {e64:.2e}; FP32 oracle vs FP64 oracle {o64:.2e}", flush=True)
-    assert e32 <= 1e-5
-    assert e64 <= 1e-4
+          f"vs FP64 oracle rel {e64:.2e} max {m64:.2e}; FP32 oracle vs FP64 oracle {o64:.2e}; "
+          f"bound {tol:.2e}", flush=True)
+    assert e32 <= tol and m32 <= 2 * tol
+    assert e64 <= tol and m64 <= 2 * tol
     S.release()
 
 
@@ -471,7 +496,8 @@ def test_full_size_poisson150(precision):
     if precision == "fp64":
         assert e <= 1e-12 and m <= 1e-12
     else:
-        assert e <= 1e-5
+        tol = mixed_vcycle_tol(S.nlevels, {})
+        assert e <= tol and m <= 2 * tol, (e, m, tol)
     announce("full size 150^3 solve", precision)
     x, info = S.solve(dev(f))
     x = host(x)
