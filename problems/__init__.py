@@ -24,3 +24,9 @@ from .irregular import (  # noqa: F401
     poisson3d_27,
     random_laplacian,
 )
+from .blocks import (  # noqa: F401
+    BSR,
+    coupled_diffusion3d,
+    decoupled_diffusion3d,
+    random_block_rhs,
+)
