@@ -205,6 +205,23 @@ amg_status amg_get_smoother(amg_handle h, int32_t level, double* m_host, double*
                             double* cheb_hi);
 
 /*
+ * For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * V-cycle z = V(r) exactly as amg_vcycle computes it (bitwise the same z),
+ * whose per-level work vectors live in a fixed device array of the library
+ * (64 MiB per GPU, held until the process ends) instead of the handle's
+ * memory.  Calls no hipMalloc, hipFree or allocating library routine.
+ * r_dev, z_dev: double[n] device arrays of the caller (must not alias).
+ * The kernels are enqueued on hip_stream (one launch per step) and the call
+ * returns without waiting; the handle's device must be current.  Returns
+ * AMG_ERR_TOO_LARGE when the work vectors of the hierarchy (the sum over
+ * the levels of their vector lengths times the value size, 256-byte
+ * aligned) exceed 64 MiB.  All calls on one GPU share that array: calls
+ * that overlap on one GPU (other streams, threads or handles) race.
+ */
+amg_status amg_vcycle_noalloc(amg_handle h, const double* r_dev, double* z_dev, void* hip_stream);
+
+/*
  * Where the setup's wall time went: seconds[AMG_SETUP_PHASES] receives the
  * time of each step of section 2's "AMG setup", summed over the levels, in
  * this order: 0 copy and validation of the input CSR, 1 strength graph,

@@ -101,6 +101,7 @@ def lib():
         "amg_time_kernel": (i32, [vp, i32, i32, vp, PD, PD]),
         "amg_tail_info": (i32, [vp, P32, P32]),
         "amg_setup_profile": (i32, [vp, PD]),
+        "amg_vcycle_noalloc": (i32, [vp, vp, vp, vp]),
         "amg_tail_set_wait": (i32, [vp, dbl]),
         "amg_server_create": (i32, [C.POINTER(Params), C.c_size_t, i32, i32, vp, C.POINTER(vp)]),
         "amg_server_submit": (i32, [vp, C.c_uint64, i64, P64, P32, PD, PD]),
@@ -124,7 +125,7 @@ def exported_symbols():
         "amg_last_error", "amg_vcycle", "amg_num_levels", "amg_level_info", "amg_get_aggregates",
         "amg_get_level_csr", "amg_get_smoother", "amg_level_kernel_info", "amg_csr_upload", "amg_csr_spmv",
         "amg_csr_kernel_info", "amg_csr_release", "amg_time_kernel", "amg_tail_info", "amg_tail_set_wait",
-        "amg_setup_profile",
+        "amg_setup_profile", "amg_vcycle_noalloc",
         "amg_server_create", "amg_server_submit", "amg_server_step", "amg_server_wait_ready", "amg_server_poll",
         "amg_server_fetch", "amg_server_destroy",
     ]
@@ -342,6 +343,20 @@ class Solver(_Handle):
         _check(lib().amg_time_kernel(self._h, k, reps, C.c_void_p(_torch_stream().cuda_stream),
                                      C.byref(us), C.byref(by)))
         return us.value, by.value
+
+    def vcycle_noalloc(self, r, z=None):
+        """z = V(r) with the work vectors in the library's fixed device array
+        (no device allocation by the library; enqueued on the current stream,
+        no wait)."""
+        import torch
+
+        assert r.dtype == torch.float64 and r.is_cuda and r.numel() == self.n
+        r = r.contiguous()
+        if z is None:
+            z = torch.empty_like(r)
+        _check(lib().amg_vcycle_noalloc(self._h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()),
+                                        C.c_void_p(_torch_stream().cuda_stream)))
+        return z
 
     def tail_info(self):
         """(first fused level or -1, workgroups of the fused launch)."""

@@ -23,7 +23,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SOURCES = ["host_setup.cpp"]
-HIP_SOURCES = ["solver.hip", "serve.hip", "galerkin.hip"]
+HIP_SOURCES = ["solver.hip", "serve.hip", "galerkin.hip", "noalloc.hip"]
 
 # Host arithmetic of the setup follows each definition's natural order with
 # separate multiply and add (no contraction), for reproducible hierarchies.
