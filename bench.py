@@ -39,6 +39,8 @@ WORKLOADS = {
     "convection128-bicgstab": (128, "ones", "convection", "bicgstab", "jacobi"),
     "convection128-gmres": (128, "ones", "convection", "gmres", "jacobi"),
     "diffusion128-chebyshev": (128, "ones", "diffusion", "cg", "chebyshev"),
+    # 4 unknowns per node, 4 x 4 blocks (96^3 nodes: 3,538,944 unknowns)
+    "block96": (96, "uniform", "block", "cg", "spai0"),
 }
 KRYLOV_NAMES = {"cg": "PCG", "bicgstab": "BiCGStab", "gmres": "FGMRES(30)"}
 
@@ -48,6 +50,8 @@ def workload_matrix(kind, N):
 
     if kind == "poisson":
         return problems.poisson3d(N)
+    if kind == "block":
+        return problems.coupled_diffusion3d(N, problems.gaussian_field(N, 1.0, 8.0, 2))
     g = problems.gaussian_field(N, 2.0, 8.0, 1)
     vel = (50.0, 25.0, 12.5) if kind == "convection" else None
     return problems.diffusion3d(N, g, velocity=vel)
@@ -107,12 +111,13 @@ def run_solves(S, f, steps, warmup, torch):
     return x, info, times, wall
 
 
-def kernel_table(S, reps, relax="spai0"):
+def kernel_table(S, reps, relax="spai0", block=False):
     """HIP-event timing of the level-1 kernels and of whole V-cycles.  The
     Chebyshev V-cycle runs other kernels than the four level-1 SPAI-0/Jacobi
-    kernels, so for it only the outer SpMV and the V-cycle are timed."""
+    kernels, so for it only the outer SpMV and the V-cycle are timed; block
+    values time the V-cycle only."""
     out = {}
-    names = ("outer_spmv_dot", "vcycle") if relax == "chebyshev" else S.KERNELS
+    names = ("vcycle",) if block else ("outer_spmv_dot", "vcycle") if relax == "chebyshev" else S.KERNELS
     for k in names:
         us, by = S.time_kernel(k, reps=reps)
         out[k] = {"us": us, "bytes": by, "GBps": by / us / 1e3, "frac": by / us / 1e3 / HBM_PEAK_GBS}
@@ -215,14 +220,15 @@ def serving_schedule(count, seed_sizes=6, seed_gaps=5):
     return sizes, gaps
 
 
-def run_serving(args):
+def generate_requests(count):
+    """Sizes, arrival gaps, per-size CSR structure and per-request values of the
+    served stream (values computed by a process pool: run before any GPU use)."""
     import multiprocessing as mp
 
     import numpy as np
 
     import problems
 
-    count = args.serving_requests
     sizes, gaps = serving_schedule(count)
     log(f"serving: generating {count} requests (mean n^3 = {float(np.mean(sizes.astype(float) ** 3)):.0f})")
     t = time.perf_counter()
@@ -236,12 +242,27 @@ def run_serving(args):
                                         chunksize=2):
             vals[i] = v
     log(f"serving: generated in {time.perf_counter() - t:.1f} s")
+    return {"count": count, "sizes": sizes, "gaps": gaps, "structs": structs, "vals": vals}
 
+
+def serving_runs(reqs, setup_threads, window, fracs=(0.5, 0.9, 1.2), small_budget=True, fp64_baseline=False,
+                 check_every=10):
+    """Serve the stream: closed loop (saturation rate mu), then Poisson
+    arrivals at each fraction of mu, optionally once more at 0.9 mu under a
+    2 GiB budget; optionally the same requests one at a time with plain FP64
+    amg_setup + amg_solve (the unbatched baseline), and the served (mixed)
+    solutions of every `check_every`-th request against that FP64 solve."""
+    import numpy as np
+
+    import problems
     import torch
 
     from paper_1811_05704_amd import amg
 
+    count = reqs["count"]
+    sizes, gaps, structs, vals = reqs["sizes"], reqs["gaps"], reqs["structs"], reqs["vals"]
     torch.cuda.set_device(0)
+    torch.cuda.empty_cache()
     free, _total = torch.cuda.mem_get_info()
 
     class Req:
@@ -256,10 +277,11 @@ def run_serving(args):
         return r
 
     ones = {int(n): np.ones(int(n) ** 3) for n in set(sizes.tolist())}
+    kept = {}
 
-    def one_run(arrivals, budget, window=None, label=""):
+    def one_run(arrivals, budget, window=None, label="", keep=False):
         """Serve all requests; arrivals = offsets in s (None: closed loop with `window` in flight)."""
-        srv = amg.Server(budget, max_slots=64, setup_threads=args.setup_threads, precision="mixed")
+        srv = amg.Server(budget, max_slots=64, setup_threads=setup_threads, precision="mixed")
         lat, iters, stat, setup_s, solve_s, queue_s = [], [], [], [], [], []
         failed = []
         t0 = time.perf_counter()
@@ -304,6 +326,8 @@ def run_serving(args):
                 lat.append(tdone - sub_time.pop(rid))
                 iters.append(info["iters"])
                 stat.append(status)
+                if keep and rid % check_every == 0:
+                    kept[int(rid)] = (np.array(x, copy=True), info["iters"])
                 if status != 0:
                     failed.append({"id": int(rid), "n": int(sizes[rid]), "status": int(status), "iters": info["iters"],
                                    "true_rel_resid": info["true_rel_resid"]})
@@ -341,38 +365,84 @@ def run_serving(args):
         return res
 
     budget = int(0.8 * free)
-    sat = one_run(None, budget, window=args.serving_window, label="closed loop")
-    if args.serving_closed_only:
-        print(json.dumps({"closed_loop": sat}), flush=True)
-        return
+    out = {"requests": count, "budget_bytes": budget, "setup_threads": setup_threads, "max_slots": 64}
+    sat = one_run(None, budget, window=window, label="closed loop", keep=fp64_baseline)
+    out["closed_loop"] = sat
     mu = sat["solves_per_s"]
     rates = {}
-    for frac in (0.5, 0.9, 1.2):
+    for frac in fracs:
         lam = frac * mu
         arrivals = np.cumsum(gaps) / lam
         rates[f"{frac}mu"] = {"rate_per_s": lam, **one_run(arrivals, budget, label=f"{frac} mu")}
-    small = one_run(np.cumsum(gaps) / (0.9 * mu), 2 << 30, label="0.9 mu, 2 GiB budget")
+    out["rates"] = rates
+    if small_budget:
+        out["small_budget_0.9mu"] = one_run(np.cumsum(gaps) / (0.9 * mu), 2 << 30, label="0.9 mu, 2 GiB budget")
+    if fp64_baseline:
+        # the same requests, one at a time: plain FP64 setup + solve, no batching
+        lat, iters, errs, ok = [], [], [], 0
+        t0 = time.perf_counter()
+        for i in range(count):
+            ts = time.perf_counter()
+            r = req(i)
+            A = problems.CSR(r.n, r.row_ptr, r.col, r.val)
+            S = amg.Solver(A, precision="fp64")
+            x, info = S.solve(torch.tensor(ones[int(sizes[i])], device="cuda"))
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - ts)
+            iters.append(info["iters"])
+            ok += int(info["status"] == 0)
+            if i in kept:
+                x64 = x.cpu().numpy()
+                xs, its = kept[i]
+                errs.append({"id": i, "n": int(sizes[i]), "served_iters": its, "fp64_iters": info["iters"],
+                             "rel_err_vs_fp64": float(np.linalg.norm(xs - x64) / np.linalg.norm(x64))})
+            S.release()
+        wall = time.perf_counter() - t0
+        out["fp64_one_at_a_time"] = {
+            "solves_per_s": count / wall, "wall_s": wall, "latency_p50_s": pct(lat, 50),
+            "latency_p99_s": pct(lat, 99), "iters_mean": float(np.mean(iters)), "ok": ok,
+        }
+        out["served_vs_fp64"] = {
+            "checked": len(errs),
+            "max_rel_err": max(e["rel_err_vs_fp64"] for e in errs) if errs else None,
+            "max_iter_diff": max(abs(e["served_iters"] - e["fp64_iters"]) for e in errs) if errs else None,
+            "cases": errs[:8],
+        }
+        log(f"serving fp64 one at a time: {out['fp64_one_at_a_time']['solves_per_s']:.1f} solves/s, "
+            f"p50 {out['fp64_one_at_a_time']['latency_p50_s']:.3f} s; served vs FP64 max rel err "
+            f"{out['served_vs_fp64']['max_rel_err']}")
+    return out
+
+
+def run_serving(args):
+    reqs = generate_requests(args.serving_requests)
+    if args.serving_closed_only:
+        res = serving_runs(reqs, args.setup_threads, args.serving_window, fracs=(), small_budget=False)
+        print(json.dumps({"closed_loop": res["closed_loop"]}), flush=True)
+        return
+    res = serving_runs(reqs, args.setup_threads, args.serving_window, fp64_baseline=True)
     line = {
         "metric": "served solves/s and p50/p99 latency (arrival -> result on host), mixed AMG-PCG",
-        "value": rates["0.9mu"]["solves_per_s"],
+        "value": res["rates"]["0.9mu"]["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "higher_is_better": True,
         "dtype": "f32 V-cycle / f64 Krylov",
         "data": "synthetic",
         "config": {
-            "workload": f"{count} diffusion systems n^3, n~U{{16..96}} (seed 6), k=exp(g), g Gaussian "
-                        "sigma 1 length 8 (seed 10000+i), f=1, tol 1e-8, setup + mixed AMG-PCG per request, "
-                        "Poisson arrivals (gaps seed 5)",
-            "budget_bytes": budget,
+            "workload": SERVING_WORKLOAD.format(count=args.serving_requests),
+            "budget_bytes": res["budget_bytes"],
             "setup_threads": args.setup_threads,
             "max_slots": 64,
         },
-        "closed_loop": sat,
-        "rates": rates,
-        "small_budget_0.9mu": small,
+        **{k: v for k, v in res.items() if k not in ("requests", "budget_bytes", "setup_threads", "max_slots")},
     }
     print(json.dumps(line), flush=True)
+
+
+SERVING_WORKLOAD = ("{count} diffusion systems n^3, n~U{{16..96}} (seed 6), k=exp(g), g Gaussian sigma 1 "
+                    "length 8 (seed 10000+i), f=1, tol 1e-8, setup + mixed AMG-PCG per request, "
+                    "Poisson arrivals (gaps seed 5)")
 
 
 def main():
@@ -392,6 +462,8 @@ def main():
     ap.add_argument("--serving-window", type=int, default=64, help="in-flight requests of the closed loop")
     ap.add_argument("--setup-threads", type=int, default=12)
     ap.add_argument("--serving-closed-only", action="store_true")
+    ap.add_argument("--serving-leg", type=int, default=300,
+                    help="requests of the reduced served stream in the default line (0: none)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch a 1 GiB copy and a few launches of each hot kernel (run under "
                          "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
@@ -415,11 +487,14 @@ def main():
     if args.pmc_probe:
         pmc_probe(N, torch, amg, problems)
         return
+    # the served stream's inputs come from a process pool: before any GPU use
+    reqs = generate_requests(args.serving_leg) if args.serving_leg > 0 else None
     A = workload_matrix(kind, N)
     f_host = problems.rhs_uniform(A.n, 0) if rhs == "uniform" else problems.rhs_ones(A.n)
     torch.cuda.set_device(0)
     f = torch.tensor(f_host, device="cuda")
-    log(f"workload {args.workload}: n={A.n} nnz={A.nnz}")
+    nnz = A.nnz if hasattr(A, "nnz") else A.nnzb * A.b * A.b
+    log(f"workload {args.workload}: n={A.n} nnz={nnz}")
 
     results = {}
     xs = {}
@@ -434,7 +509,7 @@ def main():
         xs[prec] = x.cpu().numpy()
         true_res = float(np.linalg.norm(f_host - A.to_scipy() @ xs[prec]) / np.linalg.norm(f_host))
         log(f"{prec}: {info['iters']} iters, solve {np.mean(times) * 1e3:.2f} ms, true res {true_res:.2e}")
-        ktab = kernel_table(S, args.reps, relax)
+        ktab = kernel_table(S, args.reps, relax, block=(kind == "block"))
         vc = ktab.pop("vcycle")
         results[prec] = {
             "solve_s_mean": wall / args.steps,
@@ -460,7 +535,7 @@ def main():
     log(f"device copy reference: {copy_gbps:.0f} GB/s")
     base = results["fp64"]
     cands = dict(base["kernels"])
-    if relax == "chebyshev":  # its per-step kernels are not timed one by one
+    if relax == "chebyshev" or kind == "block":  # their per-step kernels are not timed one by one
         cands["vcycle"] = {"us": base["vcycle_us"], "GBps": base["vcycle_GBps"], "frac": base["vcycle_frac_of_peak"]}
     dom_name, dom = max(cands.items(), key=lambda kv: kv[1]["us"])
     line = {
@@ -477,14 +552,16 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{kind}3d {N}^3 (n={A.n}, nnz={A.nnz}), f={'U[0,1) seed 0' if rhs == 'uniform' else 'ones'}, "
+            "workload": f"{kind}3d {N}^3 (n={A.n}, nnz={nnz}), f={'U[0,1) seed 0' if rhs == 'uniform' else 'ones'}, "
                         f"AMG-{KRYLOV_NAMES[solver]}: smoothed aggregation eps 0.08, "
                         f"{relax + ' degree 3' if relax == 'chebyshev' else relax} 1+1 sweeps, V-cycle, "
                         f"coarse <= 3000 dense, tol 1e-8"
-                        + (", k=exp(g) sigma 2 length 8 seed 1" if kind != "poisson" else "")
+                        + (", 4x4 blocks: coupled 4-field diffusion, k=exp(g) sigma 1 length 8 seed 2"
+                           if kind == "block" else "")
+                        + (", k=exp(g) sigma 2 length 8 seed 1" if kind not in ("poisson", "block") else "")
                         + (", upwind v=(1,0.5,0.25)*50" if kind == "convection" else ""),
             "n": A.n,
-            "nnz": A.nnz,
+            "nnz": nnz,
         },
         "roofline": {
             "bound": "hbm",
@@ -502,7 +579,13 @@ def main():
     }
     if "mixed" in results:
         line["mixed"] = results["mixed"]
-    if not args.no_cpu_baseline:
+    if reqs is not None:
+        log(f"serving leg: {args.serving_leg} requests")
+        sv = serving_runs(reqs, args.setup_threads, args.serving_window, fracs=(0.9,), small_budget=False,
+                          fp64_baseline=True)
+        sv["workload"] = SERVING_WORKLOAD.format(count=args.serving_leg)
+        line["serving"] = sv
+    if not args.no_cpu_baseline and kind != "block":  # the block oracle is sized for the parity tests
         log("cpu baseline (oracle)")
         cb, errs = cpu_baseline(A, f_host, xs, solver, relax)
         line["cpu_baseline"] = cb

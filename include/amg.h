@@ -151,6 +151,46 @@ amg_status amg_setup_host(int64_t n, const int64_t* row_ptr, const int32_t* col,
                           const double* val, const amg_params* p, amg_handle* out);
 
 /*
+ * Block values (section 3, "Value types": matrix entries that are 4 x 4
+ * blocks, one per pair of coupled grid nodes, as in the paper's
+ * Navier-Stokes runs of section 4).  A has nb block rows; block_row_ptr
+ * int64[nb+1] (from 0, non-decreasing), block_col int32[nnzb] (strictly
+ * ascending per block row, the diagonal block stored), block_val
+ * double[16 nnzb] (block k row-major at 16 k); host arrays owned by the
+ * caller, read during the call and copied.  block_size must be 4.  The
+ * unknowns are interlaced (unknown 4 i + f is component f of node i), so
+ * amg_solve, amg_vcycle and amg_time_kernel (which = 5) take vectors of
+ * n = 4 nb doubles.  The hierarchy is built blockwise: strength from block
+ * Frobenius norms, aggregation over nodes, identity tentative blocks,
+ * block-diagonal filtered matrix and damping, block Galerkin products, and
+ * block SPAI-0 (the block-diagonal minimiser of ||I - M A||_F) or block
+ * Jacobi smoothing, the post-sweep applying M^T.  Supported: solver AMG_CG or
+ * AMG_BICGSTAB, relax AMG_SPAI0 or AMG_JACOBI, npre = npost = 1, precision
+ * AMG_FP64 or AMG_MIXED; anything else is AMG_ERR_INVALID_ARG.
+ * coarse_enough counts unknowns (4 nb).  Errors as for amg_setup; a singular
+ * diagonal block gives AMG_ERR_ZERO_DIAG.  amg_level_info then reports block
+ * rows and stored blocks; amg_get_level_csr, amg_get_smoother and the
+ * scalar kernel queries refuse the handle.
+ */
+amg_status amg_setup_block(int64_t nb, int32_t block_size, const int64_t* block_row_ptr,
+                           const int32_t* block_col, const double* block_val,
+                           const amg_params* p, const amg_allocator* alloc, void* hip_stream,
+                           amg_handle* out);
+/* The block hierarchy on the host only (queries only, like amg_setup_host). */
+amg_status amg_setup_block_host(int64_t nb, int32_t block_size, const int64_t* block_row_ptr,
+                                const int32_t* block_col, const double* block_val,
+                                const amg_params* p, amg_handle* out);
+/*
+ * A block level matrix (which = 0 A_l, 1 P_l, 2 R_l) in the layout of
+ * amg_setup_block, arrays sized from amg_level_info (block rows, stored
+ * blocks); and the smoother blocks of a level (double[16 nb], M_i row-major)
+ * with the prolongator damping.  Block-value handles only.
+ */
+amg_status amg_get_level_bsr(amg_handle h, int32_t level, int32_t which, int64_t* block_row_ptr,
+                             int32_t* block_col, double* block_val);
+amg_status amg_get_smoother_blocks(amg_handle h, int32_t level, double* blocks, double* omega);
+
+/*
  * Solve A u = f.  f_dev, u_dev: device double[n]; u holds the initial guess
  * on entry and the solution on exit.  info may be NULL.  Returns AMG_OK,
  * AMG_NOT_CONVERGED (u is the last iterate), or a negative error.  A zero f

@@ -84,6 +84,11 @@ def lib():
         "amg_params_default": (None, [C.POINTER(Params)]),
         "amg_setup": (i32, [i64, P64, P32, PD, C.POINTER(Params), C.POINTER(Allocator), vp, C.POINTER(vp)]),
         "amg_setup_host": (i32, [i64, P64, P32, PD, C.POINTER(Params), C.POINTER(vp)]),
+        "amg_setup_block": (i32, [i64, i32, P64, P32, PD, C.POINTER(Params), C.POINTER(Allocator), vp,
+                                  C.POINTER(vp)]),
+        "amg_setup_block_host": (i32, [i64, i32, P64, P32, PD, C.POINTER(Params), C.POINTER(vp)]),
+        "amg_get_level_bsr": (i32, [vp, i32, i32, P64, P32, PD]),
+        "amg_get_smoother_blocks": (i32, [vp, i32, PD, PD]),
         "amg_solve": (i32, [vp, vp, vp, vp, C.POINTER(Info)]),
         "amg_release": (None, [vp]),
         "amg_last_error": (C.c_char_p, []),
@@ -121,7 +126,8 @@ def lib():
 
 def exported_symbols():
     return [
-        "amg_params_default", "amg_setup", "amg_setup_host", "amg_solve", "amg_release",
+        "amg_params_default", "amg_setup", "amg_setup_host", "amg_setup_block", "amg_setup_block_host",
+        "amg_get_level_bsr", "amg_get_smoother_blocks", "amg_solve", "amg_release",
         "amg_last_error", "amg_vcycle", "amg_num_levels", "amg_level_info", "amg_get_aggregates",
         "amg_get_level_csr", "amg_get_smoother", "amg_level_kernel_info", "amg_csr_upload", "amg_csr_spmv",
         "amg_csr_kernel_info", "amg_csr_release", "amg_time_kernel", "amg_tail_info", "amg_tail_set_wait",
@@ -160,6 +166,17 @@ def make_params(**kw) -> Params:
 
 
 def _csr_arrays(A):
+    row_ptr = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(A.col, dtype=np.int32)
+    val = np.ascontiguousarray(A.val, dtype=np.float64)
+    return row_ptr, col, val
+
+
+def _is_block(A):
+    return hasattr(A, "nb") and hasattr(A, "b")
+
+
+def _bsr_arrays(A):
     row_ptr = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
     col = np.ascontiguousarray(A.col, dtype=np.int32)
     val = np.ascontiguousarray(A.val, dtype=np.float64)
@@ -231,6 +248,30 @@ class _Handle:
         _check(lib().amg_setup_profile(self._h, out))
         return dict(zip(self.SETUP_PHASES, list(out)))
 
+    def level_bsr(self, level, which="A", b=4):
+        """(block rows, block cols, row_ptr, col, blocks[nnzb, b, b]) of a block level matrix."""
+        w = {"A": 0, "P": 1, "R": 2}[which]
+        n, na, npp = self.level_info(level)
+        if w == 0:
+            rows, cols, nnzb = n, n, na
+        else:
+            nc = self.level_info(level + 1)[0]
+            rows, cols = (n, nc) if w == 1 else (nc, n)
+            nnzb = npp
+        rp = np.empty(rows + 1, dtype=np.int64)
+        c = np.empty(nnzb, dtype=np.int32)
+        v = np.empty(nnzb * b * b, dtype=np.float64)
+        _check(lib().amg_get_level_bsr(self._h, level, w, _ptr(rp, C.c_int64), _ptr(c, C.c_int32),
+                                       _ptr(v, C.c_double)))
+        return rows, cols, rp, c, v.reshape(nnzb, b, b)
+
+    def smoother_blocks(self, level, b=4):
+        n, _, _ = self.level_info(level)
+        M = np.empty(n * b * b, dtype=np.float64)
+        om = C.c_double()
+        _check(lib().amg_get_smoother_blocks(self._h, level, _ptr(M, C.c_double), C.byref(om)))
+        return M.reshape(n, b, b), om.value
+
     def level_kernel_info(self, level, which="A", precision="fp64"):
         """SpMV schedule of A_l, P_l or R_l in the given value type (host query)."""
         w = {"A": 0, "P": 1, "R": 2}[which]
@@ -253,14 +294,20 @@ class _Handle:
 
 
 class HostHierarchy(_Handle):
-    """Hierarchy built on the host only (``amg_setup_host``); no device needed."""
+    """Hierarchy built on the host only (``amg_setup_host``, or
+    ``amg_setup_block_host`` for a block matrix); no device needed."""
 
     def __init__(self, A, **params):
         self.params = make_params(**params)
-        rp, c, v = _csr_arrays(A)
         h = C.c_void_p()
-        _check(lib().amg_setup_host(int(A.n), _ptr(rp, C.c_int64), _ptr(c, C.c_int32), _ptr(v, C.c_double),
-                                    C.byref(self.params), C.byref(h)))
+        if _is_block(A):
+            rp, c, v = _bsr_arrays(A)
+            _check(lib().amg_setup_block_host(int(A.nb), int(A.b), _ptr(rp, C.c_int64), _ptr(c, C.c_int32),
+                                              _ptr(v, C.c_double), C.byref(self.params), C.byref(h)))
+        else:
+            rp, c, v = _csr_arrays(A)
+            _check(lib().amg_setup_host(int(A.n), _ptr(rp, C.c_int64), _ptr(c, C.c_int32), _ptr(v, C.c_double),
+                                        C.byref(self.params), C.byref(h)))
         self._h = h
 
 
@@ -308,10 +355,16 @@ class Solver(_Handle):
 
             self._alloc = Allocator(ALLOC_FN(_a), FREE_FN(_f), None)
             alloc_p = C.byref(self._alloc)
-        rp, c, v = _csr_arrays(A)
         h = C.c_void_p()
-        _check(lib().amg_setup(self.n, _ptr(rp, C.c_int64), _ptr(c, C.c_int32), _ptr(v, C.c_double),
-                               C.byref(self.params), alloc_p, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        if _is_block(A):
+            rp, c, v = _bsr_arrays(A)
+            _check(lib().amg_setup_block(int(A.nb), int(A.b), _ptr(rp, C.c_int64), _ptr(c, C.c_int32),
+                                         _ptr(v, C.c_double), C.byref(self.params), alloc_p,
+                                         C.c_void_p(stream.cuda_stream), C.byref(h)))
+        else:
+            rp, c, v = _csr_arrays(A)
+            _check(lib().amg_setup(self.n, _ptr(rp, C.c_int64), _ptr(c, C.c_int32), _ptr(v, C.c_double),
+                                   C.byref(self.params), alloc_p, C.c_void_p(stream.cuda_stream), C.byref(h)))
         self._h = h
 
     def solve(self, f, x0=None, raise_on_error: bool = True):

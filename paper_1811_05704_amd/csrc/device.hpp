@@ -36,6 +36,11 @@ struct DevError {
       throw ::amg::DevError{-6, std::string("kernel launch: ") + hipGetErrorString(e_)}; \
   } while (0)
 
+// Copies between pageable host memory and the device that return when done;
+// large ones are staged through pinned buffers (staging.hip).
+void staged_h2d(void* dst, const void* src, size_t bytes, hipStream_t s);
+void staged_d2h(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 // Device memory from the caller's allocator (or hipMalloc), freed together.
 class DevArena {
  public:
@@ -77,10 +82,7 @@ class DevArena {
   template <class T>
   T* upload(const T* host, size_t count) {
     T* d = get<T>(count);
-    if (count) {
-      AMG_HIP(hipMemcpyAsync(d, host, count * sizeof(T), hipMemcpyHostToDevice, stream_));
-      AMG_HIP(hipStreamSynchronize(stream_));
-    }
+    if (count) staged_h2d(d, host, count * sizeof(T), stream_);
     return d;
   }
   size_t bytes() const { return bytes_; }

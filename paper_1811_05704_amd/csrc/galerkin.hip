@@ -213,10 +213,9 @@ DMat upload_mat(DevArena& ar, const Csr& M, hipStream_t s) {
   d.col = ar.get<int32_t>(std::max<int64_t>(d.nnz, 1));
   d.val = ar.get<double>(std::max<int64_t>(d.nnz, 1));
   if (d.nnz) {
-    AMG_HIP(hipMemcpyAsync(d.col, M.col.data(), sizeof(int32_t) * d.nnz, hipMemcpyHostToDevice, s));
-    AMG_HIP(hipMemcpyAsync(d.val, M.val.data(), sizeof(double) * d.nnz, hipMemcpyHostToDevice, s));
+    staged_h2d(d.col, M.col.data(), sizeof(int32_t) * d.nnz, s);
+    staged_h2d(d.val, M.val.data(), sizeof(double) * d.nnz, s);
   }
-  AMG_HIP(hipStreamSynchronize(s));  // p32 is a pageable temporary
   return d;
 }
 
@@ -419,28 +418,40 @@ int grid_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<
 template <class T>
 void download(std::vector<T>& h, const T* d, size_t n, hipStream_t s) {
   h.resize(n);
-  if (n) {
-    AMG_HIP(hipMemcpyAsync(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, s));
-    AMG_HIP(hipStreamSynchronize(s));
-  }
+  if (n) staged_d2h(h.data(), d, sizeof(T) * n, s);
 }
 
 class DeviceSetupAccel final : public SetupAccel {
  public:
-  DeviceSetupAccel(const amg_allocator* alloc, hipStream_t s) : stream_(s) {
+  DeviceSetupAccel(const amg_allocator* alloc, hipStream_t s, const DeviceCsrRef* fine) : stream_(s) {
     if (alloc) {
       alloc_ = *alloc;
       has_alloc_ = true;
+    }
+    if (fine) {
+      fine_ = *fine;
+      has_fine_ = true;
     }
   }
 
   void begin_level(const Csr& A, bool from_galerkin) override {
     s_ok_ = p_ok_ = have_A_ = false;
+    const bool first = level_++ == 0;
     work_ = arena();
     try {
       if (from_galerkin && next_) {
         a_ = std::move(next_);
         dA_ = dAc_;
+      } else if (first && has_fine_ && fine_.rows == A.rows && fine_.nnz == A.nnz()) {
+        // the caller's device copy of level 1 (read only by the steps)
+        next_.reset();
+        a_.reset();
+        dA_.rows = fine_.rows;
+        dA_.cols = fine_.cols;
+        dA_.nnz = fine_.nnz;
+        dA_.ptr = const_cast<int32_t*>(fine_.ptr);
+        dA_.col = const_cast<int32_t*>(fine_.col);
+        dA_.val = const_cast<double*>(fine_.val);
       } else {
         next_.reset();
         a_ = arena();
@@ -601,12 +612,16 @@ class DeviceSetupAccel final : public SetupAccel {
   uint8_t* strong_ = nullptr;
   int32_t* Sp_ = nullptr;
   bool have_A_ = false, s_ok_ = false, p_ok_ = false;
+  DeviceCsrRef fine_;
+  bool has_fine_ = false;
+  int level_ = 0;
 };
 
 }  // namespace
 
-std::unique_ptr<SetupAccel> make_device_setup_accel(const amg_allocator* alloc, hipStream_t stream) {
-  return std::make_unique<DeviceSetupAccel>(alloc, stream);
+std::unique_ptr<SetupAccel> make_device_setup_accel(const amg_allocator* alloc, hipStream_t stream,
+                                                    const DeviceCsrRef* fine) {
+  return std::make_unique<DeviceSetupAccel>(alloc, stream, fine);
 }
 
 }  // namespace amg

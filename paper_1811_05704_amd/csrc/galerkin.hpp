@@ -23,6 +23,18 @@ namespace amg {
 // a step whose allocation fails, whose rows do not fit the sort blocks, or
 // (strength graph) whose matrix is structurally nonsymmetric is left to the
 // host.  Other HIP errors throw DevError.
-std::unique_ptr<SetupAccel> make_device_setup_accel(const amg_allocator* alloc, hipStream_t stream);
+//
+// `fine` (optional) is a device copy of the level-1 matrix the caller already
+// holds (int32 row pointers and columns, FP64 values, valid while the
+// accelerator lives); level 1 then uses it instead of uploading A again.
+struct DeviceCsrRef {
+  int32_t rows = 0, cols = 0;
+  int64_t nnz = 0;
+  const int32_t* ptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* val = nullptr;
+};
+std::unique_ptr<SetupAccel> make_device_setup_accel(const amg_allocator* alloc, hipStream_t stream,
+                                                    const DeviceCsrRef* fine = nullptr);
 
 }  // namespace amg

@@ -80,6 +80,28 @@ std::vector<double> diagonal(const Csr& A) {
 
 void set_setup_threads(int n) { tl_max_threads = n; }
 
+int setup_threads() { return num_threads(); }
+
+ScopedSetupThreads::ScopedSetupThreads(int n) : saved_(tl_max_threads) { tl_max_threads = n; }
+ScopedSetupThreads::~ScopedSetupThreads() { tl_max_threads = saved_; }
+
+void copy_parallel(void* dst, const void* src, size_t bytes) {
+  constexpr size_t kChunk = size_t(8) << 20;
+  const int nt = num_threads();
+  if (bytes < 4 * kChunk || nt == 1) {
+    if (bytes) std::memcpy(dst, src, bytes);
+    return;
+  }
+  const size_t per = (bytes + nt - 1) / nt;
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) {
+    const size_t b = t * per, e = std::min(bytes, b + per);
+    if (b >= e) break;
+    th.emplace_back([=] { std::memcpy(static_cast<char*>(dst) + b, static_cast<const char*>(src) + b, e - b); });
+  }
+  for (auto& x : th) x.join();
+}
+
 void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val) {
   if (n <= 0 || !ptr || !col || !val) fail(-1, "null array or non-positive size");
   // int32 indices everywhere on the device; grid-stride loops step past the
@@ -90,21 +112,42 @@ void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const doubl
   for (int64_t i = 0; i < n; ++i)
     if (ptr[i + 1] < ptr[i]) fail(-2, "row_ptr must be non-decreasing");
   if (ptr[n] >= kIndexLimit) fail(-8, "nnz must be below 2^31 - 2^25");
-  for (int64_t i = 0; i < n; ++i) {
-    bool has_diag = false;
-    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
-      int32_t c = col[e];
-      if (c < 0 || c >= n) fail(-2, "column index out of range in row " + std::to_string(i));
-      if (e > ptr[i] && col[e - 1] >= c)
-        fail(-2, "columns not strictly ascending in row " + std::to_string(i));
-      if (!std::isfinite(val[e])) fail(-9, "non-finite matrix value in row " + std::to_string(i));
-      if (c == i) {
-        has_diag = true;
-        if (!(val[e] > 0.0)) fail(-3, "non-positive diagonal in row " + std::to_string(i));
+  // Rows are checked in parallel chunks; the lowest failing row is reported.
+  struct Bad {
+    int64_t row = -1;
+    int code = 0;
+    const char* what = nullptr;
+  };
+  auto check = [&](int64_t b, int64_t e) -> Bad {
+    for (int64_t i = b; i < e; ++i) {
+      bool has_diag = false;
+      for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const int32_t c = col[k];
+        if (c < 0 || c >= n) return {i, -2, "column index out of range in row "};
+        if (k > ptr[i] && col[k - 1] >= c) return {i, -2, "columns not strictly ascending in row "};
+        if (!std::isfinite(val[k])) return {i, -9, "non-finite matrix value in row "};
+        if (c == i) {
+          has_diag = true;
+          if (!(val[k] > 0.0)) return {i, -3, "non-positive diagonal in row "};
+        }
       }
+      if (!has_diag) return {i, -3, "missing diagonal in row "};
     }
-    if (!has_diag) fail(-3, "missing diagonal in row " + std::to_string(i));
+    return {};
+  };
+  const int nt = (n < 65536) ? 1 : num_threads();
+  std::vector<Bad> bad(nt);
+  const int64_t chunk = (n + nt - 1) / nt;
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) {
+    const int64_t b = t * chunk, e = std::min(n, b + chunk);
+    if (b >= e) break;
+    if (nt == 1) bad[t] = check(b, e);
+    else th.emplace_back([&, t, b, e] { bad[t] = check(b, e); });
   }
+  for (auto& x : th) x.join();
+  for (const Bad& x : bad)
+    if (x.row >= 0) fail(x.code, std::string(x.what) + std::to_string(x.row));
 }
 
 Graph strength_graph(const Csr& A, double eps) {
@@ -206,22 +249,56 @@ std::vector<int32_t> aggregate(const Graph& S, int32_t* count) {
   return agg;
 }
 
+// T = M^T.  Each thread takes a contiguous range of M's rows; within a row
+// of T the entries of thread t follow those of threads < t, each in row
+// order, so T's rows come out in ascending column order whatever the thread
+// count (the sequential transpose's result).
 Csr transpose(const Csr& M) {
   Csr T;
   T.rows = M.cols;
   T.cols = M.rows;
   T.ptr.assign(T.rows + 1, 0);
-  for (int64_t e = 0; e < M.nnz(); ++e) T.ptr[M.col[e] + 1]++;
-  for (int64_t i = 0; i < T.rows; ++i) T.ptr[i + 1] += T.ptr[i];
   T.col.resize(M.nnz());
   T.val.resize(M.nnz());
-  std::vector<int64_t> pos(T.ptr.begin(), T.ptr.end() - 1);
-  for (int64_t i = 0; i < M.rows; ++i)
-    for (int64_t e = M.ptr[i]; e < M.ptr[i + 1]; ++e) {
-      int64_t p = pos[M.col[e]]++;
-      T.col[p] = static_cast<int32_t>(i);
-      T.val[p] = M.val[e];
+  const int64_t nr = M.rows, nc = T.rows;
+  int nt = (nr < 65536 || nc == 0) ? 1 : num_threads();
+  // per-thread column counts are nt * nc int64: keep them within ~256 MB
+  nt = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(32) << 20) / std::max<int64_t>(nc, 1))));
+  const int64_t chunk = (nr + nt - 1) / nt;
+  std::vector<int64_t> cnt(static_cast<size_t>(nt) * nc, 0);  // cnt[t * nc + c]
+  auto run = [&](auto body) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+      const int64_t b = t * chunk, e = std::min(nr, b + chunk);
+      if (b >= e) break;
+      if (nt == 1) body(t, b, e);
+      else th.emplace_back([=] { body(t, b, e); });
     }
+    for (auto& x : th) x.join();
+  };
+  run([&](int t, int64_t b, int64_t e) {
+    int64_t* c = &cnt[static_cast<size_t>(t) * nc];
+    for (int64_t k = M.ptr[b]; k < M.ptr[e]; ++k) c[M.col[k]]++;
+  });
+  // row pointers of T, and each thread's first slot in every row of T
+  for (int64_t c = 0; c < nc; ++c) {
+    int64_t s = T.ptr[c];
+    for (int t = 0; t < nt; ++t) {
+      const int64_t k = cnt[static_cast<size_t>(t) * nc + c];
+      cnt[static_cast<size_t>(t) * nc + c] = s;
+      s += k;
+    }
+    T.ptr[c + 1] = s;
+  }
+  run([&](int t, int64_t b, int64_t e) {
+    int64_t* pos = &cnt[static_cast<size_t>(t) * nc];
+    for (int64_t i = b; i < e; ++i)
+      for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
+        const int64_t p = pos[M.col[k]]++;
+        T.col[p] = static_cast<int32_t>(i);
+        T.val[p] = M.val[k];
+      }
+  });
   return T;
 }
 

@@ -71,6 +71,23 @@ void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const doubl
 
 // Limit the worker threads the setup of the calling thread uses (0 = default).
 void set_setup_threads(int n);
+// Worker threads the setup of the calling thread may use (at least 1).
+int setup_threads();
+
+// Sets the calling thread's setup thread limit for a scope.
+class ScopedSetupThreads {
+ public:
+  explicit ScopedSetupThreads(int n);
+  ~ScopedSetupThreads();
+  ScopedSetupThreads(const ScopedSetupThreads&) = delete;
+  ScopedSetupThreads& operator=(const ScopedSetupThreads&) = delete;
+
+ private:
+  int saved_;
+};
+
+// memcpy split over the setup's worker threads (large copies only).
+void copy_parallel(void* dst, const void* src, size_t bytes);
 
 struct Graph;
 

@@ -765,6 +765,8 @@ amg_status amg_server_submit(amg_server s, uint64_t request_id, int64_t n, const
                              const double* val, const double* f_host) {
   return guarded([&]() -> amg_status {
     if (!s || !f_host) throw SetupError{-1, "NULL argument"};
+    // the client's thread: no helper threads beside the workers and the driver
+    ScopedSetupThreads one(1);
     validate_csr(n, row_ptr, col, val);
     auto q = std::make_unique<Request>();
     q->id = request_id;

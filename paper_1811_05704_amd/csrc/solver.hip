@@ -42,14 +42,30 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
     else amg_params_default(&S->prm);
     check_params(S->prm);
     validate_csr(n, row_ptr, col, val);
-    // Data-parallel setup steps on the device (bit-identical to the host's);
-    // a step that does not fit the device path stays on the host.
-    std::unique_ptr<SetupAccel> accel;
-    if (device) accel = make_device_setup_accel(alloc, static_cast<hipStream_t>(stream));
     Csr A = to_csr(n, row_ptr, col, val);
     const double t_input = now_s() - t0;
+    // Data-parallel setup steps on the device (bit-identical to the host's);
+    // a step that does not fit the device path stays on the host.  The fine
+    // operator goes to the device once: the solver's copy also serves them.
+    std::unique_ptr<SetupAccel> accel;
+    double t_up = 0.0;
+    if (device) {
+      const double t1 = now_s();
+      S->arena = std::make_unique<DevArena>(alloc, static_cast<hipStream_t>(stream));
+      S->A0 = upload_csr<double>(*S->arena, A);
+      t_up = now_s() - t1;
+      DeviceCsrRef fine;
+      fine.rows = S->A0.rows;
+      fine.cols = S->A0.cols;
+      fine.nnz = S->A0.nnz;
+      fine.ptr = S->A0.ptr;
+      fine.col = S->A0.col;
+      fine.val = S->A0.val;
+      accel = make_device_setup_accel(alloc, static_cast<hipStream_t>(stream), &fine);
+    }
     S->host = build_hierarchy(std::move(A), setup_params(S->prm), accel.get());
     S->host.phase_s[kPhInput] += t_input;
+    S->host.phase_s[kPhUpload] += t_up;
     const double t1 = now_s();
     accel.reset();
     S->host.phase_s[kPhOther] += now_s() - t1;
@@ -59,6 +75,50 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
     g_last_error.clear();
     return AMG_OK;
   });
+}
+
+static amg_status do_setup_block(int64_t nb, int32_t bs, const int64_t* ptr, const int32_t* col,
+                                 const double* val, const amg_params* p, bool device, const amg_allocator* alloc,
+                                 void* stream, amg_handle* out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> amg_status {
+    if (!out) throw SetupError{-1, "out must not be NULL"};
+    if (bs != kBlock) throw SetupError{-1, "block_size must be 4"};
+    const double t0 = now_s();
+    auto S = std::make_unique<amg_solver>();
+    if (p) S->prm = *p;
+    else amg_params_default(&S->prm);
+    check_params(S->prm);
+    check_block_params(S->prm);
+    validate_bsr(nb, ptr, col, val);
+    Bsr A;
+    A.rows = A.cols = nb;
+    A.ptr.assign(ptr, ptr + nb + 1);
+    A.col.assign(col, col + ptr[nb]);
+    A.val.assign(val, val + ptr[nb] * kBB);
+    const double t_input = now_s() - t0;
+    S->block = true;
+    S->bhost = build_block_hierarchy(std::move(A), setup_params(S->prm));
+    for (int k = 0; k < kPhCount; ++k) S->host.phase_s[k] = S->bhost.phase_s[k];
+    S->host.phase_s[kPhInput] += t_input;
+    if (device) device_setup(*S, alloc, static_cast<hipStream_t>(stream));
+    S->setup_s = now_s() - t0;
+    *out = S.release();
+    g_last_error.clear();
+    return AMG_OK;
+  });
+}
+
+amg_status amg_setup_block(int64_t nb, int32_t block_size, const int64_t* block_row_ptr, const int32_t* block_col,
+                           const double* block_val, const amg_params* p, const amg_allocator* alloc,
+                           void* hip_stream, amg_handle* out) {
+  return do_setup_block(nb, block_size, block_row_ptr, block_col, block_val, p, true, alloc, hip_stream, out);
+}
+
+amg_status amg_setup_block_host(int64_t nb, int32_t block_size, const int64_t* block_row_ptr,
+                                const int32_t* block_col, const double* block_val, const amg_params* p,
+                                amg_handle* out) {
+  return do_setup_block(nb, block_size, block_row_ptr, block_col, block_val, p, false, nullptr, nullptr, out);
 }
 
 amg_status amg_setup(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
@@ -254,14 +314,19 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
   if (which == 5) {
     // Algorithmic bytes of one V-cycle with npre = npost = 1: per level
     // 2 passes over A_l, one over P_l and R_l each, 11 vector passes of n_l
-    // (level 1: f and z are FP64), 2 of n_{l+1}; dense coarse inverse + f, z.
+    // and 2 of n_{l+1}, by step: pre-sweep + residual reads f and m, writes
+    // r; restriction reads r (writes f_c); prolongation reads z_c, m, f,
+    // writes y; post-sweep reads y (gathered), m, f, writes z.  On level 1 f
+    // and z are the Krylov loop's FP64 vectors: 3 reads of f and the write of
+    // z at 8 bytes, the other 7 passes at the hierarchy's value size.
+    // Dense coarse inverse + f_L, z_L.
     double b = 0.0;
     for (size_t l = 0; l < H.lev.size(); ++l) {
       const DevLevel<T>& L = H.lev[l];
       const double nl = L.n, ncl = L.nc;
       b += 2.0 * double(L.A.nnz) * (sz + 4) + 2.0 * double(L.P.nnz) * (sz + 4);
       b += 12.0 * (nl + 1) + 4.0 * (ncl + 1) + 2.0 * ncl * sz;
-      b += (l == 0) ? nl * (32.0 + 6.0 * sz) : 11.0 * nl * sz;  // level 1: m not read by the pre-sweep
+      b += (l == 0) ? nl * (4.0 * 8.0 + 7.0 * sz) : 11.0 * nl * sz;
     }
     b += 8.0 * double(S.nL) * double(S.nL) + 2.0 * double(S.nL) * sz;
     *bytes = b;
@@ -270,11 +335,71 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
   const double idx = 4.0;
   switch (which) {
     case 0: *bytes = zA * (8 + idx) + idx * (n + 1) + 16 * n; break;                    // p in, q out
-    case 1: *bytes = zA * (sz + idx) + idx * (n + 1) + n * 8 + n * sz; break;           // A diag(m), f in; r out
+    case 1: *bytes = zA * (sz + idx) + idx * (n + 1) + n * 8 + 2 * n * sz; break;       // f, m (folded into A diag(m)) in; r out
     case 2: *bytes = zA * (sz + idx) + idx * (n + 1) + n * sz * 2 + n * 8 * 2; break;   // y, m, f in; z out
     case 3: *bytes = zP * (sz + idx) + idx * (nc + 1) + n * sz + nc * sz; break;        // r in; f_c out
     default: *bytes = zP * (sz + idx) + idx * (n + 1) + nc * sz + n * 8 + 2 * n * sz; break;  // z_c, f, m in; y out
   }
+  return 1000.0 * ms / reps;
+}
+
+// Back-to-back block V-cycles captured in one graph, between HIP events.
+// Algorithmic bytes per level l < L (one pre- and one post-sweep): two
+// passes over A_l (level 1: A M for the pre-sweep) and one over P_l and
+// R_l, each 16 values + 4 index bytes per block and 4 bytes per block row
+// pointer; vectors of 4 n_l values: pre-sweep f (gathered and read) and r,
+// restriction r in, f_c and m_c f_c out (M_c read, 16 per node), or the
+// coarsest f_L; prolongation z_c in, M f (level 1: M and f) or the stored
+// M f in, y out; post-sweep y (gathered and read), M, f in, z out (level 1:
+// f and z FP64).  Coarsest: dense inverse + f_L, z_L.
+template <class T>
+double time_block_vcycle(amg_solver& S, DevBlockHierarchy<T>& H, int reps, hipStream_t s, double* bytes) {
+  const int nb = vec_blocks(S.n);
+  fill_kernel<double><<<nb, kVecBS, 0, s>>>(static_cast<int>(S.n), S.r, 1.0);
+  AMG_LAUNCHED();
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  AMG_HIP(hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    BlockVcycle<T> V(&H, S.Ainv, S.nL);
+    for (int k = 0; k < reps; ++k) V.template run<0>(S.r, S.z, S.partials, nullptr, S.cap_stream);
+  } catch (...) {
+    (void)hipStreamEndCapture(S.cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  AMG_HIP(hipStreamEndCapture(S.cap_stream, &g));
+  AMG_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+  hipEvent_t e0, e1;
+  AMG_HIP(hipEventCreate(&e0));
+  AMG_HIP(hipEventCreate(&e1));
+  AMG_HIP(hipGraphLaunch(ge, s));  // warm-up
+  AMG_HIP(hipEventRecord(e0, s));
+  AMG_HIP(hipGraphLaunch(ge, s));
+  AMG_HIP(hipEventRecord(e1, s));
+  AMG_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(ge);
+  (void)hipGraphDestroy(g);
+  const double sz = sizeof(T);
+  double b = 0.0;
+  const size_t nlev = H.lev.size();
+  for (size_t l = 0; l < nlev; ++l) {
+    const DevBlockLevel<T>& L = H.lev[l];
+    const double n = double(kB) * L.nb, nbr = L.nb, ncb = L.R.rows, nc = double(kB) * ncb;
+    const double sf = (l == 0) ? 8.0 : sz;  // level 1: f and z are the Krylov loop's FP64 vectors
+    auto pass = [&](const DevBsr<T>& M) { return double(M.nnzb) * (16.0 * sz + 4.0) + 4.0 * (M.rows + 1); };
+    b += 2.0 * pass(L.A) + pass(L.P) + pass(L.R);
+    b += (l == 0) ? n * sf * 2.0 + n * sz : n * sz * 3.0;                          // pre-sweep: f (or m f), f in; r out
+    b += n * sz + ((l + 1 < nlev) ? 2.0 * nc * sz + 16.0 * ncb * sz : nc * sz);     // restriction
+    b += nc * sz + ((l == 0) ? 16.0 * nbr * sz + n * sf : n * sz) + n * sz;         // prolongation
+    b += 2.0 * n * sz + 16.0 * nbr * sz + n * sf + n * sf;                          // post-sweep
+  }
+  b += 8.0 * double(S.nL) * double(S.nL) + 2.0 * double(S.nL) * sz;
+  *bytes = b;
   return 1000.0 * ms / reps;
 }
 
@@ -289,22 +414,46 @@ amg_status amg_time_kernel(amg_handle h, int32_t which, int32_t reps, void* hip_
     if (!h || !avg_us || !bytes || reps < 1 || which < 0 || which > 5) throw SetupError{-1, "bad argument"};
     if (!h->on_device) throw SetupError{-1, "handle was built by amg_setup_host: no device data"};
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (h->block) {
+      if (which != 5) throw SetupError{-1, "block-value handles time the whole V-cycle only (which = 5)"};
+      if (h->prm.precision == AMG_MIXED) *avg_us = time_block_vcycle<float>(*h, h->bh32, reps, s, bytes);
+      else *avg_us = time_block_vcycle<double>(*h, h->bh64, reps, s, bytes);
+      return AMG_OK;
+    }
     if (h->prm.precision == AMG_MIXED) *avg_us = time_level0_kernel<float>(*h, h->h32, which, reps, s, bytes);
     else *avg_us = time_level0_kernel<double>(*h, h->h64, which, reps, s, bytes);
     return AMG_OK;
   });
 }
 
-int32_t amg_num_levels(amg_handle h) { return h ? static_cast<int32_t>(h->host.levels.size()) : 0; }
+int32_t amg_num_levels(amg_handle h) {
+  if (!h) return 0;
+  return static_cast<int32_t>(h->block ? h->bhost.levels.size() : h->host.levels.size());
+}
 
 static const HostLevel& level_of(amg_handle h, int32_t level) {
   if (!h) throw SetupError{-1, "NULL handle"};
+  if (h->block) throw SetupError{-1, "block-value handle: use the block queries"};
   if (level < 0 || level >= static_cast<int32_t>(h->host.levels.size())) throw SetupError{-1, "level out of range"};
   return h->host.levels[level];
 }
 
+static const BlockLevel& block_level_of(amg_handle h, int32_t level) {
+  if (!h) throw SetupError{-1, "NULL handle"};
+  if (!h->block) throw SetupError{-1, "not a block-value handle"};
+  if (level < 0 || level >= static_cast<int32_t>(h->bhost.levels.size())) throw SetupError{-1, "level out of range"};
+  return h->bhost.levels[level];
+}
+
 amg_status amg_level_info(amg_handle h, int32_t level, int64_t* n, int64_t* nnz_A, int64_t* nnz_P) {
   return guarded([&]() -> amg_status {
+    if (h && h->block) {
+      const BlockLevel& L = block_level_of(h, level);
+      if (n) *n = L.A.rows;
+      if (nnz_A) *nnz_A = L.A.nnzb();
+      if (nnz_P) *nnz_P = L.P.nnzb();
+      return AMG_OK;
+    }
     const HostLevel& L = level_of(h, level);
     if (n) *n = L.A.rows;
     if (nnz_A) *nnz_A = L.A.nnz();
@@ -315,10 +464,35 @@ amg_status amg_level_info(amg_handle h, int32_t level, int64_t* n, int64_t* nnz_
 
 amg_status amg_get_aggregates(amg_handle h, int32_t level, int32_t* agg_host) {
   return guarded([&]() -> amg_status {
-    const HostLevel& L = level_of(h, level);
+    const std::vector<int32_t>& agg = (h && h->block) ? block_level_of(h, level).agg : level_of(h, level).agg;
     if (!agg_host) throw SetupError{-1, "NULL output"};
-    if (L.agg.empty()) throw SetupError{-1, "the coarsest level has no aggregates"};
-    std::memcpy(agg_host, L.agg.data(), L.agg.size() * sizeof(int32_t));
+    if (agg.empty()) throw SetupError{-1, "the coarsest level has no aggregates"};
+    std::memcpy(agg_host, agg.data(), agg.size() * sizeof(int32_t));
+    return AMG_OK;
+  });
+}
+
+amg_status amg_get_level_bsr(amg_handle h, int32_t level, int32_t which, int64_t* block_row_ptr,
+                             int32_t* block_col, double* block_val) {
+  return guarded([&]() -> amg_status {
+    const BlockLevel& L = block_level_of(h, level);
+    if (!block_row_ptr || !block_col || !block_val) throw SetupError{-1, "NULL output"};
+    const Bsr* M = which == 0 ? &L.A : which == 1 ? &L.P : which == 2 ? &L.R : nullptr;
+    if (!M) throw SetupError{-1, "which must be 0 (A), 1 (P) or 2 (R)"};
+    if (M->ptr.empty()) throw SetupError{-1, "matrix not present on this level"};
+    std::memcpy(block_row_ptr, M->ptr.data(), M->ptr.size() * sizeof(int64_t));
+    std::memcpy(block_col, M->col.data(), M->col.size() * sizeof(int32_t));
+    std::memcpy(block_val, M->val.data(), M->val.size() * sizeof(double));
+    return AMG_OK;
+  });
+}
+
+amg_status amg_get_smoother_blocks(amg_handle h, int32_t level, double* blocks, double* omega) {
+  return guarded([&]() -> amg_status {
+    const BlockLevel& L = block_level_of(h, level);
+    if (L.M.empty()) throw SetupError{-1, "the coarsest level has no smoother"};
+    if (blocks) std::memcpy(blocks, L.M.data(), L.M.size() * sizeof(double));
+    if (omega) *omega = L.omega;
     return AMG_OK;
   });
 }

@@ -39,6 +39,8 @@
 
 #include "chebyshev.hpp"
 #include "device.hpp"
+#include "block_device.hpp"
+#include "coarse.hpp"
 #include "gmres.hpp"
 #include "tail.hpp"
 
@@ -415,6 +417,14 @@ struct amg_solver {
   amg::DevCsr<double> A0;  // FP64 fine operator for the Krylov loop
   amg::DevHierarchy<double> h64;
   amg::DevHierarchy<float> h32;
+
+  // Block values (4 x 4 per node): host hierarchy, FP64 fine operator and
+  // the device hierarchies; the scalar members above stay empty.
+  bool block = false;
+  amg::BlockHierarchy bhost;
+  amg::DevBsr<double> B0;
+  amg::DevBlockHierarchy<double> bh64;
+  amg::DevBlockHierarchy<float> bh32;
   double* Ainv = nullptr;
   int32_t nL = 0;
   int64_t n = 0;
@@ -477,12 +487,25 @@ inline void check_params(const amg_params& p) {
   if (p.fuse_coarse != 0 && p.fuse_coarse != 1) throw SetupError{-1, "fuse_coarse must be 0 or 1"};
 }
 
+// Settings the block path implements: CG or BiCGStab, SPAI-0 or Jacobi
+// blocks, one pre- and one post-sweep.
+inline void check_block_params(const amg_params& p) {
+  if (p.solver != AMG_CG && p.solver != AMG_BICGSTAB)
+    throw SetupError{-1, "block values: solver must be AMG_CG or AMG_BICGSTAB"};
+  if (p.relax != AMG_SPAI0 && p.relax != AMG_JACOBI)
+    throw SetupError{-1, "block values: relax must be AMG_SPAI0 or AMG_JACOBI"};
+  if (p.npre != 1 || p.npost != 1) throw SetupError{-1, "block values: npre and npost must be 1"};
+}
+
 inline Csr to_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val) {
   Csr A;
   A.rows = A.cols = n;
-  A.ptr.assign(ptr, ptr + n + 1);
-  A.col.assign(col, col + ptr[n]);
-  A.val.assign(val, val + ptr[n]);
+  A.ptr.resize(n + 1);
+  A.col.resize(ptr[n]);
+  A.val.resize(ptr[n]);
+  copy_parallel(A.ptr.data(), ptr, sizeof(int64_t) * (n + 1));
+  copy_parallel(A.col.data(), col, sizeof(int32_t) * ptr[n]);
+  copy_parallel(A.val.data(), val, sizeof(double) * ptr[n]);
   return A;
 }
 
@@ -503,24 +526,6 @@ static __global__ void __launch_bounds__(kVecBS) dense_rows_kernel(int n, const 
   for (int j = threadIdx.x; j < n; j += kVecBS) row[j] = 0.0;
   __syncthreads();
   for (int e = ptr[i] + threadIdx.x; e < ptr[i + 1]; e += kVecBS) row[col[e]] = val[e];
-}
-
-// Smallest diagonal entry of the dense n x n matrix M (one workgroup, fixed
-// order); a NaN on the diagonal gives -infinity.
-static __global__ void __launch_bounds__(kVecBS) min_diagonal_kernel(int n, const double* M, double* out) {
-  __shared__ double sh[kVecBS];
-  double m = INFINITY;
-  for (int k = threadIdx.x; k < n; k += kVecBS) {
-    const double x = M[static_cast<int64_t>(k) * (n + 1)];
-    m = (x == x) ? fmin(m, x) : -INFINITY;
-  }
-  sh[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = kVecBS / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 // Symmetry up to rounding of a CSR matrix with ascending columns:
@@ -577,26 +582,51 @@ inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, con
                            rocblas_handle shared = nullptr) {
   const int32_t n = static_cast<int32_t>(AL.rows);
   S.Ainv = S.arena->get<double>(static_cast<size_t>(n) * n);
-  DevArena tmp(alloc, stream);  // CSR copy, LU factors, pivots: freed on return
-  double* lu = tmp.get<double>(static_cast<size_t>(n) * n);
+  DevArena tmp(alloc, stream);  // CSR copy, LU factors, pivots, check vectors: freed on return
   const std::vector<int32_t> p32(AL.ptr.begin(), AL.ptr.end());
   const int32_t* dptr = tmp.upload(p32.data(), p32.size());
   const int32_t* dcol = tmp.upload(AL.col.data(), AL.col.size());
   const double* dval = tmp.upload(AL.val.data(), AL.val.size());
-  auto expand = [&]() {
-    dense_rows_kernel<<<n, kVecBS, 0, stream>>>(n, dptr, dcol, dval, lu);
+  auto expand_into = [&](double* M) {
+    dense_rows_kernel<<<n, kVecBS, 0, stream>>>(n, dptr, dcol, dval, M);
     AMG_LAUNCHED();
   };
-  auto identity = [&]() {
-    identity_kernel<<<std::min<int64_t>((static_cast<int64_t>(n) * n + kVecBS - 1) / kVecBS, 65536), kVecBS, 0,
-                      stream>>>(n, S.Ainv);
+  // the check vectors: w = A v on the host, z = Ainv w on the device
+  std::vector<double> v(n), w(n, 0.0), z(n);
+  for (int32_t i = 0; i < n; ++i) v[i] = 1.0 + (i % 7) / 8.0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t e = AL.ptr[i]; e < AL.ptr[i + 1]; ++e) w[i] += AL.val[e] * v[AL.col[e]];
+  double* wd = tmp.upload(w.data(), w.size());
+  double* zd = tmp.get<double>(n);
+  // largest relative error of z against v (a wrong inverse is off by O(1);
+  // ill-conditioning up to about 1e12 stays below 1e-3)
+  auto check_error = [&]() {
+    coarse_gemv_kernel<double, double><<<n, kBS, 0, stream>>>(n, S.Ainv, wd, zd, nullptr);
     AMG_LAUNCHED();
+    AMG_HIP(hipMemcpyAsync(z.data(), zd, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+    AMG_HIP(hipStreamSynchronize(stream));
+    double err = 0.0;
+    for (int32_t i = 0; i < n; ++i) err = std::max(err, std::fabs(z[i] - v[i]) / v[i]);
+    return err;
   };
-  expand();
-  identity();
+  if (symmetric_to_rounding(AL)) {
+    expand_into(S.Ainv);
+    double* P = tmp.get<double>(kGjB * kGjB);
+    int* bad = tmp.get<int>(1);
+    AMG_HIP(gj_inverse_spd(n, S.Ainv, P, bad, stream));
+    int hbad = 0;
+    AMG_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+    AMG_HIP(hipStreamSynchronize(stream));
+    if (!hbad && check_error() <= 1e-3) return;
+    // not positive definite (or not accurate enough): LU with pivoting below
+  }
+  double* lu = tmp.get<double>(static_cast<size_t>(n) * n);
+  expand_into(lu);
+  identity_kernel<<<std::min<int64_t>((static_cast<int64_t>(n) * n + kVecBS - 1) / kVecBS, 65536), kVecBS, 0,
+                    stream>>>(n, S.Ainv);
+  AMG_LAUNCHED();
   rocblas_int* ipiv = tmp.get<rocblas_int>(n);
   rocblas_int* dinfo = tmp.get<rocblas_int>(1);
-  double* dmin = tmp.get<double>(1);
   struct Handle {  // the caller's rocBLAS handle, or one of our own
     rocblas_handle h = nullptr;
     bool own = false;
@@ -616,56 +646,6 @@ inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, con
     }
     rocblas_set_stream(hb.h, stream);
   }
-  // the check vectors: w = A v on the host, z = Ainv w on the device
-  std::vector<double> v(n), w(n, 0.0), z(n);
-  for (int32_t i = 0; i < n; ++i) v[i] = 1.0 + (i % 7) / 8.0;
-  for (int32_t i = 0; i < n; ++i)
-    for (int64_t e = AL.ptr[i]; e < AL.ptr[i + 1]; ++e) w[i] += AL.val[e] * v[AL.col[e]];
-  double* wd = tmp.upload(w.data(), w.size());
-  double* zd = tmp.get<double>(n);
-  // largest relative error of z against v (a wrong inverse is off by O(1);
-  // ill-conditioning up to about 1e12 stays below 1e-3)
-  auto check_error = [&]() {
-    coarse_gemv_kernel<double, double><<<n, kBS, 0, stream>>>(n, S.Ainv, wd, zd, nullptr);
-    AMG_LAUNCHED();
-    AMG_HIP(hipMemcpyAsync(z.data(), zd, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
-    AMG_HIP(hipStreamSynchronize(stream));
-    double err = 0.0;
-    for (int32_t i = 0; i < n; ++i) err = std::max(err, std::fabs(z[i] - v[i]) / v[i]);
-    return err;
-  };
-  // the solves against I with pivots ipiv
-  auto solve_identity = [&]() {
-    rocblas_status st;
-    {
-      auto lk = blas_lock();
-      st = rocsolver_dgetrs(hb.h, rocblas_operation_none, n, n, lu, n, ipiv, S.Ainv, n);
-    }
-    if (st != rocblas_status_success || hipStreamSynchronize(stream) != hipSuccess)
-      throw DevError{-6, "coarse triangular solves failed"};
-  };
-  if (symmetric_to_rounding(AL)) {
-    rocblas_status st;
-    {
-      auto lk = blas_lock();
-      st = rocsolver_dgetrf_npvt(hb.h, n, n, lu, n, dinfo);
-    }
-    min_diagonal_kernel<<<1, kVecBS, 0, stream>>>(n, lu, dmin);
-    AMG_LAUNCHED();
-    double pmin = 0.0;
-    AMG_HIP(hipMemcpyAsync(&pmin, dmin, sizeof(double), hipMemcpyDeviceToHost, stream));
-    AMG_HIP(hipStreamSynchronize(stream));
-    if (st == rocblas_status_success && pmin > 0.0) {
-      std::vector<rocblas_int> unit(n);  // no row interchanges
-      for (int32_t i = 0; i < n; ++i) unit[i] = i + 1;
-      AMG_HIP(hipMemcpyAsync(ipiv, unit.data(), sizeof(rocblas_int) * n, hipMemcpyHostToDevice, stream));
-      AMG_HIP(hipStreamSynchronize(stream));  // unit is a pageable temporary
-      solve_identity();
-      if (check_error() <= 1e-3) return;
-      identity();
-    }
-    expand();  // not positive definite (or not accurate enough): LU with pivoting of a fresh copy
-  }
   rocblas_int info = 0;
   rocblas_status st1;
   {
@@ -678,7 +658,14 @@ inline void coarse_inverse(amg_solver& S, const Csr& AL, hipStream_t stream, con
     throw DevError{-6, "coarse LU factorisation failed"};
   if (info != 0)
     throw DevError{-4, "zero pivot " + std::to_string(info) + " in the coarsest LU (n = " + std::to_string(n) + ")"};
-  solve_identity();
+  // the solves against I with pivots ipiv
+  rocblas_status st2;
+  {
+    auto lk = blas_lock();
+    st2 = rocsolver_dgetrs(hb.h, rocblas_operation_none, n, n, lu, n, ipiv, S.Ainv, n);
+  }
+  if (st2 != rocblas_status_success || hipStreamSynchronize(stream) != hipSuccess)
+    throw DevError{-6, "coarse triangular solves failed"};
   const double err = check_error();
   if (!(err <= 1e-3))
     throw DevError{-4, "coarse inverse check failed (max error " + std::to_string(err) + ", n = " + std::to_string(n) + ")"};
@@ -733,6 +720,8 @@ inline void upload_levels(amg_solver& S, DevHierarchy<T>& H) {
     H.lev.push_back(d);
   }
   if (L > 1) {
+    if (S.nL != static_cast<int32_t>(S.host.levels.back().A.rows))
+      throw DevError{-6, "coarsest level size not set before the level upload"};
     H.fL = ar.get<T>(S.nL);
     H.zL = ar.get<T>(S.nL);
   }
@@ -787,6 +776,11 @@ inline void check_tail(DevHierarchy<T>& H, hipStream_t s) {
 inline int64_t max_parts(const amg_solver& S) {
   int64_t m = vec_blocks(S.n);
   m = std::max<int64_t>(m, S.A0.nblocks);
+  if (S.block) {
+    m = std::max<int64_t>(m, S.B0.blocks());
+    for (const auto& lv : S.bh64.lev) m = std::max<int64_t>(m, lv.A.blocks());
+    for (const auto& lv : S.bh32.lev) m = std::max<int64_t>(m, lv.A.blocks());
+  }
   auto scan = [&](const auto& H) {
     for (const auto& lv : H.lev) {
       m = std::max<int64_t>(m, lv.A.nblocks);
@@ -801,6 +795,14 @@ inline int64_t max_parts(const amg_solver& S) {
 template <class F>
 inline auto with_vcycle(amg_solver& S, F fn) {
   VcycleOpts o{S.prm.npre, S.prm.npost, S.prm.relax};
+  if (S.block) {
+    if (S.prm.precision == AMG_MIXED) {
+      BlockVcycle<float> V(&S.bh32, S.Ainv, S.nL);
+      return fn(V);
+    }
+    BlockVcycle<double> V(&S.bh64, S.Ainv, S.nL);
+    return fn(V);
+  }
   if (S.prm.precision == AMG_MIXED) {
     Vcycle<float> V(&S.h32, S.Ainv, S.nL, o);
     return fn(V);
@@ -819,9 +821,17 @@ inline void fin(amg_solver& S, int K, int nparts, int op, hipStream_t s) {
 
 inline const int* skip_of(amg_solver& S) { return &S.st->done; }
 
+// Product with the FP64 fine operator of the Krylov loop (scalar CSR, or
+// block CSR with the scalar epilogue applied row by row).
+template <class G, class E>
+inline int outer_spmv(amg_solver& S, G g, E e, double* partials, const int* skip, hipStream_t s) {
+  if (S.block) return launch_bsr(S.B0, g, PerRow<E>{e}, partials, skip, s);
+  return launch_spmv(S.A0, g, e, partials, skip, s);
+}
+
 // r = f - A x with (r.r, f.f) and the init scalar update.
 inline void enqueue_init(amg_solver& S, hipStream_t s) {
-  int nb = launch_spmv(S.A0, GatherX<double, double>{S.x}, EpiResidNorms{S.r, S.f}, S.partials, nullptr, s);
+  int nb = outer_spmv(S, GatherX<double, double>{S.x}, EpiResidNorms{S.r, S.f}, S.partials, nullptr, s);
   fin(S, 2, nb, kFinInit, s);
 }
 
@@ -836,7 +846,7 @@ inline void enqueue_pcg_start(amg_solver& S, hipStream_t s) {
 inline void enqueue_pcg_iteration(amg_solver& S, hipStream_t s) {
   const int n = static_cast<int>(S.n);
   const int vb = vec_blocks(n);
-  int nb = launch_spmv(S.A0, GatherX<double, double>{S.p}, EpiStoreDot{S.q, S.p}, S.partials, skip_of(S), s);
+  int nb = outer_spmv(S, GatherX<double, double>{S.p}, EpiStoreDot{S.q, S.p}, S.partials, skip_of(S), s);
   fin(S, 1, nb, kFinAlpha, s);
   pcg_update_kernel<<<vb, kVecBS, 0, s>>>(n, S.x, S.r, S.p, S.q, S.st, S.partials);
   AMG_LAUNCHED();
@@ -859,7 +869,7 @@ inline void enqueue_bicg_iteration(amg_solver& S, hipStream_t s) {
   bicg_p_kernel<<<vb, kVecBS, 0, s>>>(n, S.p, S.r, S.v, S.st);
   AMG_LAUNCHED();
   with_vcycle(S, [&](auto& V) { return V.template run<0>(S.p, S.phat, S.partials, skip_of(S), s); });
-  int nb = launch_spmv(S.A0, GatherX<double, double>{S.phat}, EpiStoreDot{S.v, S.rt}, S.partials, skip_of(S), s);
+  int nb = outer_spmv(S, GatherX<double, double>{S.phat}, EpiStoreDot{S.v, S.rt}, S.partials, skip_of(S), s);
   fin(S, 1, nb, kFinBiAlpha, s);
   bicg_s_kernel<<<vb, kVecBS, 0, s>>>(n, S.s, S.r, S.v, S.st, S.partials);
   AMG_LAUNCHED();
@@ -868,7 +878,7 @@ inline void enqueue_bicg_iteration(amg_solver& S, hipStream_t s) {
   AMG_LAUNCHED();
   fin(S, 1, 0, kFinBiHalfDone, s);
   with_vcycle(S, [&](auto& V) { return V.template run<0>(S.s, S.shat, S.partials, skip_of(S), s); });
-  nb = launch_spmv(S.A0, GatherX<double, double>{S.shat}, EpiStoreDot2{S.t, S.s}, S.partials, skip_of(S), s);
+  nb = outer_spmv(S, GatherX<double, double>{S.shat}, EpiStoreDot2{S.t, S.s}, S.partials, skip_of(S), s);
   fin(S, 2, nb, kFinBiOmega, s);
   bicg_xr_kernel<<<vb, kVecBS, 0, s>>>(n, S.x, S.r, S.phat, S.shat, S.s, S.t, S.rt, S.st, S.partials);
   AMG_LAUNCHED();
@@ -1026,7 +1036,7 @@ inline amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, h
     }
     if (k.done == kZeroRhs) break;
     // true residual of the current iterate
-    int nb = launch_spmv(S.A0, GatherX<double, double>{S.x}, EpiResidNorms{S.tmp, S.f}, S.partials, nullptr, s);
+    int nb = outer_spmv(S, GatherX<double, double>{S.x}, EpiResidNorms{S.tmp, S.f}, S.partials, nullptr, s);
     fin(S, 2, nb, kFinTrue, s);
     k = poll(S, s);
     if (k.done == kConverged && k.true_rr > k.tol2 && restarts == 0) {
@@ -1056,7 +1066,7 @@ inline amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, h
   }
   if (info) {
     info->iters = k.iters;
-    info->levels = static_cast<int32_t>(S.host.levels.size());
+    info->levels = static_cast<int32_t>(S.block ? S.bhost.levels.size() : S.host.levels.size());
     info->restarts = restarts;
     info->status = status;
     const bool zero = (k.done == kZeroRhs);
@@ -1065,8 +1075,13 @@ inline amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, h
     info->setup_s = S.setup_s;
     info->solve_s = now_s() - t0;
     double nnz = 0;
-    for (auto& lv : S.host.levels) nnz += double(lv.A.nnz());
-    info->op_complexity = nnz / double(S.host.levels[0].A.nnz());
+    if (S.block) {
+      for (auto& lv : S.bhost.levels) nnz += double(lv.A.nnzb());
+      info->op_complexity = nnz / double(S.bhost.levels[0].A.nnzb());
+    } else {
+      for (auto& lv : S.host.levels) nnz += double(lv.A.nnz());
+      info->op_complexity = nnz / double(S.host.levels[0].A.nnz());
+    }
   }
   if (status == AMG_NOT_CONVERGED) g_last_error = "iteration limit or tolerance not reached";
   if (status == AMG_ERR_BREAKDOWN) g_last_error = "Krylov breakdown (zero inner product)";
@@ -1085,23 +1100,32 @@ struct DeviceSetupOpts {
 inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t s,
                          const DeviceSetupOpts& opts = DeviceSetupOpts{}) {
   AMG_HIP(hipGetDevice(&S.device));
-  S.arena = std::make_unique<DevArena>(alloc, s);
+  if (!S.arena) S.arena = std::make_unique<DevArena>(alloc, s);
   if (opts.standalone) AMG_HIP(hipStreamCreateWithFlags(&S.cap_stream, hipStreamNonBlocking));
   DevArena& ar = *S.arena;
-  const HostLevel& fine = S.host.levels[0];
-  S.n = fine.A.rows;
-  const Csr& AL = S.host.levels.back().A;
+  // the coarsest operator in scalar form; upload_levels sizes f_L, z_L by nL
+  const Csr AL = S.block ? bsr_to_csr(S.bhost.levels.back().A) : S.host.levels.back().A;
   S.nL = static_cast<int32_t>(AL.rows);
   double t = now_s();
-  S.A0 = upload_csr<double>(ar, fine.A);
-  if (S.prm.precision == AMG_MIXED) upload_levels<float>(S, S.h32);
-  else upload_levels<double>(S, S.h64);
+  if (S.block) {
+    const Bsr& fine = S.bhost.levels[0].A;
+    S.n = int64_t(kB) * fine.rows;
+    S.B0 = upload_bsr<double>(ar, fine);
+    if (S.prm.precision == AMG_MIXED) upload_block_levels<float>(ar, S.bhost, S.B0, S.bh32);
+    else upload_block_levels<double>(ar, S.bhost, S.B0, S.bh64);
+  } else {
+    const HostLevel& fine = S.host.levels[0];
+    S.n = fine.A.rows;
+    if (!S.A0.val) S.A0 = upload_csr<double>(ar, fine.A);  // unless uploaded before the setup steps
+    if (S.prm.precision == AMG_MIXED) upload_levels<float>(S, S.h32);
+    else upload_levels<double>(S, S.h64);
+  }
   S.host.phase_s[kPhUpload] += now_s() - t;
   t = now_s();
   coarse_inverse(S, AL, s, alloc, opts.blas);
   S.host.phase_s[kPhCoarse] += now_s() - t;
   t = now_s();
-  if (opts.standalone) {
+  if (opts.standalone && !S.block) {
     if (S.prm.precision == AMG_MIXED) plan_tail<float>(S, S.h32, s);
     else plan_tail<double>(S, S.h64, s);
   }

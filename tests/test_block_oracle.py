@@ -204,7 +204,7 @@ def test_prolongator_is_one_damped_block_jacobi_step_on_the_tentative_basis():
     """P = (I - omega D_F^-1 A_F) P_hat evaluated densely with LAPACK solves,
     and omega = (4/3) / rho with rho the dense Gershgorin bound of D_F^-1 A_F,
     which bounds its spectral radius."""
-    A = _coupled()
+    A = _coupled(5)
     S = ba.strength_graph(A, 0.08)
     agg = sa.aggregate(S)
     A_F, D_F, iso = ba.filtered_matrix(A, S)
@@ -234,8 +234,8 @@ def test_two_grid_closed_form_without_sweeps():
 
 @pytest.mark.parametrize("relax", ["spai0", "jacobi"])
 def test_vcycle_operator_symmetric_spd_linear(relax):
-    A = _coupled(6)
-    h = ba.setup(A, sa.Params(coarse_enough=4 * 20, relax=relax))
+    A = _coupled(5)
+    h = ba.setup(A, sa.Params(coarse_enough=24, relax=relax))
     assert h.nlevels >= 3
     n = A.nb * 4
     Bm = np.column_stack([ba.vcycle(h, e) for e in np.eye(n)])
