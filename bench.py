@@ -58,9 +58,9 @@ def workload_matrix(kind, N):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_poisson150.json")
-# the kernels and the V-cycle driver that picks their gathers and epilogues
+# the kernels, their schedules and the V-cycle driver that picks their gathers and epilogues
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1811_05704_amd", "csrc", f)
-                  for f in ("kernels.hpp", "device.hpp", "solver.hpp", "solver.hip")]
+                  for f in ("kernels.hpp", "device.hpp", "vcycle.hpp")]
 
 
 def kernel_source_hash():

@@ -27,13 +27,15 @@ HIP_SOURCES = ["solver.hip", "serve.hip", "galerkin.hip", "noalloc.hip", "stagin
 
 # Host arithmetic of the setup follows each definition's natural order with
 # separate multiply and add (no contraction), for reproducible hierarchies.
-CXXFLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wextra", "-pthread"]
+CXXFLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wextra", "-pthread",
+            "-I" + os.path.join(ROCM, "include")]
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROCM, "include"), "-Wall",
 ]
-LDFLAGS = ["-shared", "-L" + os.path.join(ROCM, "lib"), "-lrocsolver", "-lrocblas", "-pthread",
+LDFLAGS = ["-shared", "-L" + os.path.join(ROCM, "lib"), "-lrocsolver", "-lrocblas", "-lrocprofiler-sdk-roctx",
+           "-pthread",
            "-Wl,-rpath," + os.path.join(ROCM, "lib")]
 
 

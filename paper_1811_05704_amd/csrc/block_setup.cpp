@@ -384,25 +384,21 @@ Csr bsr_to_csr(const Bsr& A) {
 BlockHierarchy build_block_hierarchy(Bsr A, const SetupParams& prm) {
   if (prm.relax != 0 && prm.relax != 1) bfail(-1, "block values take the SPAI-0 or Jacobi smoother");
   BlockHierarchy H;
-  double t = setup_clock();
-  auto lap = [&](int phase) {
-    const double now = setup_clock();
-    H.phase_s[phase] += now - t;
-    t = now;
-  };
+  PhaseClock clk(H.phase_s);
   while (true) {
     const int64_t n = A.rows;
     const int lvl_no = static_cast<int>(H.levels.size()) + 1;
     if (n * kBlock <= prm.coarse_enough || lvl_no >= prm.max_levels) break;
     const double eps = prm.eps_strong * std::ldexp(1.0, -(lvl_no - 1));
+    clk.enter(kPhStrength);
     Graph S = block_strength_graph(A, eps);
-    lap(kPhStrength);
+    clk.enter(kPhAggregate);
     int32_t nc = 0;
     std::vector<int32_t> agg = aggregate(S, &nc);
-    lap(kPhAggregate);
     if (nc == 0 || nc >= n) break;
     BlockLevel L;
     L.eps = eps;
+    clk.enter(kPhProlong);
     std::vector<double> DF;
     std::vector<uint8_t> isolated;
     const Bsr AF = filtered_matrix(A, S, DF, isolated);
@@ -410,18 +406,18 @@ BlockHierarchy build_block_hierarchy(Bsr A, const SetupParams& prm) {
     for (int64_t i = 0; i < n; ++i) block_inverse(&DF[i * kBB], &Dinv[i * kBB]);
     L.omega = prolongator_damping(AF, Dinv, isolated);
     L.P = smoothed_prolongator(AF, Dinv, tentative(agg, nc), L.omega);
-    lap(kPhProlong);
+    clk.enter(kPhTranspose);
     L.R = block_transpose(L.P);
-    lap(kPhTranspose);
+    clk.enter(kPhSmoother);
     L.M = smoother_blocks(A, prm);
-    lap(kPhSmoother);
+    clk.enter(kPhGalerkin);
     Bsr Ac = block_spgemm(L.R, block_spgemm(A, L.P));
-    lap(kPhGalerkin);
     L.agg = std::move(agg);
     L.A = std::move(A);
     H.levels.push_back(std::move(L));
     A = std::move(Ac);
   }
+  clk.stop();
   if (A.rows * kBlock > prm.max_coarse)
     bfail(-8, "coarsest level has " + std::to_string(A.rows * kBlock) + " unknowns (limit " +
                   std::to_string(prm.max_coarse) + ")");

@@ -24,52 +24,76 @@ namespace amg {
 constexpr int kGjB = 64;   // block size
 constexpr int kGjBS = 256; // threads per workgroup
 
-// P = A_KK^-1 for the kb x kb diagonal block at k0 (in-place Gauss-Jordan in
-// LDS); bad = 1 if a pivot is not positive.
+// P = A_KK^-1 for the kb x kb diagonal block at k0 (Gauss-Jordan in place,
+// one workgroup); bad = 1 if a pivot is not positive.  Thread t keeps 16
+// entries of row t / 4 (columns 16 (t % 4) ..) in registers; each pivot step
+// publishes the scaled pivot row and the pivot column through LDS (double
+// buffered, two barriers per step).
 static __global__ void __launch_bounds__(kGjBS) gj_diag_kernel(int n, const double* __restrict__ A, int k0, int kb,
                                                                double* __restrict__ P, int* bad) {
-  __shared__ double D[kGjB][kGjB + 1];
-  __shared__ double f[kGjB];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kGjB * kGjB; e += kGjBS) {
-    const int r = e / kGjB, c = e % kGjB;
-    D[r][c] = (r < kb && c < kb) ? A[static_cast<int64_t>(k0 + r) * n + k0 + c] : 0.0;
+  static_assert(kGjB == 64 && kGjBS == 256, "thread layout: 64 rows x 4 column groups");
+  __shared__ double prow[2][kGjB];
+  __shared__ double fcol[2][kGjB];
+  __shared__ double pdiag[2];
+  const int t = threadIdx.x;
+  const int r = t >> 2, c0 = (t & 3) * 16;
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = c0 + q;
+    v[q] = (r < kb && c < kb) ? A[static_cast<int64_t>(k0 + r) * n + k0 + c] : 0.0;
   }
-  for (int k = 0; k < kb; ++k) {
-    __syncthreads();
-    const double p = D[k][k];
-    if (tid == 0 && !(p > 0.0)) *bad = 1;
-    if (tid < kb) f[tid] = D[tid][k];
-    __syncthreads();
-    if (tid < kb) D[k][tid] = (tid == k ? 1.0 : D[k][tid]) / p;
-    __syncthreads();
-    for (int e = tid; e < kb * kb; e += kGjBS) {
-      const int r = e / kb, c = e % kb;
-      if (r == k) continue;
-      D[r][c] = (c == k ? 0.0 : D[r][c]) - f[r] * D[k][c];
-    }
-  }
+  if (t == 0) pdiag[0] = v[0];  // D[0][0]
   __syncthreads();
-  for (int e = tid; e < kGjB * kGjB; e += kGjBS) P[e] = D[e / kGjB][e % kGjB];  // zero outside kb x kb
+  for (int k = 0; k < kb; ++k) {
+    const int b = k & 1;
+    const double p = pdiag[b];
+    if (t == 0 && !(p > 0.0)) *bad = 1;
+    if (r == k) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        v[q] = (c0 + q == k ? 1.0 : v[q]) / p;
+        prow[b][c0 + q] = v[q];
+      }
+    }
+    if ((k >> 4) == (t & 3)) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (c0 + q == k) fcol[b][r] = v[q];
+    }
+    __syncthreads();
+    if (r != k) {
+      const double f = fcol[b][r];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = (c0 + q == k ? 0.0 : v[q]) - f * prow[b][c0 + q];
+    }
+    if (r == k + 1 && ((k + 1) >> 4) == (t & 3)) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (c0 + q == k + 1) pdiag[1 - b] = v[q];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) P[r * kGjB + c0 + q] = (r < kb && c0 + q < kb) ? v[q] : 0.0;  // zero outside kb x kb
 }
 
-// A_Kj = P A_Kj for every column j outside the block (one thread per column).
+// A_Kj = P A_Kj for every column j outside the block: a workgroup takes four
+// columns, stages their kb-entry segments in LDS and writes 64 x 4 outputs.
 static __global__ void __launch_bounds__(kGjBS) gj_row_kernel(int n, double* __restrict__ A, int k0, int kb,
                                                               const double* __restrict__ P) {
-  __shared__ double Ps[kGjB * kGjB];
-  for (int e = threadIdx.x; e < kGjB * kGjB; e += kGjBS) Ps[e] = P[e];
+  __shared__ double X[kGjB][4];
+  const int t = threadIdx.x;
+  const int r = t >> 2, jq = t & 3;
+  const int j = blockIdx.x * 4 + jq;
+  const bool col_ok = j < n && !(j >= k0 && j < k0 + kb);
+  X[r][jq] = (col_ok && r < kb) ? A[static_cast<int64_t>(k0 + r) * n + j] : 0.0;
   __syncthreads();
-  const int j = blockIdx.x * kGjBS + threadIdx.x;
-  if (j >= n || (j >= k0 && j < k0 + kb)) return;
-  double x[kGjB];
-#pragma unroll
-  for (int c = 0; c < kGjB; ++c) x[c] = c < kb ? A[static_cast<int64_t>(k0 + c) * n + j] : 0.0;
-  for (int r = 0; r < kb; ++r) {
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < kGjB; ++c) s += Ps[r * kGjB + c] * x[c];
-    A[static_cast<int64_t>(k0 + r) * n + j] = s;
-  }
+  if (!col_ok || r >= kb) return;
+  const double* pr = P + r * kGjB;
+  double s = 0.0;
+  for (int c = 0; c < kb; ++c) s += pr[c] * X[c][jq];
+  A[static_cast<int64_t>(k0 + r) * n + j] = s;
 }
 
 // A_ij -= A_iK A_Kj for i, j outside the block: 64 x 64 output tiles, each
@@ -114,29 +138,28 @@ static __global__ void __launch_bounds__(kGjBS) gj_trailing_kernel(int n, double
   }
 }
 
-// A_iK = -A_iK P for every row i outside the block (one thread per row), and
-// A_KK = P.
+// A_iK = -A_iK P for every row i outside the block, and A_KK = P: a
+// workgroup takes four rows, stages their kb-entry segments in LDS and writes
+// 4 x 64 outputs.
 static __global__ void __launch_bounds__(kGjBS) gj_col_kernel(int n, double* __restrict__ A, int k0, int kb,
                                                               const double* __restrict__ P) {
-  __shared__ double Ps[kGjB * kGjB];
-  for (int e = threadIdx.x; e < kGjB * kGjB; e += kGjBS) Ps[e] = P[e];
-  __syncthreads();
-  const int i = blockIdx.x * kGjBS + threadIdx.x;
-  if (i >= n) return;
+  __shared__ double X[4][kGjB];
+  const int t = threadIdx.x;
+  const int iq = t >> 6, c = t & 63;
+  const int i = blockIdx.x * 4 + iq;
+  const bool row_ok = i < n;
   double* row = A + static_cast<int64_t>(i) * n + k0;
-  if (i >= k0 && i < k0 + kb) {
-    for (int c = 0; c < kb; ++c) row[c] = Ps[(i - k0) * kGjB + c];
+  const bool in_block = i >= k0 && i < k0 + kb;
+  X[iq][c] = (row_ok && !in_block && c < kb) ? row[c] : 0.0;
+  __syncthreads();
+  if (!row_ok || c >= kb) return;
+  if (in_block) {
+    row[c] = P[(i - k0) * kGjB + c];
     return;
   }
-  double x[kGjB];
-#pragma unroll
-  for (int r = 0; r < kGjB; ++r) x[r] = r < kb ? row[r] : 0.0;
-  for (int c = 0; c < kb; ++c) {
-    double s = 0.0;
-#pragma unroll
-    for (int r = 0; r < kGjB; ++r) s += x[r] * Ps[r * kGjB + c];
-    row[c] = -s;
-  }
+  double s = 0.0;
+  for (int q = 0; q < kb; ++q) s += X[iq][q] * P[q * kGjB + c];
+  row[c] = -s;
 }
 
 // In-place inverse of the dense row-major n x n matrix A (device), scratch P
@@ -145,13 +168,13 @@ inline hipError_t gj_inverse_spd(int n, double* A, double* P, int* bad, hipStrea
   hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), s);
   if (e != hipSuccess) return e;
   const int nt = (n + kGjB - 1) / kGjB;
-  const int lines = (n + kGjBS - 1) / kGjBS;
+  const int quads = (n + 3) / 4;
   for (int K = 0; K < nt; ++K) {
     const int k0 = K * kGjB, kb = (n - k0 < kGjB) ? n - k0 : kGjB;
     gj_diag_kernel<<<1, kGjBS, 0, s>>>(n, A, k0, kb, P, bad);
-    gj_row_kernel<<<lines, kGjBS, 0, s>>>(n, A, k0, kb, P);
+    gj_row_kernel<<<quads, kGjBS, 0, s>>>(n, A, k0, kb, P);
     gj_trailing_kernel<<<dim3(nt, nt), kGjBS, 0, s>>>(n, A, k0, kb);
-    gj_col_kernel<<<lines, kGjBS, 0, s>>>(n, A, k0, kb, P);
+    gj_col_kernel<<<quads, kGjBS, 0, s>>>(n, A, k0, kb, P);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -16,12 +16,22 @@
 //
 // The same product forms the smoothed prolongator: P = P_hat - omega D_F^-1
 // (A_F P_hat), where A_F P_hat sums, in column order, the filtered entries of
-// a row by aggregate, which is what the host does.  The strength graph is a
-// per-entry test; only the greedy aggregation (sequential by its definition),
-// the transpose and the smoother diagonal stay on the host.
+// a row by aggregate, which is what the host does.  The strength graph and the
+// smoother diagonal are per-row formulas; R = P^T scatters the entries by
+// column and then orders each row of R by column, which fixes the order the
+// host's transpose gives.  Only the greedy aggregation (sequential by its
+// definition) stays on the host.
 
 #include <rocprim/block/block_radix_sort.hpp>
 #include <rocprim/block/block_scan.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include <condition_variable>
+#include <deque>
+#include <exception>
+#include <functional>
+#include <mutex>
+#include <thread>
 
 #include "device.hpp"
 #include "galerkin.hpp"
@@ -219,10 +229,16 @@ DMat upload_mat(DevArena& ar, const Csr& M, hipStream_t s) {
   return d;
 }
 
-// C = A B with A's host row pointers (Ahost) for the block schedule; C's row
+// Row lengths of A on the host: ptr[i + 1] - ptr[i] + extra.
+struct HostRows {
+  const int64_t* ptr;
+  int64_t extra;
+};
+
+// C = A B with A's row lengths on the host (for the block schedule); C's row
 // pointers are returned on the host too.  False: a row does not fit a block.
-bool spgemm_dev(DevArena& ar, DevArena& out, const std::vector<int64_t>& Aptr_host, const DMat& A, const DMat& B,
-                DMat& C, std::vector<int64_t>& Cptr, hipStream_t s) {
+bool spgemm_dev(DevArena& ar, DevArena& out, HostRows arows, const DMat& A, const DMat& B, DMat& C,
+                std::vector<int64_t>& Cptr, hipStream_t s) {
   const int colbits = bits_for(B.cols);
   if (colbits > kGMaxColBits) return false;
   const int m = A.rows;
@@ -241,7 +257,7 @@ bool spgemm_dev(DevArena& ar, DevArena& out, const std::vector<int64_t>& Aptr_ho
   std::vector<int32_t> blk{0};
   int64_t prods = 0, ents = 0;
   for (int i = 0; i < m; ++i) {
-    const int64_t len = Aptr_host[i + 1] - Aptr_host[i];
+    const int64_t len = arows.ptr[i + 1] - arows.ptr[i] + arows.extra;
     if (L[i] > kGCap || len > kGMaxEntries) return false;
     if (prods + L[i] > kGCap || ents + len > kGMaxEntries || i - blk.back() >= kGMaxRows) {
       blk.push_back(i);
@@ -411,6 +427,82 @@ __global__ void __launch_bounds__(256) prolongator_finish_kernel(DMat C, const i
   }
 }
 
+// ------------------------------------------------------------------ transpose, smoother
+
+// Entries per column of M (the row lengths of M^T).
+__global__ void __launch_bounds__(256) col_count_kernel(DMat M, int32_t* cnt) {
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < M.nnz; e += static_cast<int64_t>(gridDim.x) * 256)
+    atomicAdd(&cnt[M.col[e]], 1);
+}
+
+// Entry (i, j) of M goes to row j of T at the slot it takes from pos[j]; the
+// slots of a row are filled in no fixed order (rank_rows_kernel fixes it).
+__global__ void __launch_bounds__(256) transpose_scatter_kernel(DMat M, int32_t* pos, int32_t* Tc, double* Tv) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < M.rows; i += gridDim.x * 256)
+    for (int e = M.ptr[i]; e < M.ptr[i + 1]; ++e) {
+      const int p = atomicAdd(&pos[M.col[e]], 1);
+      Tc[p] = i;
+      Tv[p] = M.val[e];
+    }
+}
+
+// Row j of T in ascending column order from its slots in (Uc, Uv), filled in
+// no fixed order: each entry goes to its rank among the row's columns (the
+// columns of a row are distinct), one thread per entry.
+__global__ void __launch_bounds__(256) rank_rows_kernel(int rows, int64_t nnz, const int32_t* Tp, const int32_t* Uc,
+                                                        const double* Uv, int32_t* Tc, double* Tv) {
+  for (int64_t q = blockIdx.x * 256 + threadIdx.x; q < nnz; q += static_cast<int64_t>(gridDim.x) * 256) {
+    int lo = 0, hi = rows - 1;  // the row holding slot q: last j with Tp[j] <= q
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (Tp[mid] <= q) lo = mid;
+      else hi = mid - 1;
+    }
+    const int b = Tp[lo], e = Tp[lo + 1];
+    const int c = Uc[q];
+    int rank = 0;
+    for (int k = b; k < e; ++k) rank += Uc[k] < c ? 1 : 0;
+    Tc[b + rank] = c;
+    Tv[b + rank] = Uv[q];
+  }
+}
+
+// Row pointers of the filtered matrix: row i holds the diagonal and the
+// strong entries, AFp[i] = Sp[i] + i.
+__global__ void __launch_bounds__(256) af_ptr_kernel(int n, const int32_t* Sp, int32_t* AFp) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i <= n; i += gridDim.x * 256) AFp[i] = Sp[i] + i;
+}
+
+// flag[i] = 1 when node i belongs to an aggregate (its row of P_hat holds one entry).
+__global__ void __launch_bounds__(256) aggregated_kernel(int n, const int32_t* agg, int32_t* flag) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) flag[i] = agg[i] >= 0 ? 1 : 0;
+}
+
+// Tentative prolongator P_hat: entry 1 at (i, agg_i) for every aggregated node.
+__global__ void __launch_bounds__(256) tentative_kernel(int n, const int32_t* agg, const int32_t* php, int32_t* phc,
+                                                        double* phv) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    if (agg[i] >= 0) {
+      phc[php[i]] = agg[i];
+      phv[php[i]] = 1.0;
+    }
+}
+
+// Smoother diagonal, the host's formula and summation order: SPAI-0
+// m_i = a_ii / sum_j a_ij^2 (relax 0), damped Jacobi omega / a_ii (relax 1),
+// 1 / a_ii for the Chebyshev scaling (relax 2).
+__global__ void __launch_bounds__(256) smoother_kernel(DMat A, int relax, double omega, double* m) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < A.rows; i += gridDim.x * 256) {
+    double aii = 0.0, sq = 0.0;
+    for (int e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+      const double v = A.val[e];
+      sq += v * v;
+      if (A.col[e] == i) aii = v;
+    }
+    m[i] = (relax == 0) ? aii / sq : (relax == 1) ? omega / aii : 1.0 / aii;
+  }
+}
+
 int grid_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096))); }
 
 // Waits for the copy: h may be a local of a step that a later allocation
@@ -423,7 +515,8 @@ void download(std::vector<T>& h, const T* d, size_t n, hipStream_t s) {
 
 class DeviceSetupAccel final : public SetupAccel {
  public:
-  DeviceSetupAccel(const amg_allocator* alloc, hipStream_t s, const DeviceCsrRef* fine) : stream_(s) {
+  DeviceSetupAccel(const amg_allocator* alloc, hipStream_t s, const DeviceCsrRef* fine, bool keep)
+      : stream_(s), keep_(keep) {
     if (alloc) {
       alloc_ = *alloc;
       has_alloc_ = true;
@@ -434,47 +527,67 @@ class DeviceSetupAccel final : public SetupAccel {
     }
   }
 
-  void begin_level(const Csr& A, bool from_galerkin) override {
-    s_ok_ = p_ok_ = have_A_ = false;
-    const bool first = level_++ == 0;
-    work_ = arena();
+  ~DeviceSetupAccel() override {
     try {
-      if (from_galerkin && next_) {
-        a_ = std::move(next_);
-        dA_ = dAc_;
-      } else if (first && has_fine_ && fine_.rows == A.rows && fine_.nnz == A.nnz()) {
-        // the caller's device copy of level 1 (read only by the steps)
-        next_.reset();
-        a_.reset();
-        dA_.rows = fine_.rows;
-        dA_.cols = fine_.cols;
-        dA_.nnz = fine_.nnz;
-        dA_.ptr = const_cast<int32_t*>(fine_.ptr);
-        dA_.col = const_cast<int32_t*>(fine_.col);
-        dA_.val = const_cast<double*>(fine_.val);
-      } else {
-        next_.reset();
-        a_ = arena();
-        dA_ = upload_mat(*a_, A, stream_);
+      finish_host_copies();
+    } catch (...) {
+    }
+    if (copier_.joinable()) {
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        stop_ = true;
       }
+      cv_.notify_all();
+      copier_.join();
+    }
+    if (copy_stream_) (void)hipStreamDestroy(copy_stream_);
+  }
+
+  void begin_level(const Csr& A, bool from_galerkin) override {
+    s_ok_ = p_ok_ = r_ok_ = have_A_ = false;
+    cur_ = level_++;
+    if (lv_.size() < static_cast<size_t>(cur_ + 1)) lv_.resize(cur_ + 1);
+    if (!keep_ && cur_ > 0) lv_[cur_ - 1] = Level{};  // only this level's A is still needed
+    work_ = arena();
+    Level& L = lv_[cur_];
+    try {
+      if (from_galerkin && L.A.val) {
+        // the previous level's product, already in L's storage
+      } else if (cur_ == 0 && has_fine_ && fine_.rows == A.rows && fine_.nnz == A.nnz()) {
+        // the caller's device copy of level 1 (read only by the steps)
+        L.A.rows = fine_.rows;
+        L.A.cols = fine_.cols;
+        L.A.nnz = fine_.nnz;
+        L.A.ptr = const_cast<int32_t*>(fine_.ptr);
+        L.A.col = const_cast<int32_t*>(fine_.col);
+        L.A.val = const_cast<double*>(fine_.val);
+      } else {
+        finish_host_copies();  // A's values come from the host
+        L = Level{};
+        L.ar = arena();
+        L.A = upload_mat(*L.ar, A, stream_);
+      }
+      if (!L.ar) L.ar = arena();
       have_A_ = true;
     } catch (const DevError& e) {
       if (e.code != AMG_ERR_OOM) throw;
+      L = Level{};
     }
   }
 
   bool strength(const Csr& A, double eps, Graph& S) override {
-    if (!have_A_) return false;
+    if (!have_A_) return host_step();
+    const DMat& dA = lv_[cur_].A;
     return guard([&] {
-      const int n = dA_.rows;
+      const int n = dA.rows;
       d_ = work_->get<double>(n);
-      strong_ = work_->get<uint8_t>(std::max<int64_t>(dA_.nnz, 1));
+      strong_ = work_->get<uint8_t>(std::max<int64_t>(dA.nnz, 1));
       int32_t* cnt = work_->get<int32_t>(n);
       int32_t* unsupported = work_->get<int32_t>(1);
       AMG_HIP(hipMemsetAsync(unsupported, 0, sizeof(int32_t), stream_));
-      diag_kernel<<<grid_for(n), 256, 0, stream_>>>(dA_, d_);
+      diag_kernel<<<grid_for(n), 256, 0, stream_>>>(dA, d_);
       AMG_LAUNCHED();
-      strength_kernel<<<grid_for(n), 256, 0, stream_>>>(dA_, d_, eps * eps, strong_, cnt, unsupported);
+      strength_kernel<<<grid_for(n), 256, 0, stream_>>>(dA, d_, eps * eps, strong_, cnt, unsupported);
       AMG_LAUNCHED();
       std::vector<int32_t> ch, ah;
       download(ch, cnt, n, stream_);
@@ -486,7 +599,7 @@ class DeviceSetupAccel final : public SetupAccel {
       std::vector<int32_t> p32(S.ptr.begin(), S.ptr.end());
       Sp_ = work_->upload(p32.data(), p32.size());
       int32_t* Si = work_->get<int32_t>(std::max<int64_t>(S.ptr[n], 1));
-      strong_fill_kernel<<<grid_for(n), 256, 0, stream_>>>(dA_, strong_, Sp_, Si);
+      strong_fill_kernel<<<grid_for(n), 256, 0, stream_>>>(dA, strong_, Sp_, Si);
       AMG_LAUNCHED();
       download(S.idx, Si, S.ptr[n], stream_);
       AMG_HIP(hipStreamSynchronize(stream_));  // p32 is a pageable temporary
@@ -498,130 +611,335 @@ class DeviceSetupAccel final : public SetupAccel {
 
   bool prolongator(const Csr& A, const Graph& S, const std::vector<int32_t>& agg, int32_t nc, Csr& P,
                    double* omega) override {
-    if (!s_ok_) return false;
+    if (!s_ok_) return host_step();
+    Level& L = lv_[cur_];
+    const DMat& dA = L.A;
     return guard([&] {
-      const int n = dA_.rows;
-      // A_F on the device, dF, ratio, isolated flags
-      std::vector<int64_t> AFp(n + 1);
-      for (int i = 0; i <= n; ++i) AFp[i] = S.ptr[i] + i;
-      std::vector<int32_t> afp32(AFp.begin(), AFp.end());
+      const int n = dA.rows;
+      // A_F on the device (row i: the diagonal and the strong entries), dF,
+      // ratio, isolated flags
       DMat AF;
       AF.rows = n;
       AF.cols = n;
-      AF.nnz = AFp[n];
-      AF.ptr = work_->upload(afp32.data(), afp32.size());
+      AF.nnz = S.ptr[n] + n;
+      AF.ptr = work_->get<int32_t>(n + 1);
       AF.col = work_->get<int32_t>(std::max<int64_t>(AF.nnz, 1));
       AF.val = work_->get<double>(std::max<int64_t>(AF.nnz, 1));
+      af_ptr_kernel<<<grid_for(n + 1), 256, 0, stream_>>>(n, Sp_, AF.ptr);
+      AMG_LAUNCHED();
       dF_ = work_->get<double>(n);
       double* ratio = work_->get<double>(n);
       uint8_t* iso = work_->get<uint8_t>(n);
-      filtered_kernel<<<grid_for(n), 256, 0, stream_>>>(dA_, strong_, Sp_, dF_, ratio, iso, AF.col, AF.val);
+      filtered_kernel<<<grid_for(n), 256, 0, stream_>>>(dA, strong_, Sp_, dF_, ratio, iso, AF.col, AF.val);
       AMG_LAUNCHED();
       const int nbm = grid_for(n);
       double* part = work_->get<double>(nbm);
       ratio_max_kernel<<<nbm, 256, 0, stream_>>>(n, ratio, iso, part);
       AMG_LAUNCHED();
-      std::vector<double> ph;
-      download(ph, part, nbm, stream_);
-      // P_hat: one entry 1 per aggregated row
-      std::vector<int32_t> php(n + 1, 0), phc;
-      for (int i = 0; i < n; ++i) {
-        php[i + 1] = php[i] + (agg[i] >= 0 ? 1 : 0);
-        if (agg[i] >= 0) phc.push_back(agg[i]);
-      }
-      std::vector<double> phv(phc.size(), 1.0);
+      // P_hat: one entry 1 per aggregated row (row pointers by a scan of the flags)
+      int32_t* agg_d = work_->upload(agg.data(), agg.size());
       DMat Ph;
       Ph.rows = n;
       Ph.cols = nc;
-      Ph.nnz = static_cast<int64_t>(phc.size());
-      Ph.ptr = work_->upload(php.data(), php.size());
-      Ph.col = work_->upload(phc.data(), std::max<size_t>(phc.size(), 1));
-      Ph.val = work_->upload(phv.data(), std::max<size_t>(phv.size(), 1));
-      int32_t* agg_d = work_->upload(agg.data(), agg.size());
-      AMG_HIP(hipStreamSynchronize(stream_));  // temporaries above are pageable
+      Ph.nnz = n;  // at most
+      Ph.ptr = work_->get<int32_t>(n + 1);
+      Ph.col = work_->get<int32_t>(std::max(n, 1));
+      Ph.val = work_->get<double>(std::max(n, 1));
+      int32_t* flag = work_->get<int32_t>(std::max(n, 1));
+      aggregated_kernel<<<grid_for(n), 256, 0, stream_>>>(n, agg_d, flag);
+      AMG_LAUNCHED();
+      AMG_HIP(hipMemsetAsync(Ph.ptr, 0, sizeof(int32_t), stream_));
+      size_t scan_bytes = 0;
+      AMG_HIP(rocprim::inclusive_scan(nullptr, scan_bytes, flag, Ph.ptr + 1, static_cast<size_t>(n),
+                                      rocprim::plus<int32_t>(), stream_));
+      void* scan_tmp = work_->raw(scan_bytes);
+      AMG_HIP(rocprim::inclusive_scan(scan_tmp, scan_bytes, flag, Ph.ptr + 1, static_cast<size_t>(n),
+                                      rocprim::plus<int32_t>(), stream_));
+      tentative_kernel<<<grid_for(n), 256, 0, stream_>>>(n, agg_d, Ph.ptr, Ph.col, Ph.val);
+      AMG_LAUNCHED();
+      std::vector<double> ph;
+      download(ph, part, nbm, stream_);
       double rho = -1.0;
       for (double v : ph) rho = std::max(rho, v);
       if (rho < 0.0) rho = 1.0;  // no non-isolated row
       const double om = (4.0 / 3.0) / rho;
       std::vector<int64_t> Pptr;
-      if (!spgemm_dev(*work_, *work_, AFp, AF, Ph, dP_, Pptr, stream_)) return false;
-      prolongator_finish_kernel<<<grid_for(n), 256, 0, stream_>>>(dP_, agg_d, dF_, om);
+      DMat dP;
+      if (!spgemm_dev(*work_, *L.ar, HostRows{S.ptr.data(), 1}, AF, Ph, dP, Pptr, stream_)) return false;
+      prolongator_finish_kernel<<<grid_for(n), 256, 0, stream_>>>(dP, agg_d, dF_, om);
       AMG_LAUNCHED();
-      Csr out;
-      out.rows = n;
-      out.cols = nc;
-      out.ptr = std::move(Pptr);
-      download(out.col, dP_.col, dP_.nnz, stream_);
-      download(out.val, dP_.val, dP_.nnz, stream_);
-      AMG_HIP(hipStreamSynchronize(stream_));
+      P = Csr{};
+      P.rows = n;
+      P.cols = nc;
+      P.ptr = std::move(Pptr);
+      to_host(P.col, dP.col, dP.nnz);
+      to_host(P.val, dP.val, dP.nnz);
       (void)A;
-      P = std::move(out);
       *omega = om;
+      L.P = dP;
       p_ok_ = true;
       return true;
     });
   }
 
-  bool galerkin(const Csr& R, const Csr& A, const Csr& P, Csr& Ac) override {
-    if (!have_A_) return false;
+  bool transpose(const Csr& P, Csr& R) override {
+    // Only worth it when the levels stay on the device: R is then made there
+    // anyway and the solve uses that copy.
+    if (!p_ok_ || !keep_) return host_step();
+    Level& L = lv_[cur_];
     return guard([&] {
-      const DMat dP = p_ok_ ? dP_ : upload_mat(*work_, P, stream_);
-      const DMat dR = upload_mat(*work_, R, stream_);
-      DMat AP;
-      std::vector<int64_t> APptr, Cptr;
-      if (!spgemm_dev(*work_, *work_, A.ptr, dA_, dP, AP, APptr, stream_)) return false;
-      next_ = arena();
-      if (!spgemm_dev(*work_, *next_, R.ptr, dR, AP, dAc_, Cptr, stream_)) {
-        next_.reset();
-        return false;
+      const DMat& dP = L.P;
+      const int nc = dP.cols;
+      int32_t* cnt = work_->get<int32_t>(std::max(nc, 1));
+      AMG_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * std::max(nc, 1), stream_));
+      if (dP.nnz) {
+        col_count_kernel<<<grid_for(dP.nnz), 256, 0, stream_>>>(dP, cnt);
+        AMG_LAUNCHED();
       }
-      Csr out;
-      out.rows = dAc_.rows;
-      out.cols = dAc_.cols;
-      out.ptr = std::move(Cptr);
-      download(out.col, dAc_.col, dAc_.nnz, stream_);
-      download(out.val, dAc_.val, dAc_.nnz, stream_);
-      AMG_HIP(hipStreamSynchronize(stream_));
-      Ac = std::move(out);
+      std::vector<int32_t> ch;
+      download(ch, cnt, nc, stream_);
+      R = Csr{};
+      R.rows = nc;
+      R.cols = dP.rows;
+      R.ptr.assign(nc + 1, 0);
+      for (int j = 0; j < nc; ++j) R.ptr[j + 1] = R.ptr[j] + ch[j];
+      std::vector<int32_t> p32(R.ptr.begin(), R.ptr.end());
+      DMat dR;
+      dR.rows = nc;
+      dR.cols = dP.rows;
+      dR.nnz = dP.nnz;
+      dR.ptr = L.ar->upload(p32.data(), p32.size());
+      dR.col = L.ar->get<int32_t>(std::max<int64_t>(dR.nnz, 1));
+      dR.val = L.ar->get<double>(std::max<int64_t>(dR.nnz, 1));
+      if (dP.nnz) {
+        int32_t* pos = work_->get<int32_t>(std::max(nc, 1));
+        int32_t* Uc = work_->get<int32_t>(dP.nnz);
+        double* Uv = work_->get<double>(dP.nnz);
+        AMG_HIP(hipMemcpyAsync(pos, dR.ptr, sizeof(int32_t) * nc, hipMemcpyDeviceToDevice, stream_));
+        transpose_scatter_kernel<<<grid_for(dP.rows), 256, 0, stream_>>>(dP, pos, Uc, Uv);
+        AMG_LAUNCHED();
+        rank_rows_kernel<<<grid_for(dP.nnz), 256, 0, stream_>>>(nc, dP.nnz, dR.ptr, Uc, Uv, dR.col, dR.val);
+        AMG_LAUNCHED();
+      }
+      to_host(R.col, dR.col, dR.nnz);
+      to_host(R.val, dR.val, dR.nnz);
+      (void)P;
+      L.R = dR;
+      r_ok_ = true;
       return true;
     });
   }
 
- private:
-  std::unique_ptr<DevArena> arena() { return std::make_unique<DevArena>(has_alloc_ ? &alloc_ : nullptr, stream_); }
+  bool smoother(const Csr& A, const SetupParams& prm, std::vector<double>& m) override {
+    if (!have_A_ || !keep_ || prm.relax < 0 || prm.relax > 2) return host_step();
+    Level& L = lv_[cur_];
+    return guard([&] {
+      const int n = L.A.rows;
+      double* dm = L.ar->get<double>(std::max(n, 1));
+      smoother_kernel<<<grid_for(n), 256, 0, stream_>>>(L.A, prm.relax, prm.jacobi_omega, dm);
+      AMG_LAUNCHED();
+      to_host(m, static_cast<const double*>(dm), n);
+      (void)A;
+      L.m = dm;
+      return true;
+    });
+  }
 
-  // Runs a step; an allocation failure leaves the step to the host.
-  template <class F>
-  bool guard(F fn) {
-    try {
-      return fn();
-    } catch (const DevError& e) {
-      if (e.code != AMG_ERR_OOM) throw;
-      next_.reset();
-      return false;
+  bool galerkin(const Csr& R, const Csr& A, const Csr& P, Csr& Ac) override {
+    if (!have_A_) return host_step();
+    return guard([&] {
+      {
+        Level& L = lv_[cur_];
+        if (!p_ok_ || !r_ok_) finish_host_copies();  // P or R come from the host
+        if (!p_ok_) L.P = upload_mat(*L.ar, P, stream_);
+        if (!r_ok_) L.R = upload_mat(*L.ar, R, stream_);
+      }
+      DMat AP;
+      std::vector<int64_t> APptr, Cptr;
+      if (!spgemm_dev(*work_, *work_, HostRows{A.ptr.data(), 0}, lv_[cur_].A, lv_[cur_].P, AP, APptr, stream_))
+        return false;
+      if (lv_.size() < static_cast<size_t>(cur_ + 2)) lv_.resize(cur_ + 2);
+      Level& N = lv_[cur_ + 1];
+      N = Level{};
+      N.ar = arena();
+      DMat dAc;
+      if (!spgemm_dev(*work_, *N.ar, HostRows{R.ptr.data(), 0}, lv_[cur_].R, AP, dAc, Cptr, stream_)) {
+        N = Level{};
+        return false;
+      }
+      N.A = dAc;
+      Ac = Csr{};
+      Ac.rows = dAc.rows;
+      Ac.cols = dAc.cols;
+      Ac.ptr = std::move(Cptr);
+      to_host(Ac.col, dAc.col, dAc.nnz);
+      to_host(Ac.val, dAc.val, dAc.nnz);
+      return true;
+    });
+  }
+
+  // Waits for the copies to_host started; rethrows the first error of one.
+  void finish_host_copies() override {
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_done_.wait(lk, [&] { return q_.empty() && busy_ == 0; });
+    if (err_) {
+      std::exception_ptr e = err_;
+      err_ = nullptr;
+      std::rethrow_exception(e);
     }
   }
 
+  bool level_refs(int l, DeviceLevelRefs* out) const {
+    if (!keep_ || l < 0 || static_cast<size_t>(l) >= lv_.size()) return false;
+    const Level& L = lv_[l];
+    *out = DeviceLevelRefs{};
+    out->A = ref(L.A);
+    out->P = ref(L.P);
+    out->R = ref(L.R);
+    out->m = L.m;
+    return true;
+  }
+
+ private:
+  // Device copies of one level (FP64): A (the caller's for level 1), P, R =
+  // P^T and the smoother diagonal, in the level's own arena.
+  struct Level {
+    std::unique_ptr<DevArena> ar;
+    DMat A, P, R;
+    double* m = nullptr;
+  };
+
+  static DeviceCsrRef ref(const DMat& M) {
+    DeviceCsrRef r;
+    if (!M.val) return r;
+    r.rows = M.rows;
+    r.cols = M.cols;
+    r.nnz = M.nnz;
+    r.ptr = M.ptr;
+    r.col = M.col;
+    r.val = M.val;
+    return r;
+  }
+
+  std::unique_ptr<DevArena> arena() { return std::make_unique<DevArena>(has_alloc_ ? &alloc_ : nullptr, stream_); }
+
+  // Host copy of n device elements into h.  With kept levels the copy runs on
+  // a thread and stream of its own, after the work enqueued so far on the
+  // setup stream, and overlaps the following steps (the device memory lives
+  // until the accelerator goes); otherwise it completes before returning.
+  template <class T>
+  void to_host(std::vector<T>& h, const T* d, int64_t n) {
+    if (!keep_) {
+      download(h, d, static_cast<size_t>(n), stream_);
+      return;
+    }
+    if (!copy_stream_) AMG_HIP(hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking));
+    hipEvent_t ev = nullptr;
+    AMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    const hipError_t e = hipEventRecord(ev, stream_);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(ev);
+      AMG_HIP(e);
+    }
+    std::vector<T>* dst = &h;
+    hipStream_t cs = copy_stream_;
+    enqueue([dst, d, n, ev, cs] {
+      struct Ev {
+        hipEvent_t e;
+        ~Ev() { (void)hipEventDestroy(e); }
+      } guard_ev{ev};
+      AMG_HIP(hipStreamWaitEvent(cs, ev, 0));
+      download(*dst, d, static_cast<size_t>(n), cs);
+    });
+  }
+
+  void enqueue(std::function<void()> job) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      q_.push_back(std::move(job));
+      if (!copier_.joinable()) copier_ = std::thread([this] { copy_loop(); });
+    }
+    cv_.notify_one();
+  }
+
+  void copy_loop() {
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+      cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
+      if (q_.empty()) return;  // stopping
+      std::function<void()> job = std::move(q_.front());
+      q_.pop_front();
+      ++busy_;
+      lk.unlock();
+      std::exception_ptr e;
+      try {
+        job();
+      } catch (...) {
+        e = std::current_exception();
+      }
+      lk.lock();
+      --busy_;
+      if (e && !err_) err_ = e;
+      if (q_.empty() && busy_ == 0) cv_done_.notify_all();
+    }
+  }
+
+  // A step left to the host reads the host copies of its inputs.
+  bool host_step() {
+    finish_host_copies();
+    return false;
+  }
+
+  // Runs a step; a false result (a row that does not fit the device kernels,
+  // an allocation failure) leaves the step to the host.
+  template <class F>
+  bool guard(F fn) {
+    bool ok = false;
+    try {
+      ok = fn();
+    } catch (const DevError& e) {
+      if (e.code != AMG_ERR_OOM) throw;
+      ok = false;
+    }
+    return ok ? true : host_step();
+  }
+
   hipStream_t stream_;
+  bool keep_;
   amg_allocator alloc_{};
   bool has_alloc_ = false;
-  std::unique_ptr<DevArena> a_, next_, work_;  // A of the level, next level's A, level scratch
-  DMat dA_, dAc_, dP_;
+  std::vector<Level> lv_;
+  std::unique_ptr<DevArena> work_;  // scratch of the current level
+  int cur_ = -1;
   double* d_ = nullptr;
   double* dF_ = nullptr;
   uint8_t* strong_ = nullptr;
   int32_t* Sp_ = nullptr;
-  bool have_A_ = false, s_ok_ = false, p_ok_ = false;
+  bool have_A_ = false, s_ok_ = false, p_ok_ = false, r_ok_ = false;
   DeviceCsrRef fine_;
   bool has_fine_ = false;
   int level_ = 0;
+  // host copies in flight (kept levels only)
+  hipStream_t copy_stream_ = nullptr;
+  std::thread copier_;
+  std::mutex mu_;
+  std::condition_variable cv_, cv_done_;
+  std::deque<std::function<void()>> q_;
+  int busy_ = 0;
+  bool stop_ = false;
+  std::exception_ptr err_;
 };
 
 }  // namespace
 
 std::unique_ptr<SetupAccel> make_device_setup_accel(const amg_allocator* alloc, hipStream_t stream,
-                                                    const DeviceCsrRef* fine) {
-  return std::make_unique<DeviceSetupAccel>(alloc, stream, fine);
+                                                    const DeviceCsrRef* fine, bool keep_levels) {
+  return std::make_unique<DeviceSetupAccel>(alloc, stream, fine, keep_levels);
+}
+
+bool device_level_refs(const SetupAccel* accel, int level, DeviceLevelRefs* out) {
+  const auto* d = dynamic_cast<const DeviceSetupAccel*>(accel);
+  return d && d->level_refs(level, out);
 }
 
 }  // namespace amg

@@ -27,14 +27,26 @@ namespace amg {
 // `fine` (optional) is a device copy of the level-1 matrix the caller already
 // holds (int32 row pointers and columns, FP64 values, valid while the
 // accelerator lives); level 1 then uses it instead of uploading A again.
+// With `keep_levels` the accelerator keeps every level's device matrices
+// (A, P, R = P^T, smoother diagonal) until it is destroyed, for
+// device_level_refs; otherwise a level's storage goes when the next begins.
 struct DeviceCsrRef {
   int32_t rows = 0, cols = 0;
   int64_t nnz = 0;
   const int32_t* ptr = nullptr;
   const int32_t* col = nullptr;
-  const double* val = nullptr;
+  const double* val = nullptr;  // NULL: not on the device
 };
 std::unique_ptr<SetupAccel> make_device_setup_accel(const amg_allocator* alloc, hipStream_t stream,
-                                                    const DeviceCsrRef* fine = nullptr);
+                                                    const DeviceCsrRef* fine = nullptr, bool keep_levels = false);
+
+// FP64 device copies the accelerator made for level `level` (0-based), equal
+// to the host hierarchy's; a member with val == NULL (m == NULL) was made on
+// the host.  False when the accelerator keeps no levels or has no such level.
+struct DeviceLevelRefs {
+  DeviceCsrRef A, P, R;
+  const double* m = nullptr;
+};
+bool device_level_refs(const SetupAccel* accel, int level, DeviceLevelRefs* out);
 
 }  // namespace amg

@@ -32,6 +32,8 @@
 #include <cstring>
 #include <thread>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 namespace amg {
 
 namespace {
@@ -513,54 +515,82 @@ double setup_clock() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-HostHierarchy build_hierarchy(Csr A, const SetupParams& prm, SetupAccel* accel) {
+TraceRange::TraceRange(const char* name) { roctxRangePushA(name); }
+TraceRange::~TraceRange() { roctxRangePop(); }
+
+namespace {
+const char* const kPhaseRange[kPhCount] = {
+    "amg setup: input",       "amg setup: strength", "amg setup: aggregate", "amg setup: prolongator",
+    "amg setup: transpose",   "amg setup: smoother", "amg setup: galerkin",  "amg setup: upload",
+    "amg setup: coarse inverse", "amg setup: other",
+};
+}  // namespace
+
+void PhaseClock::enter(int phase) {
+  stop();
+  cur_ = phase;
+  roctxRangePushA(kPhaseRange[phase]);
+  t0_ = setup_clock();
+}
+
+void PhaseClock::stop() {
+  if (cur_ < 0) return;
+  acc_[cur_] += setup_clock() - t0_;
+  roctxRangePop();
+  cur_ = -1;
+}
+
+HostHierarchy build_hierarchy(Csr A0, const SetupParams& prm, SetupAccel* accel) {
   HostHierarchy H;
+  // Levels are built in place and never move (the capacity is reserved), so
+  // an accelerator may still be filling a level's arrays while the next
+  // level is set up (SetupAccel::finish_host_copies).
+  H.levels.reserve(static_cast<size_t>(std::max(prm.max_levels, 1)) + 1);
+  H.levels.emplace_back();
+  H.levels[0].A = std::move(A0);
   bool from_galerkin = false;
-  double t = setup_clock();
-  auto lap = [&](int phase) {  // charge the time since the last lap to `phase`
-    const double now = setup_clock();
-    H.phase_s[phase] += now - t;
-    t = now;
-  };
-  while (true) {
+  PhaseClock clk(H.phase_s);
+  for (size_t l = 0;; ++l) {
+    HostLevel& L = H.levels[l];
+    const Csr& A = L.A;
     const int64_t n = A.rows;
-    const int lvl_no = static_cast<int>(H.levels.size()) + 1;  // 1-based
+    const int lvl_no = static_cast<int>(l) + 1;  // 1-based
     if (n <= prm.coarse_enough || lvl_no >= prm.max_levels) break;
     const double eps = prm.eps_strong * std::ldexp(1.0, -(lvl_no - 1));
+    clk.enter(kPhUpload);
     if (accel) accel->begin_level(A, from_galerkin);
-    lap(kPhUpload);
+    clk.enter(kPhStrength);
     Graph S;
     if (!accel || !accel->strength(A, eps, S)) S = strength_graph(A, eps);
-    lap(kPhStrength);
+    clk.enter(kPhAggregate);
     int32_t nc = 0;
     std::vector<int32_t> agg = aggregate(S, &nc);
-    lap(kPhAggregate);
-    if (nc == 0 || nc >= n) break;
-    HostLevel L;
+    if (nc == 0 || nc >= n) break;  // this level is the coarsest
     L.eps = eps;
+    clk.enter(kPhProlong);
     if (!accel || !accel->prolongator(A, S, agg, nc, L.P, &L.omega))
       L.P = smoothed_prolongator(A, S, agg, nc, &L.omega);
-    lap(kPhProlong);
-    L.R = transpose(L.P);
-    lap(kPhTranspose);
-    L.m = smoother_diagonal(A, prm);
-    if (prm.relax == 2) L.cheb_hi = gershgorin_dinv(A);
-    lap(kPhSmoother);
-    Csr Ac;
+    clk.enter(kPhTranspose);
+    if (!accel || !accel->transpose(L.P, L.R)) L.R = transpose(L.P);
+    clk.enter(kPhSmoother);
+    if (!accel || !accel->smoother(A, prm, L.m)) L.m = smoother_diagonal(A, prm);
+    if (prm.relax == 2) {
+      if (accel) accel->finish_host_copies();  // the bound reads A's values
+      L.cheb_hi = gershgorin_dinv(A);
+    }
+    clk.enter(kPhGalerkin);
+    L.agg = std::move(agg);
+    H.levels.emplace_back();  // within the reserved capacity: L stays put
+    Csr& Ac = H.levels[l + 1].A;
     from_galerkin = accel && accel->galerkin(L.R, A, L.P, Ac);
     if (!from_galerkin) Ac = spgemm(L.R, spgemm(A, L.P));
-    lap(kPhGalerkin);
-    L.agg = std::move(agg);
-    L.A = std::move(A);
-    H.levels.push_back(std::move(L));
-    A = std::move(Ac);
   }
-  if (A.rows > prm.max_coarse)
-    fail(-8, "coarsest level has " + std::to_string(A.rows) + " rows (limit " +
+  if (accel) accel->finish_host_copies();
+  clk.stop();
+  const Csr& AL = H.levels.back().A;
+  if (AL.rows > prm.max_coarse)
+    fail(-8, "coarsest level has " + std::to_string(AL.rows) + " rows (limit " +
                  std::to_string(prm.max_coarse) + ")");
-  HostLevel C;
-  C.A = std::move(A);
-  H.levels.push_back(std::move(C));
   return H;
 }
 

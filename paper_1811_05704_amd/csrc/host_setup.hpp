@@ -60,6 +60,34 @@ struct HostHierarchy {
 // Seconds of a monotonic clock.
 double setup_clock();
 
+// A named roctx range on the calling thread for the object's lifetime (shown
+// by rocprofv3 --marker-trace; a no-op when no profiler is attached).
+class TraceRange {
+ public:
+  explicit TraceRange(const char* name);
+  ~TraceRange();
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
+// Wall time of the setup by step: enter(p) ends the running step, adds its
+// seconds to acc[step] and starts step p; each step is also a roctx range
+// "amg setup: <step>".  The destructor ends the running step.
+class PhaseClock {
+ public:
+  explicit PhaseClock(double* acc) : acc_(acc) {}
+  ~PhaseClock() { stop(); }
+  PhaseClock(const PhaseClock&) = delete;
+  PhaseClock& operator=(const PhaseClock&) = delete;
+  void enter(int phase);
+  void stop();
+
+ private:
+  double* acc_;
+  int cur_ = -1;
+  double t0_ = 0.0;
+};
+
 // Error raised by the setup; code is an amg_status value.
 struct SetupError {
   int code;
@@ -94,15 +122,25 @@ struct Graph;
 // Optional accelerator for the data-parallel steps of one level (the device).
 // Every step must give exactly what the host step gives, or return false to
 // leave that step to the host.  The steps of a level are called in order:
-// begin_level, strength, prolongator, galerkin; `from_galerkin` tells that A
-// is the product the accelerator returned for the previous level.
+// begin_level, strength, prolongator, transpose, smoother, galerkin;
+// `from_galerkin` tells that A is the product the accelerator returned for the
+// previous level.
+//
+// A step may return with the column indices and values of its output matrix
+// (P, R = P^T, the next level's A) and the smoother diagonal still being
+// copied into the given objects; row pointers and sizes are final.  Those
+// objects must stay where they are and must not be read until
+// finish_host_copies() returns; a step that returns false has finished them.
 class SetupAccel {
  public:
   virtual ~SetupAccel() = default;
+  virtual void finish_host_copies() = 0;
   virtual void begin_level(const Csr& A, bool from_galerkin) = 0;
   virtual bool strength(const Csr& A, double eps, Graph& S) = 0;
   virtual bool prolongator(const Csr& A, const Graph& S, const std::vector<int32_t>& agg, int32_t nc, Csr& P,
                            double* omega) = 0;
+  virtual bool transpose(const Csr& P, Csr& R) = 0;
+  virtual bool smoother(const Csr& A, const SetupParams& prm, std::vector<double>& m) = 0;
   virtual bool galerkin(const Csr& R, const Csr& A, const Csr& P, Csr& Ac) = 0;
 };
 

@@ -36,24 +36,25 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
   if (out) *out = nullptr;
   return guarded([&]() -> amg_status {
     if (!out) throw SetupError{-1, "out must not be NULL"};
+    TraceRange range("amg setup");
     const double t0 = now_s();
+    double pre[kPhCount] = {};  // input and fine upload, before the hierarchy exists
+    PhaseClock clk(pre);
+    clk.enter(kPhInput);
     auto S = std::make_unique<amg_solver>();
     if (p) S->prm = *p;
     else amg_params_default(&S->prm);
     check_params(S->prm);
     validate_csr(n, row_ptr, col, val);
     Csr A = to_csr(n, row_ptr, col, val);
-    const double t_input = now_s() - t0;
     // Data-parallel setup steps on the device (bit-identical to the host's);
     // a step that does not fit the device path stays on the host.  The fine
     // operator goes to the device once: the solver's copy also serves them.
     std::unique_ptr<SetupAccel> accel;
-    double t_up = 0.0;
     if (device) {
-      const double t1 = now_s();
+      clk.enter(kPhUpload);
       S->arena = std::make_unique<DevArena>(alloc, static_cast<hipStream_t>(stream));
       S->A0 = upload_csr<double>(*S->arena, A);
-      t_up = now_s() - t1;
       DeviceCsrRef fine;
       fine.rows = S->A0.rows;
       fine.cols = S->A0.cols;
@@ -61,15 +62,17 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
       fine.ptr = S->A0.ptr;
       fine.col = S->A0.col;
       fine.val = S->A0.val;
-      accel = make_device_setup_accel(alloc, static_cast<hipStream_t>(stream), &fine);
+      accel = make_device_setup_accel(alloc, static_cast<hipStream_t>(stream), &fine, /*keep_levels=*/true);
     }
+    clk.stop();
     S->host = build_hierarchy(std::move(A), setup_params(S->prm), accel.get());
-    S->host.phase_s[kPhInput] += t_input;
-    S->host.phase_s[kPhUpload] += t_up;
-    const double t1 = now_s();
-    accel.reset();
-    S->host.phase_s[kPhOther] += now_s() - t1;
-    if (device) device_setup(*S, alloc, static_cast<hipStream_t>(stream));
+    for (int k = 0; k < kPhCount; ++k) S->host.phase_s[k] += pre[k];
+    if (device) device_setup(*S, alloc, static_cast<hipStream_t>(stream), DeviceSetupOpts{}, accel.get());
+    {
+      PhaseClock other(S->host.phase_s);
+      other.enter(kPhOther);
+      accel.reset();
+    }
     S->setup_s = now_s() - t0;
     *out = S.release();
     g_last_error.clear();
@@ -84,7 +87,11 @@ static amg_status do_setup_block(int64_t nb, int32_t bs, const int64_t* ptr, con
   return guarded([&]() -> amg_status {
     if (!out) throw SetupError{-1, "out must not be NULL"};
     if (bs != kBlock) throw SetupError{-1, "block_size must be 4"};
+    TraceRange range("amg setup");
     const double t0 = now_s();
+    double pre[kPhCount] = {};
+    PhaseClock clk(pre);
+    clk.enter(kPhInput);
     auto S = std::make_unique<amg_solver>();
     if (p) S->prm = *p;
     else amg_params_default(&S->prm);
@@ -96,11 +103,10 @@ static amg_status do_setup_block(int64_t nb, int32_t bs, const int64_t* ptr, con
     A.ptr.assign(ptr, ptr + nb + 1);
     A.col.assign(col, col + ptr[nb]);
     A.val.assign(val, val + ptr[nb] * kBB);
-    const double t_input = now_s() - t0;
+    clk.stop();
     S->block = true;
     S->bhost = build_block_hierarchy(std::move(A), setup_params(S->prm));
-    for (int k = 0; k < kPhCount; ++k) S->host.phase_s[k] = S->bhost.phase_s[k];
-    S->host.phase_s[kPhInput] += t_input;
+    for (int k = 0; k < kPhCount; ++k) S->host.phase_s[k] = S->bhost.phase_s[k] + pre[k];
     if (device) device_setup(*S, alloc, static_cast<hipStream_t>(stream));
     S->setup_s = now_s() - t0;
     *out = S.release();
@@ -135,6 +141,7 @@ amg_status amg_solve(amg_handle h, const double* f_dev, double* u_dev, void* hip
   return guarded([&]() -> amg_status {
     if (!h || !f_dev || !u_dev) throw SetupError{-1, "NULL handle or vector"};
     if (!h->on_device) throw SetupError{-1, "handle was built by amg_setup_host: no device data"};
+    TraceRange range("amg solve");
     return run_solve(*h, f_dev, u_dev, static_cast<hipStream_t>(hip_stream), info);
   });
 }
@@ -147,6 +154,7 @@ amg_status amg_vcycle(amg_handle h, const double* r_dev, double* z_dev, void* hi
     if (!h->on_device) throw SetupError{-1, "handle was built by amg_setup_host: no device data"};
     if (static_cast<const void*>(r_dev) == static_cast<const void*>(z_dev))
       throw SetupError{-1, "r and z must not alias"};
+    TraceRange range("amg V-cycle");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     with_vcycle(*h, [&](auto& V) { return V.template run<0>(r_dev, z_dev, h->partials, nullptr, s); });
     AMG_HIP(hipStreamSynchronize(s));

@@ -254,8 +254,20 @@ def _tridiag(n, lower, diag, upper):
 
 
 COARSE_CASES = ([("spd", n) for n in (255, 383, 511, 895, 900, 1023, 2999)]
+                + [("dense-spd", n) for n in (65, 383, 1000)]
                 + [("nonsymmetric", n) for n in (255, 895, 2999)]
                 + [("indefinite", n) for n in (255, 895, 2999)])
+
+
+def _dense_spd(n):
+    """B B^T / n + I with Gaussian B (seed n), stored as a full CSR matrix:
+    every Gauss-Jordan block update meets nonzero entries."""
+    B = np.random.default_rng(n).standard_normal((n, n))
+    M = B @ B.T / n + np.eye(n)
+    M = 0.5 * (M + M.T)
+    rp = np.arange(0, n * n + 1, n, dtype=np.int64)
+    cols = np.tile(np.arange(n, dtype=np.int32), n)
+    return problems.CSR(n, rp, cols, M.reshape(-1).copy())
 
 
 @pytest.mark.parametrize("kind,n", COARSE_CASES, ids=[f"{k}-{n}" for k, n in COARSE_CASES])
@@ -270,12 +282,14 @@ def test_coarse_inverse_every_order(kind, n):
     the ROCm stack was found wrong at those."""
     if kind == "spd":
         A = problems.tridiag1d(n)
+    elif kind == "dense-spd":
+        A = _dense_spd(n)
     elif kind == "nonsymmetric":
         A = _tridiag(n, -1.2, 2.5, -0.8)
     else:
         A = _tridiag(n, -2.0, 1.0, -2.0)
         assert np.linalg.eigvalsh(A.to_scipy().toarray()).min() < 0
-    S = amg.Solver(A, coarse_enough=n, solver="cg" if kind == "spd" else "bicgstab")
+    S = amg.Solver(A, coarse_enough=n, solver="cg" if kind.endswith("spd") else "bicgstab")
     assert S.nlevels == 1
     f = np.random.default_rng(n).standard_normal(n)
     announce("coarse inverse", kind, "order", n)
@@ -307,9 +321,10 @@ def test_solve_with_coarsest_order_895():
 @pytest.mark.parametrize("name", ["poisson32", "diffusion24", "convection24", "convection40", "poisson27-16",
                                   "aniso20", "decoupled14", "graph60k"])
 def test_device_galerkin_matches_host_setup(name):
-    """The device setup runs the strength graph, the smoothed prolongator and
-    the Galerkin products on the GPU; every level must be bit-identical to
-    the host setup's (same arithmetic, same order)."""
+    """The device setup runs the strength graph, the smoothed prolongator,
+    R = P^T, the smoother diagonal and the Galerkin products on the GPU;
+    every level must be bit-identical to the host setup's (same arithmetic,
+    same order)."""
     if name == "convection40":
         g = problems.gaussian_field(40, 2.0, 8.0, 3)
         A, kw = problems.diffusion3d(40, g, velocity=(50.0, 25.0, 12.5)), {"relax": "jacobi"}
@@ -328,7 +343,13 @@ def test_device_galerkin_matches_host_setup(name):
         Pd, Ph = S.level_scipy(l, "P"), H.level_scipy(l, "P")
         assert np.array_equal(Pd.indptr, Ph.indptr) and np.array_equal(Pd.indices, Ph.indices)
         assert np.array_equal(Pd.data, Ph.data), l
-        assert S.smoother(l)[1] == H.smoother(l)[1]  # prolongator damping omega
+        Rd, Rh = S.level_scipy(l, "R"), H.level_scipy(l, "R")
+        assert np.array_equal(Rd.indptr, Rh.indptr) and np.array_equal(Rd.indices, Rh.indices)
+        assert np.array_equal(Rd.data, Rh.data), l
+        md, omd = S.smoother(l)[:2]
+        mh, omh = H.smoother(l)[:2]
+        assert np.array_equal(md, mh), l  # smoother diagonal
+        assert omd == omh  # prolongator damping omega
     S.release()
     H.release()
 
