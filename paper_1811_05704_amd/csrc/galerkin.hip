@@ -507,10 +507,10 @@ int grid_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<
 
 // Waits for the copy: h may be a local of a step that a later allocation
 // failure unwinds, and a copy still pending would then write freed memory.
-template <class T>
-void download(std::vector<T>& h, const T* d, size_t n, hipStream_t s) {
+template <class V>
+void download(V& h, const typename V::value_type* d, size_t n, hipStream_t s) {
   h.resize(n);
-  if (n) staged_d2h(h.data(), d, sizeof(T) * n, s);
+  if (n) staged_d2h(h.data(), d, sizeof(typename V::value_type) * n, s);
 }
 
 class DeviceSetupAccel final : public SetupAccel {
@@ -532,15 +532,13 @@ class DeviceSetupAccel final : public SetupAccel {
       finish_host_copies();
     } catch (...) {
     }
-    if (copier_.joinable()) {
-      {
-        std::lock_guard<std::mutex> lk(mu_);
-        stop_ = true;
-      }
-      cv_.notify_all();
-      copier_.join();
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
     }
-    if (copy_stream_) (void)hipStreamDestroy(copy_stream_);
+    cv_.notify_all();
+    for (auto& t : copiers_)
+      if (t.joinable()) t.join();
   }
 
   void begin_level(const Csr& A, bool from_galerkin) override {
@@ -778,6 +776,16 @@ class DeviceSetupAccel final : public SetupAccel {
     });
   }
 
+  void host_work_begins() override {
+    if (on_host_work) {
+      std::function<void()> f = std::move(on_host_work);
+      on_host_work = nullptr;
+      f();
+    }
+  }
+
+  std::function<void()> on_host_work;
+
   // Waits for the copies to_host started; rethrows the first error of one.
   void finish_host_copies() override {
     std::unique_lock<std::mutex> lk(mu_);
@@ -824,16 +832,17 @@ class DeviceSetupAccel final : public SetupAccel {
   std::unique_ptr<DevArena> arena() { return std::make_unique<DevArena>(has_alloc_ ? &alloc_ : nullptr, stream_); }
 
   // Host copy of n device elements into h.  With kept levels the copy runs on
-  // a thread and stream of its own, after the work enqueued so far on the
-  // setup stream, and overlaps the following steps (the device memory lives
-  // until the accelerator goes); otherwise it completes before returning.
-  template <class T>
-  void to_host(std::vector<T>& h, const T* d, int64_t n) {
+  // one of a few threads, each with a stream of its own, after the work
+  // enqueued so far on the setup stream, and overlaps the following steps
+  // (the device memory lives until the accelerator goes; the threads also
+  // spread the page faults of the new host arrays); otherwise it completes
+  // before returning.
+  template <class V>
+  void to_host(V& h, const typename V::value_type* d, int64_t n) {
     if (!keep_) {
       download(h, d, static_cast<size_t>(n), stream_);
       return;
     }
-    if (!copy_stream_) AMG_HIP(hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking));
     hipEvent_t ev = nullptr;
     AMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     const hipError_t e = hipEventRecord(ev, stream_);
@@ -841,9 +850,8 @@ class DeviceSetupAccel final : public SetupAccel {
       (void)hipEventDestroy(ev);
       AMG_HIP(e);
     }
-    std::vector<T>* dst = &h;
-    hipStream_t cs = copy_stream_;
-    enqueue([dst, d, n, ev, cs] {
+    V* dst = &h;
+    enqueue([dst, d, n, ev](hipStream_t cs) {
       struct Ev {
         hipEvent_t e;
         ~Ev() { (void)hipEventDestroy(e); }
@@ -853,35 +861,49 @@ class DeviceSetupAccel final : public SetupAccel {
     });
   }
 
-  void enqueue(std::function<void()> job) {
+  static constexpr int kCopyThreads = 3;
+
+  void enqueue(std::function<void(hipStream_t)> job) {
     {
       std::lock_guard<std::mutex> lk(mu_);
       q_.push_back(std::move(job));
-      if (!copier_.joinable()) copier_ = std::thread([this] { copy_loop(); });
+      if (copiers_.empty())
+        for (int t = 0; t < kCopyThreads; ++t) copiers_.emplace_back([this] { copy_loop(); });
     }
     cv_.notify_one();
   }
 
   void copy_loop() {
+    hipStream_t cs = nullptr;
+    std::exception_ptr init_err;
+    try {
+      AMG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    } catch (...) {
+      init_err = std::current_exception();
+    }
     std::unique_lock<std::mutex> lk(mu_);
     for (;;) {
       cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
-      if (q_.empty()) return;  // stopping
-      std::function<void()> job = std::move(q_.front());
+      if (q_.empty()) break;  // stopping
+      std::function<void(hipStream_t)> job = std::move(q_.front());
       q_.pop_front();
       ++busy_;
       lk.unlock();
-      std::exception_ptr e;
-      try {
-        job();
-      } catch (...) {
-        e = std::current_exception();
+      std::exception_ptr e = init_err;
+      if (!e) {
+        try {
+          job(cs);
+        } catch (...) {
+          e = std::current_exception();
+        }
       }
       lk.lock();
       --busy_;
       if (e && !err_) err_ = e;
       if (q_.empty() && busy_ == 0) cv_done_.notify_all();
     }
+    lk.unlock();
+    if (cs) (void)hipStreamDestroy(cs);
   }
 
   // A step left to the host reads the host copies of its inputs.
@@ -920,11 +942,10 @@ class DeviceSetupAccel final : public SetupAccel {
   bool has_fine_ = false;
   int level_ = 0;
   // host copies in flight (kept levels only)
-  hipStream_t copy_stream_ = nullptr;
-  std::thread copier_;
+  std::vector<std::thread> copiers_;
   std::mutex mu_;
   std::condition_variable cv_, cv_done_;
-  std::deque<std::function<void()>> q_;
+  std::deque<std::function<void(hipStream_t)>> q_;
   int busy_ = 0;
   bool stop_ = false;
   std::exception_ptr err_;
@@ -933,8 +954,17 @@ class DeviceSetupAccel final : public SetupAccel {
 }  // namespace
 
 std::unique_ptr<SetupAccel> make_device_setup_accel(const amg_allocator* alloc, hipStream_t stream,
-                                                    const DeviceCsrRef* fine, bool keep_levels) {
-  return std::make_unique<DeviceSetupAccel>(alloc, stream, fine, keep_levels);
+                                                    const DeviceCsrRef* fine, bool keep_levels,
+                                                    std::function<void()> on_host_work) {
+  auto a = std::make_unique<DeviceSetupAccel>(alloc, stream, fine, keep_levels);
+  a->on_host_work = std::move(on_host_work);
+  return a;
+}
+
+void preload_setup_kernels() {
+  hipFuncAttributes a;
+  (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&diag_kernel));
+  (void)hipGetLastError();
 }
 
 bool device_level_refs(const SetupAccel* accel, int level, DeviceLevelRefs* out) {

@@ -9,6 +9,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <memory>
 
 #include "../../include/amg.h"
@@ -37,8 +38,15 @@ struct DeviceCsrRef {
   const int32_t* col = nullptr;
   const double* val = nullptr;  // NULL: not on the device
 };
+// `on_host_work` (optional) runs once, on the calling thread, when the host
+// first starts aggregating (the device has nothing queued then).
 std::unique_ptr<SetupAccel> make_device_setup_accel(const amg_allocator* alloc, hipStream_t stream,
-                                                    const DeviceCsrRef* fine = nullptr, bool keep_levels = false);
+                                                    const DeviceCsrRef* fine = nullptr, bool keep_levels = false,
+                                                    std::function<void()> on_host_work = nullptr);
+
+// Has the runtime load the code object of the setup kernels on the calling
+// thread (it is loaded on first use otherwise).
+void preload_setup_kernels();
 
 // FP64 device copies the accelerator made for level `level` (0-based), equal
 // to the host hierarchy's; a member with val == NULL (m == NULL) was made on

@@ -563,6 +563,7 @@ HostHierarchy build_hierarchy(Csr A0, const SetupParams& prm, SetupAccel* accel)
     Graph S;
     if (!accel || !accel->strength(A, eps, S)) S = strength_graph(A, eps);
     clk.enter(kPhAggregate);
+    if (accel) accel->host_work_begins();
     int32_t nc = 0;
     std::vector<int32_t> agg = aggregate(S, &nc);
     if (nc == 0 || nc >= n) break;  // this level is the coarsest

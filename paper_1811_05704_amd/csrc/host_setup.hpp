@@ -5,16 +5,48 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <new>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 namespace amg {
 
+// Allocator of the large host arrays of a hierarchy (column indices, values,
+// the strong graph): value-initialisation of elements is skipped, so resize()
+// leaves new elements unset.  The memory is then first touched where it is
+// filled, by the parallel loops and multi-threaded copies of the setup,
+// instead of by one thread writing zeros (a page fault per 4 KB page: about
+// 20 ms per 100 MB on one core).  Every resize of such an array is followed
+// by writes to all of its new elements.
+template <class T>
+struct FillLater : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = FillLater<U>;
+  };
+  FillLater() = default;
+  template <class U>
+  FillLater(const FillLater<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+template <class T>
+using hvec = std::vector<T, FillLater<T>>;
+
 struct Csr {
   int64_t rows = 0, cols = 0;
   std::vector<int64_t> ptr;  // rows + 1
-  std::vector<int32_t> col;  // ascending within each row
-  std::vector<double> val;
+  hvec<int32_t> col;         // ascending within each row
+  hvec<double> val;
   int64_t nnz() const { return ptr.empty() ? 0 : ptr.back(); }
 };
 
@@ -142,6 +174,8 @@ class SetupAccel {
   virtual bool transpose(const Csr& P, Csr& R) = 0;
   virtual bool smoother(const Csr& A, const SetupParams& prm, std::vector<double>& m) = 0;
   virtual bool galerkin(const Csr& R, const Csr& A, const Csr& P, Csr& Ac) = 0;
+  // The host is about to aggregate (the device is idle meanwhile).
+  virtual void host_work_begins() {}
 };
 
 // Full hierarchy; throws SetupError.  `accel` (optional) runs the
@@ -151,7 +185,7 @@ HostHierarchy build_hierarchy(Csr A, const SetupParams& prm, SetupAccel* accel =
 // Steps, exposed for tests of the host logic.
 struct Graph {
   std::vector<int64_t> ptr;
-  std::vector<int32_t> idx;
+  hvec<int32_t> idx;
 };
 Graph strength_graph(const Csr& A, double eps);
 std::vector<int32_t> aggregate(const Graph& S, int32_t* count);

@@ -1,5 +1,10 @@
 // C ABI of the solver (include/amg.h): setup, solve, queries, measurement.
 
+#include <condition_variable>
+#include <functional>
+#include <mutex>
+#include <thread>
+
 #include "galerkin.hpp"
 #include "solver.hpp"
 
@@ -45,6 +50,47 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
     if (p) S->prm = *p;
     else amg_params_default(&S->prm);
     check_params(S->prm);
+    // The runtime loads a code object on the first use of one of its kernels
+    // (tens of ms for the solve's several hundred).  The setup kernels' is
+    // loaded on a side thread while the input is checked and copied, the
+    // solve's while the host aggregates the first level (loading it blocks
+    // kernel launches of other threads, so not while the device steps run).
+    std::thread preload;
+    std::mutex pre_mu;
+    std::condition_variable pre_cv;
+    bool pre_go = false;
+    if (device) {
+      int dev = 0;
+      AMG_HIP(hipGetDevice(&dev));
+      preload = std::thread([dev, &pre_mu, &pre_cv, &pre_go] {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        preload_setup_kernels();
+        {
+          std::unique_lock<std::mutex> lk(pre_mu);
+          pre_cv.wait(lk, [&] { return pre_go; });
+        }
+        hipFuncAttributes a;
+        (void)hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&copy_kernel<double, double>));
+        (void)hipGetLastError();
+      });
+    }
+    auto release_preload = [&pre_mu, &pre_cv, &pre_go] {
+      {
+        std::lock_guard<std::mutex> lk(pre_mu);
+        pre_go = true;
+      }
+      pre_cv.notify_all();
+    };
+    struct Join {
+      std::thread& t;
+      std::function<void()> release;
+      ~Join() {
+        if (t.joinable()) {
+          release();
+          t.join();
+        }
+      }
+    } join_preload{preload, release_preload};
     validate_csr(n, row_ptr, col, val);
     Csr A = to_csr(n, row_ptr, col, val);
     // Data-parallel setup steps on the device (bit-identical to the host's);
@@ -62,11 +108,18 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
       fine.ptr = S->A0.ptr;
       fine.col = S->A0.col;
       fine.val = S->A0.val;
-      accel = make_device_setup_accel(alloc, static_cast<hipStream_t>(stream), &fine, /*keep_levels=*/true);
+      accel = make_device_setup_accel(alloc, static_cast<hipStream_t>(stream), &fine, /*keep_levels=*/true,
+                                      release_preload);
     }
     clk.stop();
     S->host = build_hierarchy(std::move(A), setup_params(S->prm), accel.get());
     for (int k = 0; k < kPhCount; ++k) S->host.phase_s[k] += pre[k];
+    if (preload.joinable()) {
+      PhaseClock wait(S->host.phase_s);
+      wait.enter(kPhOther);
+      release_preload();  // a one-level hierarchy never aggregates
+      preload.join();
+    }
     if (device) device_setup(*S, alloc, static_cast<hipStream_t>(stream), DeviceSetupOpts{}, accel.get());
     {
       PhaseClock other(S->host.phase_s);
