@@ -325,7 +325,7 @@ class Solver(_Handle):
     library's device memory comes from PyTorch's caching allocator.
     """
 
-    def __init__(self, A, torch_alloc: bool = True, **params):
+    def __init__(self, A, torch_alloc: bool = True, alloc_limit=None, **params):
         import torch
 
         if not torch.cuda.is_available():
@@ -336,21 +336,31 @@ class Solver(_Handle):
         stream = _torch_stream()
         self._alloc = None
         alloc_p = None
+        # alloc_limit (bytes, with torch_alloc): requests that would take the
+        # library's live device memory past it are refused (the library then
+        # runs that setup step on the host, or reports AMG_ERR_OOM)
+        self.peak_bytes = 0
         if torch_alloc:
             dev = self.device
             self._live = {}
+            live_bytes = [0]
 
             def _a(size, strm, ctx):
+                size = int(size)
+                if alloc_limit is not None and live_bytes[0] + size > alloc_limit:
+                    return None
                 try:
-                    ptr = torch.cuda.caching_allocator_alloc(int(size), dev, stream)
+                    ptr = torch.cuda.caching_allocator_alloc(size, dev, stream)
                 except Exception:
                     return None
-                self._live[ptr] = True
+                self._live[ptr] = size
+                live_bytes[0] += size
+                self.peak_bytes = max(self.peak_bytes, live_bytes[0])
                 return ptr
 
             def _f(ptr, strm, ctx):
                 if ptr in self._live:
-                    del self._live[ptr]
+                    live_bytes[0] -= self._live.pop(ptr)
                     torch.cuda.caching_allocator_delete(ptr)
 
             self._alloc = Allocator(ALLOC_FN(_a), FREE_FN(_f), None)

@@ -42,9 +42,11 @@ struct DevBsr {
 };
 
 template <class T>
-std::vector<T> bsr_values(const Bsr& M) {
-  std::vector<T> v(M.val.size());
-  for (size_t k = 0; k < v.size(); ++k) v[k] = static_cast<T>(M.val[k]);  // FP32: round to nearest
+hvec<T> bsr_values(const Bsr& M) {
+  hvec<T> v(M.val.size());
+  for_row_ranges(static_cast<int64_t>(v.size()), [&](int64_t b, int64_t e) {
+    for (int64_t k = b; k < e; ++k) v[k] = static_cast<T>(M.val[k]);  // FP32: round to nearest
+  });
   return v;
 }
 
@@ -66,7 +68,7 @@ DevBsr<T> upload_bsr(DevArena& ar, const Bsr& M, const DevBsr<double>* like = nu
   if constexpr (std::is_same<T, double>::value) {
     d.val = ar.upload(M.val.data(), std::max<size_t>(M.val.size(), 1));
   } else {
-    const std::vector<T> v = bsr_values<T>(M);
+    const hvec<T> v = bsr_values<T>(M);
     d.val = ar.upload(v.data(), std::max<size_t>(v.size(), 1));
   }
   const double mean = M.rows ? double(M.nnzb()) / double(M.rows) : 0.0;
@@ -180,20 +182,27 @@ inline void upload_block_levels(DevArena& ar, const BlockHierarchy& H, const Dev
     std::vector<T> m(hl.M.begin(), hl.M.end());
     d.M = ar.upload(m.data(), m.size());
     if (l == 0) {
-      // (A M)_ij = A_ij M_j, block products in c order, FP64 then rounded
-      Bsr AM = hl.A;
-      for (int64_t i = 0; i < hl.A.rows; ++i)
-        for (int64_t e = hl.A.ptr[i]; e < hl.A.ptr[i + 1]; ++e) {
-          const double* a = &hl.A.val[e * kB2];
-          const double* mj = &hl.M[static_cast<int64_t>(hl.A.col[e]) * kB2];
-          double* o = &AM.val[e * kB2];
-          for (int r = 0; r < kB; ++r)
-            for (int c = 0; c < kB; ++c) {
-              double t = a[r * kB] * mj[c];
-              for (int k = 1; k < kB; ++k) t = t + a[r * kB + k] * mj[k * kB + c];
-              o[r * kB + c] = t;
-            }
-        }
+      // (A M)_ij = A_ij M_j, block products in c order, FP64 then rounded;
+      // the pattern is B0's, so only the values are formed
+      Bsr AM;
+      AM.rows = hl.A.rows;
+      AM.cols = hl.A.cols;
+      AM.ptr = hl.A.ptr;
+      AM.val.resize(hl.A.val.size());
+      for_row_ranges(hl.A.rows, [&](int64_t b, int64_t end) {
+        for (int64_t i = b; i < end; ++i)
+          for (int64_t e = hl.A.ptr[i]; e < hl.A.ptr[i + 1]; ++e) {
+            const double* a = &hl.A.val[e * kB2];
+            const double* mj = &hl.M[static_cast<int64_t>(hl.A.col[e]) * kB2];
+            double* o = &AM.val[e * kB2];
+            for (int r = 0; r < kB; ++r)
+              for (int c = 0; c < kB; ++c) {
+                double t = a[r * kB] * mj[c];
+                for (int k = 1; k < kB; ++k) t = t + a[r * kB + k] * mj[k * kB + c];
+                o[r * kB + c] = t;
+              }
+          }
+      });
       d.As = upload_bsr<T>(ar, AM, &B0);
     }
     AMG_HIP(hipStreamSynchronize(ar.stream()));

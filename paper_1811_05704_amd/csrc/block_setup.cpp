@@ -28,7 +28,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
+#include <thread>
 
 namespace amg {
 
@@ -79,9 +81,11 @@ bool sym_part_pos_def(const double* B) {
 
 std::vector<double> diagonal_blocks(const Bsr& A) {
   std::vector<double> D(static_cast<size_t>(A.rows) * kBB, 0.0);
-  for (int64_t i = 0; i < A.rows; ++i)
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
-      if (A.col[e] == i) std::copy(&A.val[e * kBB], &A.val[e * kBB] + kBB, &D[i * kBB]);
+  for_row_ranges(A.rows, [&](int64_t b, int64_t end) {
+    for (int64_t i = b; i < end; ++i)
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
+        if (A.col[e] == i) std::copy(&A.val[e * kBB], &A.val[e * kBB] + kBB, &D[i * kBB]);
+  });
   return D;
 }
 
@@ -96,67 +100,83 @@ Bsr filtered_matrix(const Bsr& A, const Graph& S, std::vector<double>& DF, std::
   F.rows = F.cols = n;
   F.ptr.assign(n + 1, 0);
   std::vector<uint8_t> keep(A.nnzb(), 0);
-  for (int64_t i = 0; i < n; ++i) {
-    isolated[i] = S.ptr[i] == S.ptr[i + 1];
-    int64_t s = S.ptr[i];
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
-      const int32_t j = A.col[e];
-      if (j == i) {
-        keep[e] = 1;
-        continue;
+  // rows are independent: kept blocks, lumped weak blocks and the kept count
+  for_row_ranges(n, [&](int64_t b, int64_t end) {
+    for (int64_t i = b; i < end; ++i) {
+      isolated[i] = S.ptr[i] == S.ptr[i + 1];
+      int64_t s = S.ptr[i];
+      int64_t kept = 0;
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+        const int32_t j = A.col[e];
+        if (j == i) {
+          keep[e] = 1;
+          ++kept;
+          continue;
+        }
+        while (s < S.ptr[i + 1] && S.idx[s] < j) ++s;
+        const bool strong = s < S.ptr[i + 1] && S.idx[s] == j;
+        if (strong) {
+          keep[e] = 1;
+          ++kept;
+        } else {
+          for (int k = 0; k < kBB; ++k) lumped[i * kBB + k] = lumped[i * kBB + k] + A.val[e * kBB + k];
+        }
       }
-      while (s < S.ptr[i + 1] && S.idx[s] < j) ++s;
-      const bool strong = s < S.ptr[i + 1] && S.idx[s] == j;
-      if (strong) {
-        keep[e] = 1;
-      } else {
-        for (int k = 0; k < kBB; ++k) lumped[i * kBB + k] = lumped[i * kBB + k] + A.val[e * kBB + k];
-      }
+      F.ptr[i + 1] = kept;
     }
-    F.ptr[i + 1] = F.ptr[i];
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) F.ptr[i + 1] += keep[e];
-  }
+  });
+  for (int64_t i = 0; i < n; ++i) F.ptr[i + 1] += F.ptr[i];
   DF.assign(static_cast<size_t>(n) * kBB, 0.0);
-  for (int64_t i = 0; i < n; ++i) {
-    double* d = &DF[i * kBB];
-    for (int k = 0; k < kBB; ++k) d[k] = D[i * kBB + k] + lumped[i * kBB + k];
-    if (!isolated[i] && !sym_part_pos_def(d)) std::copy(&D[i * kBB], &D[i * kBB] + kBB, d);
-  }
   F.col.resize(F.ptr[n]);
   F.val.resize(static_cast<size_t>(F.ptr[n]) * kBB);
-  for (int64_t i = 0; i < n; ++i) {
-    int64_t p = F.ptr[i];
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
-      if (!keep[e]) continue;
-      F.col[p] = A.col[e];
-      const double* src = (A.col[e] == i) ? &DF[i * kBB] : &A.val[e * kBB];
-      std::copy(src, src + kBB, &F.val[p * kBB]);
-      ++p;
+  for_row_ranges(n, [&](int64_t b, int64_t end) {
+    for (int64_t i = b; i < end; ++i) {
+      double* d = &DF[i * kBB];
+      for (int k = 0; k < kBB; ++k) d[k] = D[i * kBB + k] + lumped[i * kBB + k];
+      if (!isolated[i] && !sym_part_pos_def(d)) std::copy(&D[i * kBB], &D[i * kBB] + kBB, d);
+      int64_t p = F.ptr[i];
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+        if (!keep[e]) continue;
+        F.col[p] = A.col[e];
+        const double* src = (A.col[e] == i) ? d : &A.val[e * kBB];
+        std::copy(src, src + kBB, &F.val[p * kBB]);
+        ++p;
+      }
     }
-  }
+  });
   return F;
 }
 
 double prolongator_damping(const Bsr& AF, const std::vector<double>& Dinv, const std::vector<uint8_t>& isolated) {
+  // the maximum over the rows: exact whatever the order, so taken per range
+  std::mutex mu;
   double rho = -1.0;
   bool any = false;
-  double T[kBB];
-  for (int64_t i = 0; i < AF.rows; ++i) {
-    if (isolated[i]) continue;
-    double absrow[kBlock] = {};
-    for (int64_t e = AF.ptr[i]; e < AF.ptr[i + 1]; ++e) {
-      bprod(&Dinv[i * kBB], &AF.val[e * kBB], T);
+  for_row_ranges(AF.rows, [&](int64_t b, int64_t end) {
+    double local = -1.0;
+    bool local_any = false;
+    double T[kBB];
+    for (int64_t i = b; i < end; ++i) {
+      if (isolated[i]) continue;
+      double absrow[kBlock] = {};
+      for (int64_t e = AF.ptr[i]; e < AF.ptr[i + 1]; ++e) {
+        bprod(&Dinv[i * kBB], &AF.val[e * kBB], T);
+        for (int r = 0; r < kBlock; ++r) {
+          double t = std::fabs(T[r * kBlock]);
+          for (int c = 1; c < kBlock; ++c) t = t + std::fabs(T[r * kBlock + c]);
+          absrow[r] = absrow[r] + t;
+        }
+      }
       for (int r = 0; r < kBlock; ++r) {
-        double t = std::fabs(T[r * kBlock]);
-        for (int c = 1; c < kBlock; ++c) t = t + std::fabs(T[r * kBlock + c]);
-        absrow[r] = absrow[r] + t;
+        local = local_any ? std::max(local, absrow[r]) : absrow[r];
+        local_any = true;
       }
     }
-    for (int r = 0; r < kBlock; ++r) {
-      rho = any ? std::max(rho, absrow[r]) : absrow[r];
-      any = true;
-    }
-  }
+    if (!local_any) return;
+    std::lock_guard<std::mutex> lk(mu);
+    rho = any ? std::max(rho, local) : local;
+    any = true;
+  });
   if (!any) rho = 1.0;
   return (4.0 / 3.0) / rho;
 }
@@ -179,20 +199,22 @@ Bsr tentative(const std::vector<int32_t>& agg, int32_t nc) {
 
 Bsr smoothed_prolongator(const Bsr& AF, const std::vector<double>& Dinv, const Bsr& Phat, double omega) {
   Bsr Y = block_spgemm(AF, Phat);
-  double X[kBB];
-  for (int64_t i = 0; i < Y.rows; ++i) {
-    // the tentative block of row i (at most one) sits inside Y's pattern
-    const int32_t c_hat = (Phat.ptr[i + 1] > Phat.ptr[i]) ? Phat.col[Phat.ptr[i]] : -1;
-    for (int64_t e = Y.ptr[i]; e < Y.ptr[i + 1]; ++e) {
-      bprod(&Dinv[i * kBB], &Y.val[e * kBB], X);
-      const bool on = Y.col[e] == c_hat;
-      for (int r = 0; r < kBlock; ++r)
-        for (int s = 0; s < kBlock; ++s) {
-          const double hat = (on && r == s) ? 1.0 : 0.0;
-          Y.val[e * kBB + r * kBlock + s] = hat - omega * X[r * kBlock + s];
-        }
+  for_row_ranges(Y.rows, [&](int64_t b, int64_t end) {
+    double X[kBB];
+    for (int64_t i = b; i < end; ++i) {
+      // the tentative block of row i (at most one) sits inside Y's pattern
+      const int32_t c_hat = (Phat.ptr[i + 1] > Phat.ptr[i]) ? Phat.col[Phat.ptr[i]] : -1;
+      for (int64_t e = Y.ptr[i]; e < Y.ptr[i + 1]; ++e) {
+        bprod(&Dinv[i * kBB], &Y.val[e * kBB], X);
+        const bool on = Y.col[e] == c_hat;
+        for (int r = 0; r < kBlock; ++r)
+          for (int s = 0; s < kBlock; ++s) {
+            const double hat = (on && r == s) ? 1.0 : 0.0;
+            Y.val[e * kBB + r * kBlock + s] = hat - omega * X[r * kBlock + s];
+          }
+      }
     }
-  }
+  });
   return Y;
 }
 
@@ -200,23 +222,25 @@ std::vector<double> smoother_blocks(const Bsr& A, const SetupParams& prm) {
   const int64_t n = A.rows;
   std::vector<double> M(static_cast<size_t>(n) * kBB);
   const std::vector<double> D = diagonal_blocks(A);
-  double G[kBB], acc[kBB], inv[kBB], Dt[kBB], At[kBB];
-  for (int64_t i = 0; i < n; ++i) {
-    if (prm.relax == 1) {
-      block_inverse(&D[i * kBB], inv);
-      for (int k = 0; k < kBB; ++k) M[i * kBB + k] = prm.jacobi_omega * inv[k];
-      continue;
+  for_row_ranges(n, [&](int64_t b, int64_t end) {
+    double G[kBB], acc[kBB], inv[kBB], Dt[kBB], At[kBB];
+    for (int64_t i = b; i < end; ++i) {
+      if (prm.relax == 1) {
+        block_inverse(&D[i * kBB], inv);
+        for (int k = 0; k < kBB; ++k) M[i * kBB + k] = prm.jacobi_omega * inv[k];
+        continue;
+      }
+      for (int k = 0; k < kBB; ++k) acc[k] = 0.0;
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+        btranspose(&A.val[e * kBB], At);
+        bprod(&A.val[e * kBB], At, G);
+        for (int k = 0; k < kBB; ++k) acc[k] = acc[k] + G[k];
+      }
+      block_inverse(acc, inv);
+      btranspose(&D[i * kBB], Dt);
+      bprod(Dt, inv, &M[i * kBB]);
     }
-    for (int k = 0; k < kBB; ++k) acc[k] = 0.0;
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
-      btranspose(&A.val[e * kBB], At);
-      bprod(&A.val[e * kBB], At, G);
-      for (int k = 0; k < kBB; ++k) acc[k] = acc[k] + G[k];
-    }
-    block_inverse(acc, inv);
-    btranspose(&D[i * kBB], Dt);
-    bprod(Dt, inv, &M[i * kBB]);
-  }
+  });
   for (double v : M)
     if (!std::isfinite(v)) bfail(-3, "singular diagonal block: the block smoother is not defined");
   return M;
@@ -309,37 +333,63 @@ Bsr block_spgemm(const Bsr& X, const Bsr& Y) {
   C.rows = X.rows;
   C.cols = Y.cols;
   C.ptr.assign(X.rows + 1, 0);
-  std::vector<int64_t> slot(Y.cols, -1);
-  std::vector<int32_t> cols;
-  std::vector<double> acc;  // kBB per column in `cols` order of first touch
-  double T[kBB];
-  for (int64_t i = 0; i < X.rows; ++i) {
-    cols.clear();
-    acc.clear();
-    for (int64_t e = X.ptr[i]; e < X.ptr[i + 1]; ++e) {
-      const int32_t k = X.col[e];
-      for (int64_t f = Y.ptr[k]; f < Y.ptr[k + 1]; ++f) {
-        const int32_t j = Y.col[f];
-        if (slot[j] < 0) {
-          slot[j] = static_cast<int64_t>(cols.size());
-          cols.push_back(j);
-          acc.resize(acc.size() + kBB, 0.0);
+  // symbolic: distinct block columns per row (rows are independent)
+  for_row_ranges(X.rows, [&](int64_t b, int64_t end) {
+    std::vector<int64_t> mark(Y.cols, -1);
+    for (int64_t i = b; i < end; ++i) {
+      int64_t k = 0;
+      for (int64_t e = X.ptr[i]; e < X.ptr[i + 1]; ++e) {
+        const int32_t kk = X.col[e];
+        for (int64_t f = Y.ptr[kk]; f < Y.ptr[kk + 1]; ++f) {
+          const int32_t j = Y.col[f];
+          if (mark[j] != i) {
+            mark[j] = i;
+            ++k;
+          }
         }
-        bprod(&X.val[e * kBB], &Y.val[f * kBB], T);
-        double* a = &acc[slot[j] * kBB];
-        for (int q = 0; q < kBB; ++q) a[q] = a[q] + T[q];
       }
+      C.ptr[i + 1] = k;
     }
-    std::vector<int32_t> sorted(cols);
-    std::sort(sorted.begin(), sorted.end());
-    for (int32_t j : sorted) {
-      C.col.push_back(j);
-      const double* a = &acc[slot[j] * kBB];
-      C.val.insert(C.val.end(), a, a + kBB);
+  });
+  for (int64_t i = 0; i < X.rows; ++i) C.ptr[i + 1] += C.ptr[i];
+  C.col.resize(C.ptr[X.rows]);
+  C.val.resize(static_cast<size_t>(C.ptr[X.rows]) * kBB);
+  // numeric: each row summed in its own order (X's row in order, each Y row
+  // in order, from zero), then written in column order
+  for_row_ranges(X.rows, [&](int64_t b, int64_t end) {
+    std::vector<int64_t> slot(Y.cols, -1);
+    std::vector<int32_t> cols;
+    std::vector<double> acc;  // kBB per column in `cols` order of first touch
+    double T[kBB];
+    for (int64_t i = b; i < end; ++i) {
+      cols.clear();
+      acc.clear();
+      for (int64_t e = X.ptr[i]; e < X.ptr[i + 1]; ++e) {
+        const int32_t k = X.col[e];
+        for (int64_t f = Y.ptr[k]; f < Y.ptr[k + 1]; ++f) {
+          const int32_t j = Y.col[f];
+          if (slot[j] < 0) {
+            slot[j] = static_cast<int64_t>(cols.size());
+            cols.push_back(j);
+            acc.resize(acc.size() + kBB, 0.0);
+          }
+          bprod(&X.val[e * kBB], &Y.val[f * kBB], T);
+          double* a = &acc[slot[j] * kBB];
+          for (int q = 0; q < kBB; ++q) a[q] = a[q] + T[q];
+        }
+      }
+      std::vector<int32_t> sorted(cols);
+      std::sort(sorted.begin(), sorted.end());
+      int64_t p = C.ptr[i];
+      for (int32_t j : sorted) {
+        C.col[p] = j;
+        const double* a = &acc[slot[j] * kBB];
+        std::copy(a, a + kBB, &C.val[p * kBB]);
+        ++p;
+      }
+      for (int32_t j : cols) slot[j] = -1;
     }
-    for (int32_t j : cols) slot[j] = -1;
-    C.ptr[i + 1] = C.ptr[i] + static_cast<int64_t>(cols.size());
-  }
+  });
   return C;
 }
 
@@ -348,17 +398,48 @@ Bsr block_transpose(const Bsr& P) {
   R.rows = P.cols;
   R.cols = P.rows;
   R.ptr.assign(R.rows + 1, 0);
-  for (int64_t e = 0; e < P.nnzb(); ++e) R.ptr[P.col[e] + 1]++;
-  for (int64_t i = 0; i < R.rows; ++i) R.ptr[i + 1] += R.ptr[i];
+  const int64_t nr = P.rows, nc = P.cols;
+  // contiguous ranges of P's rows, each with its own column counts, so that
+  // every row of R lists its blocks in ascending column order
+  int nt = (nr < 65536 || nc == 0) ? 1 : setup_threads();
+  nt = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(32) << 20) / std::max<int64_t>(nc, 1))));
+  const int64_t chunk = (nr + nt - 1) / nt;
+  std::vector<int64_t> cnt(static_cast<size_t>(nt) * nc, 0);
+  auto each_range = [&](auto body) {  // body(t, first row, end row), one thread per range
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+      const int64_t b = t * chunk, e = std::min(nr, b + chunk);
+      if (b >= e) break;
+      if (nt == 1) body(t, b, e);
+      else th.emplace_back([=] { body(t, b, e); });
+    }
+    for (auto& x : th) x.join();
+  };
+  each_range([&](int t, int64_t b, int64_t e) {
+    int64_t* c = &cnt[static_cast<size_t>(t) * nc];
+    for (int64_t i = b; i < e; ++i)
+      for (int64_t q = P.ptr[i]; q < P.ptr[i + 1]; ++q) c[P.col[q]]++;
+  });
+  for (int64_t j = 0; j < nc; ++j) {
+    int64_t s = R.ptr[j];
+    for (int t = 0; t < nt; ++t) {
+      const int64_t k = cnt[t * nc + j];
+      cnt[t * nc + j] = s;  // first slot of range t in row j
+      s += k;
+    }
+    R.ptr[j + 1] = s;
+  }
   R.col.resize(P.nnzb());
   R.val.resize(static_cast<size_t>(P.nnzb()) * kBB);
-  std::vector<int64_t> pos(R.ptr.begin(), R.ptr.end() - 1);
-  for (int64_t i = 0; i < P.rows; ++i)
-    for (int64_t e = P.ptr[i]; e < P.ptr[i + 1]; ++e) {
-      const int64_t p = pos[P.col[e]]++;
-      R.col[p] = static_cast<int32_t>(i);
-      btranspose(&P.val[e * kBB], &R.val[p * kBB]);
-    }
+  each_range([&](int t, int64_t b, int64_t e) {
+    int64_t* pos = &cnt[static_cast<size_t>(t) * nc];
+    for (int64_t i = b; i < e; ++i)
+      for (int64_t q = P.ptr[i]; q < P.ptr[i + 1]; ++q) {
+        const int64_t p = pos[P.col[q]]++;
+        R.col[p] = static_cast<int32_t>(i);
+        btranspose(&P.val[q * kBB], &R.val[p * kBB]);
+      }
+  });
   return R;
 }
 

@@ -20,8 +20,8 @@ constexpr int kBB = kBlock * kBlock;
 struct Bsr {
   int64_t rows = 0, cols = 0;
   std::vector<int64_t> ptr;
-  std::vector<int32_t> col;
-  std::vector<double> val;
+  hvec<int32_t> col;  // block columns, ascending within each block row
+  hvec<double> val;   // 16 values per block, row-major
   int64_t nnzb() const { return ptr.empty() ? 0 : ptr.back(); }
 };
 

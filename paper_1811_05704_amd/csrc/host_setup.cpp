@@ -87,6 +87,8 @@ int setup_threads() { return num_threads(); }
 ScopedSetupThreads::ScopedSetupThreads(int n) : saved_(tl_max_threads) { tl_max_threads = n; }
 ScopedSetupThreads::~ScopedSetupThreads() { tl_max_threads = saved_; }
 
+void for_row_ranges(int64_t n, const std::function<void(int64_t, int64_t)>& fn) { parallel_rows(n, fn); }
+
 void copy_parallel(void* dst, const void* src, size_t bytes) {
   constexpr size_t kChunk = size_t(8) << 20;
   const int nt = num_threads();

@@ -5,6 +5,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <memory>
 #include <new>
 #include <string>
@@ -148,6 +149,10 @@ class ScopedSetupThreads {
 
 // memcpy split over the setup's worker threads (large copies only).
 void copy_parallel(void* dst, const void* src, size_t bytes);
+
+// Runs fn(begin, end) over [0, n) in contiguous chunks on the calling
+// thread's setup worker threads (one chunk when n is small); fn must not throw.
+void for_row_ranges(int64_t n, const std::function<void(int64_t, int64_t)>& fn);
 
 struct Graph;
 

@@ -499,9 +499,7 @@ void worker_main(amg_server_s* V, int threads) {
           break;
         } catch (const DevError& e) {
           if (e.code != -5) throw;
-          S.arena.reset();  // give back what was taken, wait for retirements
-          S.h64 = DevHierarchy<double>{};
-          S.h32 = DevHierarchy<float>{};
+          drop_device_state(S);  // give back what was taken, wait for retirements
           std::unique_lock<std::mutex> lk(V->mu);
           if (V->reserved == q->reserved) {
             // Alone in the pool: the memory in the way may have belonged to

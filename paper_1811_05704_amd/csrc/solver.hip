@@ -120,7 +120,22 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
       release_preload();  // a one-level hierarchy never aggregates
       preload.join();
     }
-    if (device) device_setup(*S, alloc, static_cast<hipStream_t>(stream), DeviceSetupOpts{}, accel.get());
+    if (device) {
+      try {
+        device_setup(*S, alloc, static_cast<hipStream_t>(stream), DeviceSetupOpts{}, accel.get());
+      } catch (const DevError& e) {
+        if (e.code != AMG_ERR_OOM || !accel) throw;
+        // Out of device memory with the setup's own level copies still held:
+        // let them go and build the solver's storage from the host hierarchy.
+        accel.reset();
+        drop_device_state(*S);
+        if (S->cap_stream) {
+          (void)hipStreamDestroy(S->cap_stream);
+          S->cap_stream = nullptr;
+        }
+        device_setup(*S, alloc, static_cast<hipStream_t>(stream), DeviceSetupOpts{}, nullptr);
+      }
+    }
     {
       PhaseClock other(S->host.phase_s);
       other.enter(kPhOther);
@@ -153,9 +168,12 @@ static amg_status do_setup_block(int64_t nb, int32_t bs, const int64_t* ptr, con
     validate_bsr(nb, ptr, col, val);
     Bsr A;
     A.rows = A.cols = nb;
-    A.ptr.assign(ptr, ptr + nb + 1);
-    A.col.assign(col, col + ptr[nb]);
-    A.val.assign(val, val + ptr[nb] * kBB);
+    A.ptr.resize(nb + 1);
+    A.col.resize(ptr[nb]);
+    A.val.resize(static_cast<size_t>(ptr[nb]) * kBB);
+    copy_parallel(A.ptr.data(), ptr, sizeof(int64_t) * (nb + 1));
+    copy_parallel(A.col.data(), col, sizeof(int32_t) * ptr[nb]);
+    copy_parallel(A.val.data(), val, sizeof(double) * ptr[nb] * kBB);
     clk.stop();
     S->block = true;
     S->bhost = build_block_hierarchy(std::move(A), setup_params(S->prm));

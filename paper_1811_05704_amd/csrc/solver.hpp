@@ -833,6 +833,27 @@ struct DeviceSetupOpts {
   rocblas_handle blas = nullptr;
 };
 
+// Releases the device storage of a setup that failed part-way (out of
+// memory) so that device_setup can run again from the host hierarchy: every
+// member that points into the arena is cleared with it (device_setup keeps
+// a fine operator it finds already uploaded, so a stale one would be read
+// after its memory went back to the pool).
+inline void drop_device_state(amg_solver& S) {
+  S.arena.reset();
+  S.A0 = DevCsr<double>{};
+  S.B0 = DevBsr<double>{};
+  S.h64 = DevHierarchy<double>{};
+  S.h32 = DevHierarchy<float>{};
+  S.bh64 = DevBlockHierarchy<double>{};
+  S.bh32 = DevBlockHierarchy<float>{};
+  S.Ainv = nullptr;
+  S.partials = nullptr;
+  S.f = S.x = S.r = S.z = S.p = S.q = S.tmp = nullptr;
+  S.rt = S.v = S.phat = S.s = S.shat = S.t = nullptr;
+  S.gmV = S.gmZ = S.gm_partials = nullptr;
+  S.gm = nullptr;
+}
+
 // `accel`: the setup steps' accelerator, whose device copies of the levels
 // (if it kept them) replace uploads from the host hierarchy.
 inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t s,
@@ -868,7 +889,8 @@ inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t 
   }
   if (opts.standalone) {
     S.st = ar.get<KState>(1);
-    AMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.st_host), sizeof(KState), hipHostMallocDefault));
+    if (!S.st_host)
+      AMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.st_host), sizeof(KState), hipHostMallocDefault));
   }
   S.partials = ar.get<double>(2 * max_parts(S));
   const int64_t n = S.n;
@@ -887,7 +909,7 @@ inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t 
     S.gm = ar.get<GState>(1);
     S.gm_nb = static_cast<int>(std::min<int64_t>(vec_blocks(n), kGmDotBlocks));
     S.gm_partials = ar.get<double>(static_cast<size_t>(m + 1) * S.gm_nb);
-    if (opts.standalone)
+    if (opts.standalone && !S.gm_host)
       AMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.gm_host), 2 * sizeof(int32_t), hipHostMallocDefault));
   }
   if (S.prm.solver == AMG_BICGSTAB) {

@@ -386,6 +386,47 @@ def test_device_setup_structurally_nonsymmetric_falls_back():
     H.release()
 
 
+@pytest.mark.parametrize("frac", [0.1, 0.35, 0.6, 0.85])
+def test_setup_under_device_memory_limit(frac):
+    """A device allocator that refuses requests past a byte limit (a fraction
+    of the unlimited setup's peak).  Every setup step that cannot get its
+    device memory runs on the host, after the host copies still in flight
+    have landed, and when the solver's own storage does not fit beside the
+    setup's level copies, those are let go and the storage is built again
+    from the host hierarchy.  The setup then either succeeds with every level
+    equal to the host setup's bit for bit and a converging solve, or reports
+    out of memory, and nothing else happens."""
+    A, kw = _problem("diffusion24")
+    full = amg.Solver(A, **kw)
+    peak = full.peak_bytes
+    full.release()
+    H = amg.HostHierarchy(A, **kw)
+    announce("setup under a device memory limit", frac, "of", peak, "bytes")
+    try:
+        S = amg.Solver(A, alloc_limit=int(frac * peak), **kw)
+    except amg.AmgError as e:
+        assert e.code == -5, e  # AMG_ERR_OOM
+        print(f"[limit] {frac:.2f} of {peak} bytes: out of memory", flush=True)
+        H.release()
+        return
+    print(f"[limit] {frac:.2f} of {peak} bytes: set up, peak {S.peak_bytes}", flush=True)
+    assert S.peak_bytes <= frac * peak
+    assert S.nlevels == H.nlevels
+    for l in range(S.nlevels):
+        for which in (("A", "P", "R") if l + 1 < S.nlevels else ("A",)):
+            Md, Mh = S.level_scipy(l, which), H.level_scipy(l, which)
+            assert np.array_equal(Md.indptr, Mh.indptr) and np.array_equal(Md.indices, Mh.indices)
+            assert np.array_equal(Md.data, Mh.data), (l, which)
+    for l in range(S.nlevels - 1):
+        assert np.array_equal(S.aggregates(l), H.aggregates(l))
+        assert np.array_equal(S.smoother(l)[0], H.smoother(l)[0])
+    f = problems.rhs_ones(A.n)
+    x, info = S.solve(dev(f))
+    assert info["status"] == 0 and true_rel_residual(A, host(x), f) <= 1e-8
+    S.release()
+    H.release()
+
+
 @pytest.mark.parametrize("solver", ["cg", "bicgstab", "gmres"])
 def test_zero_rhs_gives_zero(solver):
     A, _ = _problem("poisson20")
