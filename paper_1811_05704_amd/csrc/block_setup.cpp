@@ -300,31 +300,91 @@ Graph block_strength_graph(const Bsr& A, double eps) {
   const int64_t n = A.rows;
   std::vector<double> sd(n, 0.0);
   std::vector<double> s(A.nnzb());
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
-      s[e] = frob_sq(&A.val[e * kBB]);
-      if (A.col[e] == i) sd[i] = s[e];
-    }
-  const double e4 = (eps * eps) * (eps * eps);
-  std::vector<std::vector<int32_t>> adj(n);
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
-      const int32_t j = A.col[e];
-      if (j == i) continue;
-      if (s[e] * s[e] > e4 * (sd[i] * sd[j])) {
-        adj[i].push_back(j);
-        adj[j].push_back(static_cast<int32_t>(i));
+  for_row_ranges(n, [&](int64_t b, int64_t end) {
+    for (int64_t i = b; i < end; ++i)
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+        s[e] = frob_sq(&A.val[e * kBB]);
+        if (A.col[e] == i) sd[i] = s[e];
       }
+  });
+  const double e4 = (eps * eps) * (eps * eps);
+  std::vector<uint8_t> strong(A.nnzb(), 0);
+  for_row_ranges(n, [&](int64_t b, int64_t end) {
+    for (int64_t i = b; i < end; ++i)
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+        const int32_t j = A.col[e];
+        strong[e] = (j != i && s[e] * s[e] > e4 * (sd[i] * sd[j])) ? 1 : 0;
+      }
+  });
+  // The union with the transposed strong entries: row j of T lists the rows
+  // i < ... with a strong entry (i, j), in ascending order (contiguous row
+  // ranges, one count array each, as in the transpose).
+  int nt = (n < 65536) ? 1 : setup_threads();
+  nt = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(32) << 20) / std::max<int64_t>(n, 1))));
+  const int64_t chunk = (n + nt - 1) / nt;
+  auto each_range = [&](auto body) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+      const int64_t b = t * chunk, e = std::min(n, b + chunk);
+      if (b >= e) break;
+      if (nt == 1) body(t, b, e);
+      else th.emplace_back([=] { body(t, b, e); });
     }
+    for (auto& x : th) x.join();
+  };
+  std::vector<int64_t> cnt(static_cast<size_t>(nt) * n, 0);
+  each_range([&](int t, int64_t b, int64_t e) {
+    int64_t* c = &cnt[static_cast<size_t>(t) * n];
+    for (int64_t i = b; i < e; ++i)
+      for (int64_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q)
+        if (strong[q]) c[A.col[q]]++;
+  });
+  std::vector<int64_t> Tp(n + 1, 0);
+  for (int64_t j = 0; j < n; ++j) {
+    int64_t acc = Tp[j];
+    for (int t = 0; t < nt; ++t) {
+      const int64_t k = cnt[t * n + j];
+      cnt[t * n + j] = acc;
+      acc += k;
+    }
+    Tp[j + 1] = acc;
+  }
+  std::vector<int32_t> Ti(Tp[n]);
+  each_range([&](int t, int64_t b, int64_t e) {
+    int64_t* pos = &cnt[static_cast<size_t>(t) * n];
+    for (int64_t i = b; i < e; ++i)
+      for (int64_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q)
+        if (strong[q]) Ti[pos[A.col[q]]++] = static_cast<int32_t>(i);
+  });
+  // row i of S: the sorted union of its strong columns and of T's row i
+  auto merge_row = [&](int64_t i, int32_t* out) -> int64_t {
+    int64_t a = A.ptr[i], ae = A.ptr[i + 1], t = Tp[i], te = Tp[i + 1], k = 0;
+    while (true) {
+      while (a < ae && !strong[a]) ++a;
+      if (a >= ae && t >= te) break;
+      int32_t c;
+      if (t >= te || (a < ae && A.col[a] <= Ti[t])) {
+        c = A.col[a];
+        if (t < te && Ti[t] == c) ++t;
+        ++a;
+      } else {
+        c = Ti[t++];
+      }
+      if (out) out[k] = c;
+      ++k;
+    }
+    return k;
+  };
   Graph S;
   S.ptr.assign(n + 1, 0);
-  for (int64_t i = 0; i < n; ++i) {
-    std::sort(adj[i].begin(), adj[i].end());
-    adj[i].erase(std::unique(adj[i].begin(), adj[i].end()), adj[i].end());
-    S.ptr[i + 1] = S.ptr[i] + static_cast<int64_t>(adj[i].size());
-  }
-  S.idx.reserve(S.ptr[n]);
-  for (int64_t i = 0; i < n; ++i) S.idx.insert(S.idx.end(), adj[i].begin(), adj[i].end());
+  for_row_ranges(n, [&](int64_t b, int64_t end) {
+    for (int64_t i = b; i < end; ++i) S.ptr[i + 1] = merge_row(i, nullptr);
+  });
+  for (int64_t i = 0; i < n; ++i) S.ptr[i + 1] += S.ptr[i];
+  S.idx.resize(S.ptr[n]);
+  for_row_ranges(n, [&](int64_t b, int64_t end) {
+    for (int64_t i = b; i < end; ++i) merge_row(i, S.idx.data() + S.ptr[i]);
+  });
   return S;
 }
 

@@ -552,6 +552,19 @@ HostHierarchy build_hierarchy(Csr A0, const SetupParams& prm, SetupAccel* accel)
   H.levels[0].A = std::move(A0);
   bool from_galerkin = false;
   PhaseClock clk(H.phase_s);
+  // copies into H may be in flight: they must land before H can go
+  struct Settle {
+    SetupAccel* a;
+    bool armed = true;
+    ~Settle() {
+      if (armed && a) {
+        try {
+          a->finish_host_copies();
+        } catch (...) {
+        }
+      }
+    }
+  } settle{accel};
   for (size_t l = 0;; ++l) {
     HostLevel& L = H.levels[l];
     const Csr& A = L.A;
@@ -589,6 +602,7 @@ HostHierarchy build_hierarchy(Csr A0, const SetupParams& prm, SetupAccel* accel)
     if (!from_galerkin) Ac = spgemm(L.R, spgemm(A, L.P));
   }
   if (accel) accel->finish_host_copies();
+  settle.armed = false;
   clk.stop();
   const Csr& AL = H.levels.back().A;
   if (AL.rows > prm.max_coarse)
