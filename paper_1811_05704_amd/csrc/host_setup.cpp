@@ -212,8 +212,10 @@ std::vector<int32_t> aggregate(const Graph& S, int32_t* count) {
   const int64_t n = static_cast<int64_t>(S.ptr.size()) - 1;
   std::vector<int32_t> agg(n, kUnagg);
   int32_t c = 0;
-  for (int64_t i = 0; i < n; ++i)
-    if (S.ptr[i] == S.ptr[i + 1]) agg[i] = kIsolated;
+  parallel_rows(n, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i)
+      if (S.ptr[i] == S.ptr[i + 1]) agg[i] = kIsolated;
+  });
   // Pass 1: a free node whose strong neighbours are all free becomes a root.
   for (int64_t i = 0; i < n; ++i) {
     if (agg[i] != kUnagg) continue;
@@ -230,17 +232,21 @@ std::vector<int32_t> aggregate(const Graph& S, int32_t* count) {
   }
   // Pass 2: leftovers join the pass-1 aggregate of their lowest-index strong
   // neighbour (neighbour lists are ascending; pass-1 membership is frozen).
-  std::vector<int32_t> frozen(agg);
-  for (int64_t i = 0; i < n; ++i) {
-    if (agg[i] != kUnagg) continue;
-    for (int64_t e = S.ptr[i]; e < S.ptr[i + 1]; ++e) {
-      int32_t a = frozen[S.idx[e]];
-      if (a >= 0) {
-        agg[i] = a;
-        break;
+  // (each node reads only the frozen copy: the nodes are independent)
+  std::vector<int32_t> frozen(n);
+  copy_parallel(frozen.data(), agg.data(), sizeof(int32_t) * n);
+  parallel_rows(n, [&](int64_t b, int64_t end) {
+    for (int64_t i = b; i < end; ++i) {
+      if (agg[i] != kUnagg) continue;
+      for (int64_t e = S.ptr[i]; e < S.ptr[i + 1]; ++e) {
+        int32_t a = frozen[S.idx[e]];
+        if (a >= 0) {
+          agg[i] = a;
+          break;
+        }
       }
     }
-  }
+  });
   // Pass 3: whatever is left starts a new aggregate with its free neighbours.
   for (int64_t i = 0; i < n; ++i) {
     if (agg[i] != kUnagg) continue;
