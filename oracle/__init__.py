@@ -31,3 +31,4 @@ from .sa_amg import (  # noqa: F401
     gmres,
     solve,
 )
+from . import schur  # noqa: F401,E402

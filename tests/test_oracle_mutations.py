@@ -14,8 +14,10 @@ import scipy.sparse as sp
 
 import oracle
 import oracle.sa_amg as sa
+import oracle.schur as schur
 import problems
 from tests import test_oracle as pins
+from tests import test_schur_oracle as schur_pins
 
 
 def _pins_fail(golden):
@@ -145,12 +147,12 @@ def _arnoldi_skips_last_vector(A, precond, V, j):
     return z, h, float(np.sqrt(w @ w)), w
 
 
-def _one_edit(fn, old, new):
+def _one_edit(fn, old, new, module=sa):
     """``fn`` recompiled from its source with the single occurrence of ``old``
     replaced by ``new`` (names resolve in the oracle module's namespace)."""
     src = textwrap.dedent(inspect.getsource(fn))
     assert src.count(old) == 1, (fn.__name__, old)
-    ns = dict(sa.__dict__)
+    ns = dict(module.__dict__)
     exec(compile(src.replace(old, new), "<mutant of %s>" % fn.__name__, "exec"), ns)
     return ns[fn.__name__]
 
@@ -196,3 +198,49 @@ def test_pins_pass_unmutated(golden_dir):
     import os
 
     assert not _pins_fail(os.path.join(golden_dir, "pw_1d_laplacian.txt"))
+
+
+# ---------------------------------------------------------------- field split
+
+def _schur_pins_fail():
+    checks = [
+        schur_pins.test_exact_inner_solves_invert_the_system,
+        schur_pins.test_schur_matrix_elementwise_definition,
+        schur_pins.test_schur_matrix_stencil_on_the_stokes_grid,
+        schur_pins.test_diagonal_velocity_solve_with_exact_schur_inverts_the_lumped_system,
+    ]
+    for chk in checks:
+        try:
+            chk()
+        except (AssertionError, ValueError, np.linalg.LinAlgError):
+            return True
+    return False
+
+
+SCHUR_MUTATIONS = {
+    "pressure_rhs_sign": ("field_split_apply", _one_edit(
+        schur.field_split_apply, "r_p - b.D @ u_star", "r_p + b.D @ u_star", schur)),
+    "divergence_as_minus_gradient_transpose": ("field_split_apply", _one_edit(
+        schur.field_split_apply, "r_p - b.D @ u_star", "r_p + b.G.T @ u_star", schur)),
+    "no_velocity_correction": ("field_split_apply", _one_edit(
+        schur.field_split_apply, "u = u_star - vel_solve(b.G @ p)", "u = u_star", schur)),
+    "schur_plus_sign": ("schur_matrix", _one_edit(
+        schur.schur_matrix, "b.S - b.D @ dinv @ b.G", "b.S + b.D @ dinv @ b.G", schur)),
+    "schur_with_full_inverse": ("schur_matrix", _one_edit(
+        schur.schur_matrix, "dinv = sp.diags(1.0 / b.K.diagonal())",
+        "dinv = sp.csr_matrix(np.linalg.inv(b.K.toarray()))", schur)),
+    "schur_with_row_sums": ("schur_matrix", _one_edit(
+        schur.schur_matrix, "dinv = sp.diags(1.0 / b.K.diagonal())",
+        "dinv = sp.diags(1.0 / np.asarray(abs(b.K).sum(axis=1)).ravel())", schur)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SCHUR_MUTATIONS))
+def test_planted_field_split_mistake_is_caught(name, monkeypatch):
+    attr, fn = SCHUR_MUTATIONS[name]
+    monkeypatch.setattr(schur, attr, fn)
+    assert _schur_pins_fail(), name
+
+
+def test_field_split_pins_pass_unmutated():
+    assert not _schur_pins_fail()

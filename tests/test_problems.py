@@ -187,3 +187,23 @@ def test_random_laplacian_structure():
     B = problems.random_laplacian(3000, hub_degree=1200, seed=5)
     assert np.array_equal(A.val, B.val) and np.array_equal(A.col, B.col)
 
+
+
+@pytest.mark.parametrize("N", [2, 4, 7])
+def test_stokes_structure(N):
+    from problems.stokes import stokes3d, stokes_rhs
+
+    A, n_u = stokes3d(N)
+    n = N**3
+    assert A.n == 4 * n and n_u == 3 * n
+    # K: three 7-point blocks; G and D: 2 N^2 (N-1) entries per axis; S: 7-point
+    assert A.nnz == 40 * N**3 - 36 * N**2
+    M = A.to_scipy()
+    K, G, D, S = M[:n_u, :n_u], M[:n_u, n_u:], M[n_u:, :n_u], M[n_u:, n_u:]
+    assert abs(K - K.T).max() == 0 and abs(D + G.T).max() == 0
+    assert np.all(M.diagonal() > 0)
+    h = 1.0 / (N + 1)
+    assert set(np.unique(np.abs(G.data))) == {0.5 * h}
+    assert np.allclose(S.diagonal(), 6 * h * h / 12)
+    f = stokes_rhs(N)
+    assert f.shape == (4 * n,) and f[:n_u].min() == 1.0 and not f[n_u:].any()
