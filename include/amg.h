@@ -191,6 +191,38 @@ amg_status amg_get_level_bsr(amg_handle h, int32_t level, int32_t which, int64_t
 amg_status amg_get_smoother_blocks(amg_handle h, int32_t level, double* blocks, double* omega);
 
 /*
+ * Schur-complement pressure-correction field split (section 3,
+ * "Extensibility": a two-step field-split preconditioner whose pressure
+ * block is preconditioned with AMG; section 4: the Navier-Stokes runs use it
+ * with smoothed aggregation on the pressure and SPAI-0 on the velocity).
+ * A is the whole n x n system [[K, G], [D, S]] in the CSR layout of
+ * amg_setup, velocity unknowns first: rows and columns 0 .. n_u-1 are the
+ * velocity, n_u .. n-1 the pressure.  Diagonal entries may be missing or of
+ * any sign outside K; K needs a nonzero diagonal in every row (else
+ * AMG_ERR_ZERO_DIAG).  The setup forms M_u = SPAI-0 of K (k_ii / sum_j k_ij^2
+ * over K's columns) and S_hat = S - D diag(K)^-1 G, and builds the
+ * smoothed-aggregation hierarchy of S_hat as amg_setup builds that of A
+ * (a row of S_hat without a positive diagonal is AMG_ERR_ZERO_DIAG).  The
+ * preconditioner maps r = (r_u, r_p) to z = (z_u, z_p):
+ *   z_p = V(r_p - D (M_u r_u)),  z_u = M_u (r_u - G z_p),
+ * V one V-cycle of that hierarchy (FP32 in AMG_MIXED, the rest FP64).
+ * amg_solve then solves the whole system (vectors of n doubles) with
+ * p->solver AMG_BICGSTAB or AMG_GMRES (the split is not symmetric: AMG_CG is
+ * AMG_ERR_INVALID_ARG, as is n_u outside 0 < n_u < n); amg_vcycle applies
+ * the preconditioner once to a vector of n doubles.  amg_level_info,
+ * amg_get_level_csr and the kernel queries describe the hierarchy of S_hat
+ * (level 0 is S_hat, n - n_u rows).  Memory and errors otherwise as for
+ * amg_setup.
+ */
+amg_status amg_setup_schur(int64_t n, const int64_t* row_ptr, const int32_t* col,
+                           const double* val, int64_t n_u, const amg_params* p,
+                           const amg_allocator* alloc, void* hip_stream, amg_handle* out);
+/* The field split's setup on the host only (queries only, like amg_setup_host). */
+amg_status amg_setup_schur_host(int64_t n, const int64_t* row_ptr, const int32_t* col,
+                                const double* val, int64_t n_u, const amg_params* p,
+                                amg_handle* out);
+
+/*
  * Solve A u = f.  f_dev, u_dev: device double[n]; u holds the initial guess
  * on entry and the solution on exit.  info may be NULL.  Returns AMG_OK,
  * AMG_NOT_CONVERGED (u is the last iterate), or a negative error.  A zero f

@@ -62,9 +62,14 @@ def split(A, n_u: int) -> Blocks:
 
 
 def schur_matrix(b: Blocks) -> sp.csr_matrix:
-    """S_hat = S - D diag(K)^-1 G, the sparse approximate Schur complement."""
+    """S_hat = S - D diag(K)^-1 G, the sparse approximate Schur complement.
+
+    Each entry's products are summed in ascending velocity index k (the
+    columns of D diag(K)^-1 are put in order before the product)."""
     dinv = sp.diags(1.0 / b.K.diagonal())
-    Sh = (b.S - b.D @ dinv @ b.G).tocsr()
+    Dk = (b.D @ dinv).tocsr()
+    Dk.sort_indices()
+    Sh = (b.S - Dk @ b.G).tocsr()
     Sh.sum_duplicates()
     Sh.sort_indices()
     return Sh

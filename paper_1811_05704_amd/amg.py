@@ -87,6 +87,9 @@ def lib():
         "amg_setup_block": (i32, [i64, i32, P64, P32, PD, C.POINTER(Params), C.POINTER(Allocator), vp,
                                   C.POINTER(vp)]),
         "amg_setup_block_host": (i32, [i64, i32, P64, P32, PD, C.POINTER(Params), C.POINTER(vp)]),
+        "amg_setup_schur": (i32, [i64, P64, P32, PD, i64, C.POINTER(Params), C.POINTER(Allocator), vp,
+                                  C.POINTER(vp)]),
+        "amg_setup_schur_host": (i32, [i64, P64, P32, PD, i64, C.POINTER(Params), C.POINTER(vp)]),
         "amg_get_level_bsr": (i32, [vp, i32, i32, P64, P32, PD]),
         "amg_get_smoother_blocks": (i32, [vp, i32, PD, PD]),
         "amg_solve": (i32, [vp, vp, vp, vp, C.POINTER(Info)]),
@@ -127,6 +130,7 @@ def lib():
 def exported_symbols():
     return [
         "amg_params_default", "amg_setup", "amg_setup_host", "amg_setup_block", "amg_setup_block_host",
+        "amg_setup_schur", "amg_setup_schur_host",
         "amg_get_level_bsr", "amg_get_smoother_blocks", "amg_solve", "amg_release",
         "amg_last_error", "amg_vcycle", "amg_num_levels", "amg_level_info", "amg_get_aggregates",
         "amg_get_level_csr", "amg_get_smoother", "amg_level_kernel_info", "amg_csr_upload", "amg_csr_spmv",
@@ -295,12 +299,17 @@ class _Handle:
 
 class HostHierarchy(_Handle):
     """Hierarchy built on the host only (``amg_setup_host``, or
-    ``amg_setup_block_host`` for a block matrix); no device needed."""
+    ``amg_setup_block_host`` for a block matrix, or ``amg_setup_schur_host``
+    for a field split with ``n_u`` velocity unknowns); no device needed."""
 
-    def __init__(self, A, **params):
+    def __init__(self, A, n_u=None, **params):
         self.params = make_params(**params)
         h = C.c_void_p()
-        if _is_block(A):
+        if n_u is not None:
+            rp, c, v = _csr_arrays(A)
+            _check(lib().amg_setup_schur_host(int(A.n), _ptr(rp, C.c_int64), _ptr(c, C.c_int32),
+                                              _ptr(v, C.c_double), int(n_u), C.byref(self.params), C.byref(h)))
+        elif _is_block(A):
             rp, c, v = _bsr_arrays(A)
             _check(lib().amg_setup_block_host(int(A.nb), int(A.b), _ptr(rp, C.c_int64), _ptr(c, C.c_int32),
                                               _ptr(v, C.c_double), C.byref(self.params), C.byref(h)))
@@ -322,10 +331,12 @@ class Solver(_Handle):
 
     ``A`` has ``n``, ``row_ptr``, ``col``, ``val`` (host arrays); keyword
     arguments are :class:`Params` fields.  With ``torch_alloc`` (default) the
-    library's device memory comes from PyTorch's caching allocator.
+    library's device memory comes from PyTorch's caching allocator.  With
+    ``n_u`` the Schur-complement field split (``amg_setup_schur``): A is the
+    whole velocity/pressure system, velocity unknowns first.
     """
 
-    def __init__(self, A, torch_alloc: bool = True, alloc_limit=None, **params):
+    def __init__(self, A, torch_alloc: bool = True, alloc_limit=None, n_u=None, **params):
         import torch
 
         if not torch.cuda.is_available():
@@ -366,7 +377,12 @@ class Solver(_Handle):
             self._alloc = Allocator(ALLOC_FN(_a), FREE_FN(_f), None)
             alloc_p = C.byref(self._alloc)
         h = C.c_void_p()
-        if _is_block(A):
+        if n_u is not None:
+            rp, c, v = _csr_arrays(A)
+            _check(lib().amg_setup_schur(self.n, _ptr(rp, C.c_int64), _ptr(c, C.c_int32), _ptr(v, C.c_double),
+                                         int(n_u), C.byref(self.params), alloc_p, C.c_void_p(stream.cuda_stream),
+                                         C.byref(h)))
+        elif _is_block(A):
             rp, c, v = _bsr_arrays(A)
             _check(lib().amg_setup_block(int(A.nb), int(A.b), _ptr(rp, C.c_int64), _ptr(c, C.c_int32),
                                          _ptr(v, C.c_double), C.byref(self.params), alloc_p,

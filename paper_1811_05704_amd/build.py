@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libamg.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HOST_SOURCES = ["host_setup.cpp", "block_setup.cpp"]
+HOST_SOURCES = ["host_setup.cpp", "block_setup.cpp", "field_split.cpp"]
 HIP_SOURCES = ["solver.hip", "serve.hip", "galerkin.hip", "noalloc.hip", "staging.hip"]
 
 # Host arithmetic of the setup follows each definition's natural order with

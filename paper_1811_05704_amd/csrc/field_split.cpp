@@ -1,0 +1,168 @@
+// Host part of the Schur-complement field split: block extraction, SPAI-0 of
+// the velocity block and the approximate Schur complement (field_split.hpp).
+#include "field_split.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <string>
+#include <vector>
+
+namespace amg {
+
+namespace {
+
+// First entry of row i whose column is >= c (columns ascending).
+int64_t first_at_or_after(const Csr& A, int64_t i, int64_t c) {
+  const int32_t* b = A.col.data() + A.ptr[i];
+  const int32_t* e = A.col.data() + A.ptr[i + 1];
+  return A.ptr[i] + (std::lower_bound(b, e, static_cast<int32_t>(c)) - b);
+}
+
+// Rows [r0, r1) of A restricted to columns [c0, c1), columns shifted by -c0
+// and values scaled by scale[col] when scale is given.
+Csr extract(const Csr& A, int64_t r0, int64_t r1, int64_t c0, int64_t c1, const double* scale) {
+  Csr B;
+  B.rows = r1 - r0;
+  B.cols = c1 - c0;
+  B.ptr.assign(B.rows + 1, 0);
+  for_row_ranges(B.rows, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i)
+      B.ptr[i + 1] = first_at_or_after(A, r0 + i, c1) - first_at_or_after(A, r0 + i, c0);
+  });
+  for (int64_t i = 0; i < B.rows; ++i) B.ptr[i + 1] += B.ptr[i];
+  B.col.resize(B.nnz());
+  B.val.resize(B.nnz());
+  for_row_ranges(B.rows, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) {
+      int64_t o = B.ptr[i];
+      for (int64_t k = first_at_or_after(A, r0 + i, c0); k < first_at_or_after(A, r0 + i, c1); ++k, ++o) {
+        const int32_t j = A.col[k];
+        B.col[o] = static_cast<int32_t>(j - c0);
+        B.val[o] = scale ? A.val[k] * scale[j] : A.val[k];
+      }
+    }
+  });
+  return B;
+}
+
+}  // namespace
+
+Csr split_fields(Csr A, int64_t n_u, FieldSplit* out) {
+  const int64_t n = A.rows;
+  if (n_u <= 0 || n_u >= n) throw SetupError{-1, "velocity unknowns n_u must satisfy 0 < n_u < n"};
+  const int64_t np = n - n_u;
+
+  // velocity diagonal, its reciprocal, and SPAI-0 over K's columns
+  hvec<double> kinv(n_u);
+  out->mu.resize(n_u);
+  std::atomic<int64_t> bad{-1};
+  for_row_ranges(n_u, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) {
+      double d = 0.0, ss = 0.0;
+      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1] && A.col[k] < n_u; ++k) {
+        const double v = A.val[k];
+        ss += v * v;
+        if (A.col[k] == i) d = v;
+      }
+      if (d == 0.0) {
+        int64_t cur = bad.load();
+        while ((cur < 0 || i < cur) && !bad.compare_exchange_weak(cur, i)) {
+        }
+        kinv[i] = 0.0;
+        out->mu[i] = 0.0;
+        continue;
+      }
+      kinv[i] = 1.0 / d;
+      out->mu[i] = d / ss;
+    }
+  });
+  if (bad.load() >= 0)
+    throw SetupError{-3, "velocity row " + std::to_string(bad.load()) + " has a zero or missing diagonal"};
+
+  out->n_u = n_u;
+  out->G = extract(A, 0, n_u, n_u, n, nullptr);
+  out->Dm = extract(A, n_u, n, 0, n_u, out->mu.data());
+  const Csr Dk = extract(A, n_u, n, 0, n_u, kinv.data());  // D diag(K)^-1
+  const Csr& G = out->G;
+
+  // S_hat row i = S row i - (D diag(K)^-1 G) row i; counted, then written.
+  Csr Sh;
+  Sh.rows = Sh.cols = np;
+  Sh.ptr.assign(np + 1, 0);
+  auto row = [&](int64_t i, std::vector<double>& acc, std::vector<double>& sv, std::vector<int64_t>& mark,
+                 std::vector<int32_t>& cols, bool write) {
+    cols.clear();
+    for (int64_t k = Dk.ptr[i]; k < Dk.ptr[i + 1]; ++k) {
+      const int32_t v = Dk.col[k];
+      const double w = Dk.val[k];
+      for (int64_t q = G.ptr[v]; q < G.ptr[v + 1]; ++q) {
+        const int32_t j = G.col[q];
+        if (mark[j] != i) {
+          mark[j] = i;
+          acc[j] = 0.0;
+          sv[j] = 0.0;
+          cols.push_back(j);
+        }
+        acc[j] += w * G.val[q];
+      }
+    }
+    for (int64_t k = first_at_or_after(A, n_u + i, n_u); k < A.ptr[n_u + i + 1]; ++k) {
+      const int32_t j = static_cast<int32_t>(A.col[k] - n_u);
+      if (mark[j] != i) {
+        mark[j] = i;
+        acc[j] = 0.0;
+        cols.push_back(j);
+      }
+      sv[j] = A.val[k];
+    }
+    std::sort(cols.begin(), cols.end());
+    int64_t o = write ? Sh.ptr[i] : 0;
+    for (int32_t j : cols) {
+      const double s = sv[j] - acc[j];
+      if (s == 0.0) continue;
+      if (write) {
+        Sh.col[o] = j;
+        Sh.val[o] = s;
+      }
+      ++o;
+    }
+    return o;
+  };
+  for (int pass = 0; pass < 2; ++pass) {
+    for_row_ranges(np, [&](int64_t b, int64_t e) {
+      std::vector<double> acc(np), sv(np);
+      std::vector<int64_t> mark(np, -1);
+      std::vector<int32_t> cols;
+      for (int64_t i = b; i < e; ++i) {
+        const int64_t c = row(i, acc, sv, mark, cols, pass == 1);
+        if (pass == 0) Sh.ptr[i + 1] = c;
+      }
+    });
+    if (pass == 0) {
+      for (int64_t i = 0; i < np; ++i) Sh.ptr[i + 1] += Sh.ptr[i];
+      Sh.col.resize(Sh.nnz());
+      Sh.val.resize(Sh.nnz());
+    }
+  }
+  // the hierarchy is built for S_hat: every row needs a positive diagonal
+  std::atomic<int64_t> bad_p{-1};
+  for_row_ranges(np, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) {
+      bool ok = false;
+      for (int64_t k = Sh.ptr[i]; k < Sh.ptr[i + 1]; ++k)
+        if (Sh.col[k] == i) ok = Sh.val[k] > 0.0;
+      if (!ok) {
+        int64_t cur = bad_p.load();
+        while ((cur < 0 || i < cur) && !bad_p.compare_exchange_weak(cur, i)) {
+        }
+      }
+    }
+  });
+  if (bad_p.load() >= 0)
+    throw SetupError{-3, "pressure Schur complement row " + std::to_string(bad_p.load()) +
+                             " has a missing or non-positive diagonal"};
+  out->A = std::move(A);
+  return Sh;
+}
+
+}  // namespace amg

@@ -106,7 +106,7 @@ void copy_parallel(void* dst, const void* src, size_t bytes) {
   for (auto& x : th) x.join();
 }
 
-void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val) {
+void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, bool require_diag) {
   if (n <= 0 || !ptr || !col || !val) fail(-1, "null array or non-positive size");
   // int32 indices everywhere on the device; grid-stride loops step past the
   // last index by up to 2^25 before they stop, so that much headroom is kept
@@ -132,10 +132,10 @@ void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const doubl
         if (!std::isfinite(val[k])) return {i, -9, "non-finite matrix value in row "};
         if (c == i) {
           has_diag = true;
-          if (!(val[k] > 0.0)) return {i, -3, "non-positive diagonal in row "};
+          if (require_diag && !(val[k] > 0.0)) return {i, -3, "non-positive diagonal in row "};
         }
       }
-      if (!has_diag) return {i, -3, "missing diagonal in row "};
+      if (require_diag && !has_diag) return {i, -3, "missing diagonal in row "};
     }
     return {};
   };

@@ -127,8 +127,10 @@ struct SetupError {
   std::string msg;
 };
 
-// Validate a CSR input as the C ABI requires; throws SetupError.
-void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val);
+// Validate a CSR input as the C ABI requires; throws SetupError.  With
+// require_diag false a row's diagonal may be missing or of any sign (the
+// whole system of a field split, whose pressure block may be zero).
+void validate_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, bool require_diag = true);
 
 // Limit the worker threads the setup of the calling thread uses (0 = default).
 void set_setup_threads(int n);

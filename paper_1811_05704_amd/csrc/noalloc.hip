@@ -151,6 +151,7 @@ extern "C" amg_status amg_vcycle_noalloc(amg_handle h, const double* r_dev, doub
     if (!h || !r_dev || !z_dev) throw SetupError{-1, "NULL handle or vector"};
     if (!h->on_device) throw SetupError{-1, "handle was built by amg_setup_host: no device data"};
     if (h->block) throw SetupError{-1, "block-value handles are not supported here"};
+    if (h->schur) throw SetupError{-1, "field-split handles are not supported here"};
     if (static_cast<const void*>(r_dev) == static_cast<const void*>(z_dev))
       throw SetupError{-1, "r and z must not alias"};
     int cur = 0;

@@ -35,9 +35,11 @@ void amg_params_default(amg_params* p) {
 
 const char* amg_last_error(void) { return g_last_error.c_str(); }
 
+// n_u > 0: a Schur-complement field split with n_u velocity unknowns; the
+// hierarchy is built for the approximate pressure Schur complement.
 static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
                            const amg_params* p, bool device, const amg_allocator* alloc, void* stream,
-                           amg_handle* out) {
+                           amg_handle* out, int64_t n_u = 0) {
   if (out) *out = nullptr;
   return guarded([&]() -> amg_status {
     if (!out) throw SetupError{-1, "out must not be NULL"};
@@ -50,6 +52,8 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
     if (p) S->prm = *p;
     else amg_params_default(&S->prm);
     check_params(S->prm);
+    if (n_u && S->prm.solver != AMG_BICGSTAB && S->prm.solver != AMG_GMRES)
+      throw SetupError{-1, "the field split is not symmetric: solver must be AMG_BICGSTAB or AMG_GMRES"};
     // The runtime loads a code object on the first use of one of its kernels
     // (tens of ms for the solve's several hundred).  The setup kernels' is
     // loaded on a side thread while the input is checked and copied, the
@@ -91,8 +95,12 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
         }
       }
     } join_preload{preload, release_preload};
-    validate_csr(n, row_ptr, col, val);
+    validate_csr(n, row_ptr, col, val, /*require_diag=*/n_u == 0);
     Csr A = to_csr(n, row_ptr, col, val);
+    if (n_u) {
+      A = split_fields(std::move(A), n_u, &S->split);
+      S->schur = true;
+    }
     // Data-parallel setup steps on the device (bit-identical to the host's);
     // a step that does not fit the device path stays on the host.  The fine
     // operator goes to the device once: the solver's copy also serves them.
@@ -206,6 +214,24 @@ amg_status amg_setup(int64_t n, const int64_t* row_ptr, const int32_t* col, cons
 amg_status amg_setup_host(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
                           const amg_params* p, amg_handle* out) {
   return do_setup(n, row_ptr, col, val, p, false, nullptr, nullptr, out);
+}
+
+amg_status amg_setup_schur(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n_u,
+                           const amg_params* p, const amg_allocator* alloc, void* hip_stream, amg_handle* out) {
+  if (n_u <= 0 || n_u >= n) {
+    if (out) *out = nullptr;
+    return set_error(AMG_ERR_INVALID_ARG, "velocity unknowns n_u must satisfy 0 < n_u < n");
+  }
+  return do_setup(n, row_ptr, col, val, p, true, alloc, hip_stream, out, n_u);
+}
+
+amg_status amg_setup_schur_host(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+                                int64_t n_u, const amg_params* p, amg_handle* out) {
+  if (n_u <= 0 || n_u >= n) {
+    if (out) *out = nullptr;
+    return set_error(AMG_ERR_INVALID_ARG, "velocity unknowns n_u must satisfy 0 < n_u < n");
+  }
+  return do_setup(n, row_ptr, col, val, p, false, nullptr, nullptr, out, n_u);
 }
 
 amg_status amg_solve(amg_handle h, const double* f_dev, double* u_dev, void* hip_stream, amg_info* info) {

@@ -32,8 +32,10 @@
 #include "device.hpp"
 #include "block_device.hpp"
 #include "coarse.hpp"
+#include "field_split.hpp"
 #include "galerkin.hpp"
 #include "gmres.hpp"
+#include "schur.hpp"
 #include "tail.hpp"
 #include "vcycle.hpp"
 
@@ -78,6 +80,15 @@ struct amg_solver {
   double* Ainv = nullptr;
   int32_t nL = 0;
   int64_t n = 0;
+
+  // Schur-complement field split: the hierarchy above (host, A0, h64/h32)
+  // is that of the approximate pressure Schur complement; the Krylov loop
+  // runs on the whole system Afull (n unknowns, velocity first).
+  bool schur = false;
+  amg::FieldSplit split;  // host copies: whole system, D diag(M_u), G, M_u
+  amg::DevCsr<double> Afull, Dm, Gs;
+  double* mu = nullptr;
+  double* rp = nullptr;
 
   amg::KState* st = nullptr;
   amg::KState* st_host = nullptr;  // pinned mirror for polling
@@ -512,6 +523,7 @@ inline void check_tail(DevHierarchy<T>& H, hipStream_t s) {
 inline int64_t max_parts(const amg_solver& S) {
   int64_t m = vec_blocks(S.n);
   m = std::max<int64_t>(m, S.A0.nblocks);
+  m = std::max<int64_t>(m, S.Afull.nblocks);
   if (S.block) {
     m = std::max<int64_t>(m, S.B0.blocks());
     for (const auto& lv : S.bh64.lev) m = std::max<int64_t>(m, lv.A.blocks());
@@ -531,6 +543,15 @@ inline int64_t max_parts(const amg_solver& S) {
 template <class F>
 inline auto with_vcycle(amg_solver& S, F fn) {
   VcycleOpts o{S.prm.npre, S.prm.npost, S.prm.relax};
+  if (S.schur) {
+    const SchurOps so{&S.Dm, &S.Gs, S.mu, S.rp, S.split.n_u};
+    if (S.prm.precision == AMG_MIXED) {
+      SchurPrecond<float> P(Vcycle<float>(&S.h32, S.Ainv, S.nL, o), so);
+      return fn(P);
+    }
+    SchurPrecond<double> P(Vcycle<double>(&S.h64, S.Ainv, S.nL, o), so);
+    return fn(P);
+  }
   if (S.block) {
     if (S.prm.precision == AMG_MIXED) {
       BlockVcycle<float> V(&S.bh32, S.Ainv, S.nL);
@@ -557,12 +578,16 @@ inline void fin(amg_solver& S, int K, int nparts, int op, hipStream_t s) {
 
 inline const int* skip_of(amg_solver& S) { return &S.st->done; }
 
-// Product with the FP64 fine operator of the Krylov loop (scalar CSR, or
-// block CSR with the scalar epilogue applied row by row).
+// The Krylov loop's scalar FP64 operator: the fine level, or the whole
+// system of a field split.
+inline const DevCsr<double>& krylov_op(const amg_solver& S) { return S.schur ? S.Afull : S.A0; }
+
+// Product with the FP64 operator of the Krylov loop (scalar CSR, or block
+// CSR with the scalar epilogue applied row by row).
 template <class G, class E>
 inline int outer_spmv(amg_solver& S, G g, E e, double* partials, const int* skip, hipStream_t s) {
   if (S.block) return launch_bsr(S.B0, g, PerRow<E>{e}, partials, skip, s);
-  return launch_spmv(S.A0, g, e, partials, skip, s);
+  return launch_spmv(krylov_op(S), g, e, partials, skip, s);
 }
 
 // r = f - A x with (r.r, f.f) and the init scalar update.
@@ -652,7 +677,7 @@ inline KState poll(amg_solver& S, hipStream_t s) {
 // r = f - A x and the opening of a cycle (first: the initial residual).
 inline void enqueue_gm_cycle_start(amg_solver& S, bool first, hipStream_t s) {
   const int n = static_cast<int>(S.n);
-  int nb = launch_spmv(S.A0, GatherX<double, double>{S.x}, EpiResidNorms{S.r, S.f}, S.partials,
+  int nb = launch_spmv(krylov_op(S), GatherX<double, double>{S.x}, EpiResidNorms{S.r, S.f}, S.partials,
                        first ? nullptr : skip_of(S), s);
   gm_start_state_kernel<<<1, kFinBS, 0, s>>>(S.partials, nb, S.st, S.gm, first ? 1 : 0);
   AMG_LAUNCHED();
@@ -670,7 +695,7 @@ inline void enqueue_gm_step(amg_solver& S, int j, hipStream_t s) {
   double* w = S.q;
   const int* stop = &S.gm->stop;
   with_vcycle(S, [&](auto& V) { return V.template run<0>(vj, zj, S.partials, stop, s); });
-  launch_spmv(S.A0, GatherX<double, double>{zj}, EpiStore<double, double>{w}, nullptr, stop, s);
+  launch_spmv(krylov_op(S), GatherX<double, double>{zj}, EpiStore<double, double>{w}, nullptr, stop, s);
   const int nb = S.gm_nb;
   for (int pass = 0; pass < 2; ++pass) {
     gm_dots_kernel<<<dim3(nb, j + 1), kVecBS, 0, s>>>(n, S.gmV, ld, w, S.gm_partials, S.gm);
@@ -753,7 +778,8 @@ inline amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, h
     k = run_gmres(S, s, &cycles);
     restarts = std::max(cycles - 1, 0);
     if (k.done != kZeroRhs) {
-      int nb = launch_spmv(S.A0, GatherX<double, double>{S.x}, EpiResidNorms{S.tmp, S.f}, S.partials, nullptr, s);
+      int nb = launch_spmv(krylov_op(S), GatherX<double, double>{S.x}, EpiResidNorms{S.tmp, S.f}, S.partials,
+                           nullptr, s);
       fin(S, 2, nb, kFinTrue, s);
       k = poll(S, s);
     }
@@ -852,6 +878,8 @@ inline void drop_device_state(amg_solver& S) {
   S.rt = S.v = S.phat = S.s = S.shat = S.t = nullptr;
   S.gmV = S.gmZ = S.gm_partials = nullptr;
   S.gm = nullptr;
+  S.Afull = S.Dm = S.Gs = DevCsr<double>{};
+  S.mu = S.rp = nullptr;
 }
 
 // `accel`: the setup steps' accelerator, whose device copies of the levels
@@ -879,6 +907,14 @@ inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t 
     if (!S.A0.val) S.A0 = upload_csr<double>(ar, fine.A);  // unless uploaded before the setup steps
     if (S.prm.precision == AMG_MIXED) upload_levels<float>(S, S.h32, accel);
     else upload_levels<double>(S, S.h64, accel);
+    if (S.schur) {
+      S.n = S.split.A.rows;
+      S.Afull = upload_csr<double>(ar, S.split.A);
+      S.Dm = upload_csr<double>(ar, S.split.Dm);
+      S.Gs = upload_csr<double>(ar, S.split.G);
+      S.mu = ar.upload(S.split.mu.data(), S.split.mu.size());
+      S.rp = ar.get<double>(S.split.A.rows - S.split.n_u);
+    }
   }
   clk.enter(kPhCoarse);
   coarse_inverse(S, AL, s, alloc, opts.blas);

@@ -225,7 +225,7 @@ SCHUR_MUTATIONS = {
     "no_velocity_correction": ("field_split_apply", _one_edit(
         schur.field_split_apply, "u = u_star - vel_solve(b.G @ p)", "u = u_star", schur)),
     "schur_plus_sign": ("schur_matrix", _one_edit(
-        schur.schur_matrix, "b.S - b.D @ dinv @ b.G", "b.S + b.D @ dinv @ b.G", schur)),
+        schur.schur_matrix, "b.S - Dk @ b.G", "b.S + Dk @ b.G", schur)),
     "schur_with_full_inverse": ("schur_matrix", _one_edit(
         schur.schur_matrix, "dinv = sp.diags(1.0 / b.K.diagonal())",
         "dinv = sp.csr_matrix(np.linalg.inv(b.K.toarray()))", schur)),
