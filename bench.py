@@ -41,6 +41,12 @@ WORKLOADS = {
     "diffusion128-chebyshev": (128, "ones", "diffusion", "cg", "chebyshev"),
     # 4 unknowns per node, 4 x 4 blocks (96^3 nodes: 3,538,944 unknowns)
     "block96": (96, "uniform", "block", "cg", "spai0"),
+    # velocity/pressure system of equal-order P1 tetrahedra, Schur pressure
+    # correction (56^3 nodes: 702,464 unknowns; section 4's Navier-Stokes
+    # system has 713,456)
+    "oseen56": (56, "force", "oseen", "bicgstab", "spai0"),
+    "oseen56-gmres": (56, "force", "oseen", "gmres", "spai0"),
+    "oseen106": (106, "force", "oseen", "bicgstab", "spai0"),
 }
 KRYLOV_NAMES = {"cg": "PCG", "bicgstab": "BiCGStab", "gmres": "FGMRES(30)"}
 
@@ -48,6 +54,8 @@ KRYLOV_NAMES = {"cg": "PCG", "bicgstab": "BiCGStab", "gmres": "FGMRES(30)"}
 def workload_matrix(kind, N):
     import problems
 
+    if kind == "oseen":
+        return problems.oseen_p1(N)[0]
     if kind == "poisson":
         return problems.poisson3d(N)
     if kind == "block":
@@ -111,13 +119,21 @@ def run_solves(S, f, steps, warmup, torch):
     return x, info, times, wall
 
 
-def kernel_table(S, reps, relax="spai0", block=False):
+def kernel_table(S, reps, relax="spai0", block=False, split=False):
     """HIP-event timing of the level-1 kernels and of whole V-cycles.  The
     Chebyshev V-cycle runs other kernels than the four level-1 SPAI-0/Jacobi
     kernels, so for it only the outer SpMV and the V-cycle are timed; block
-    values time the V-cycle only."""
+    values time the V-cycle only.  A field split times the SpMV with the
+    whole system, the pressure hierarchy's level-1 kernels, its V-cycle and
+    the whole preconditioner."""
     out = {}
-    names = ("vcycle",) if block else ("outer_spmv_dot", "vcycle") if relax == "chebyshev" else S.KERNELS
+    if block:
+        names = ("vcycle",)
+    elif split:
+        names = ("split_outer_spmv_dot", "pre_smooth_residual", "post_smooth_dot", "restrict", "prolong", "vcycle",
+                 "split_precond")
+    else:
+        names = ("outer_spmv_dot", "vcycle") if relax == "chebyshev" else S.KERNELS[:6]
     for k in names:
         us, by = S.time_kernel(k, reps=reps)
         out[k] = {"us": us, "bytes": by, "GBps": by / us / 1e3, "frac": by / us / 1e3 / HBM_PEAK_GBS}
@@ -192,7 +208,7 @@ def pmc_probe(N, torch, amg, problems):
     out = {"copy_bytes": src.numel() * 8, "kernel_source_hash": kernel_source_hash()}
     for prec in ("fp64", "mixed"):
         S = amg.Solver(A, precision=prec)
-        for k in S.KERNELS:
+        for k in S.KERNELS[:6]:
             us, by = S.time_kernel(k, reps=3)
             out[f"{prec}:{k}"] = {"us": us, "bytes": by}
         S.release()
@@ -489,8 +505,13 @@ def main():
         return
     # the served stream's inputs come from a process pool: before any GPU use
     reqs = generate_requests(args.serving_leg) if args.serving_leg > 0 else None
-    A = workload_matrix(kind, N)
-    f_host = problems.rhs_uniform(A.n, 0) if rhs == "uniform" else problems.rhs_ones(A.n)
+    n_u = None
+    if kind == "oseen":
+        A, n_u = problems.oseen_p1(N)
+        f_host = problems.oseen_rhs(N)
+    else:
+        A = workload_matrix(kind, N)
+        f_host = problems.rhs_uniform(A.n, 0) if rhs == "uniform" else problems.rhs_ones(A.n)
     torch.cuda.set_device(0)
     f = torch.tensor(f_host, device="cuda")
     nnz = A.nnz if hasattr(A, "nnz") else A.nnzb * A.b * A.b
@@ -501,7 +522,8 @@ def main():
     precs = ["fp64"] if args.no_mixed else ["fp64", "mixed"]
     for prec in precs:
         log(f"setup {prec}")
-        S = amg.Solver(A, precision=prec, solver=solver, relax=relax, fuse_coarse=1 if args.fuse_coarse else 0)
+        S = amg.Solver(A, precision=prec, solver=solver, relax=relax, fuse_coarse=1 if args.fuse_coarse else 0,
+                       n_u=n_u)
         levels = [S.level_info(l) for l in range(S.nlevels)]
         fused_from, fused_grid = S.tail_info()
         log(f"{prec}: levels {levels}")
@@ -509,8 +531,9 @@ def main():
         xs[prec] = x.cpu().numpy()
         true_res = float(np.linalg.norm(f_host - A.to_scipy() @ xs[prec]) / np.linalg.norm(f_host))
         log(f"{prec}: {info['iters']} iters, solve {np.mean(times) * 1e3:.2f} ms, true res {true_res:.2e}")
-        ktab = kernel_table(S, args.reps, relax, block=(kind == "block"))
+        ktab = kernel_table(S, args.reps, relax, block=(kind == "block"), split=(kind == "oseen"))
         vc = ktab.pop("vcycle")
+        pc = ktab.pop("split_precond", None)
         results[prec] = {
             "solve_s_mean": wall / args.steps,
             "solve_s_p50": pct(times, 50),
@@ -529,6 +552,8 @@ def main():
             "fused_workgroups": fused_grid,
             "kernels": ktab,
         }
+        if pc is not None:
+            results[prec]["split_precond"] = pc
         S.release()
 
     copy_gbps = copy_bandwidth(torch)
@@ -552,7 +577,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{kind}3d {N}^3 (n={A.n}, nnz={nnz}), f={'U[0,1) seed 0' if rhs == 'uniform' else 'ones'}, "
+            "workload": (f"oseen P1 tetrahedra (Kuhn mesh) {N}^3 nodes x 4 fields (n={A.n}, nnz={nnz}), nu 0.01, "
+                         f"dt 2h, rotating wind, ASGS-type stabilisation, f=(1,0.5,0.25) h^3, "
+                         f"{KRYLOV_NAMES[solver]} with Schur pressure correction: SPAI-0 velocity, smoothed "
+                         f"aggregation eps 0.08 spai0 1+1 V-cycle on S - D diag(K)^-1 G, coarse <= 3000 dense, "
+                         f"tol 1e-8") if kind == "oseen" else
+                        f"{kind}3d {N}^3 (n={A.n}, nnz={nnz}), f={'U[0,1) seed 0' if rhs == 'uniform' else 'ones'}, "
                         f"AMG-{KRYLOV_NAMES[solver]}: smoothed aggregation eps 0.08, "
                         f"{relax + ' degree 3' if relax == 'chebyshev' else relax} 1+1 sweeps, V-cycle, "
                         f"coarse <= 3000 dense, tol 1e-8"
@@ -585,7 +615,8 @@ def main():
                           fp64_baseline=True)
         sv["workload"] = SERVING_WORKLOAD.format(count=args.serving_leg)
         line["serving"] = sv
-    if not args.no_cpu_baseline and kind != "block":  # the block oracle is sized for the parity tests
+    # the block and field-split oracles are sized for the parity tests
+    if not args.no_cpu_baseline and kind not in ("block", "oseen"):
         log("cpu baseline (oracle)")
         cb, errs = cpu_baseline(A, f_host, xs, solver, relax)
         line["cpu_baseline"] = cb

@@ -366,8 +366,12 @@ void amg_csr_release(amg_matrix m);
  * which: 0 outer SpMV q = A p with p.q (FP64), 1 level-1 pre-sweep +
  * residual, 2 level-1 post-sweep (with r.z), 3 level-1 restriction,
  * 4 level-1 prolongation + correction, 5 one whole V-cycle (all levels,
- * bytes summed over the hierarchy); 1-5 run in the handle's precision on its
- * internal work vectors (contents are overwritten).
+ * bytes summed over the hierarchy); field-split handles only: 6 the Krylov
+ * loop's SpMV with the whole system (as 0), 7 one application of the
+ * field-split preconditioner (its two SpMVs and the pressure V-cycle, bytes
+ * summed); on a field-split handle 0-5 concern the pressure hierarchy.
+ * 1-5 and 7 run in the handle's precision on its internal work vectors
+ * (contents are overwritten).
  */
 amg_status amg_time_kernel(amg_handle h, int32_t which, int32_t reps, void* hip_stream,
                            double* avg_us, double* bytes);

@@ -413,7 +413,8 @@ class Solver(_Handle):
         d["status"] = code
         return x, d
 
-    KERNELS = ("outer_spmv_dot", "pre_smooth_residual", "post_smooth_dot", "restrict", "prolong", "vcycle")
+    KERNELS = ("outer_spmv_dot", "pre_smooth_residual", "post_smooth_dot", "restrict", "prolong", "vcycle",
+               "split_outer_spmv_dot", "split_precond")
 
     def time_kernel(self, which, reps=50):
         """(mean microseconds per launch, algorithmic bytes per launch) of one hot kernel."""

@@ -338,6 +338,30 @@ double cheb_vcycle_bytes(const amg_solver& S, const DevHierarchy<T>& H) {
   return b;
 }
 
+// Algorithmic bytes of one V-cycle with npre = npost = 1: per level
+// 2 passes over A_l, one over P_l and R_l each, 11 vector passes of n_l
+// and 2 of n_{l+1}, by step: pre-sweep + residual reads f and m, writes
+// r; restriction reads r (writes f_c); prolongation reads z_c, m, f,
+// writes y; post-sweep reads y (gathered), m, f, writes z.  On level 1 f
+// and z are the Krylov loop's FP64 vectors: 3 reads of f and the write of
+// z at 8 bytes, the other 7 passes at the hierarchy's value size.
+// Dense coarse inverse + f_L, z_L.
+template <class T>
+double vcycle_bytes(const amg_solver& S, const DevHierarchy<T>& H) {
+  if (S.prm.relax == AMG_CHEBYSHEV) return cheb_vcycle_bytes(S, H);
+  const double sz = sizeof(T);
+  double b = 0.0;
+  for (size_t l = 0; l < H.lev.size(); ++l) {
+    const DevLevel<T>& L = H.lev[l];
+    const double nl = L.n, ncl = L.nc;
+    b += 2.0 * double(L.A.nnz) * (sz + 4) + 2.0 * double(L.P.nnz) * (sz + 4);
+    b += 12.0 * (nl + 1) + 4.0 * (ncl + 1) + 2.0 * ncl * sz;
+    b += (l == 0) ? nl * (4.0 * 8.0 + 7.0 * sz) : 11.0 * nl * sz;
+  }
+  b += 8.0 * double(S.nL) * double(S.nL) + 2.0 * double(S.nL) * sz;
+  return b;
+}
+
 template <class T>
 double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps, hipStream_t s,
                           double* bytes) {
@@ -375,6 +399,16 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
         launch_spmv(lv.P, GatherX<T, T>{zc}, EpiProlong<T, double, 1>{lv.y, lv.m, S.r, nullptr}, nullptr, nullptr,
                     st);
         break;
+      case 6:
+        launch_spmv(S.Afull, GatherX<double, double>{S.p}, EpiStoreDot{S.q, S.p}, S.partials, nullptr, st);
+        break;
+      case 7: {
+        VcycleOpts o{S.prm.npre, S.prm.npost, S.prm.relax};
+        const SchurOps so{&S.Dm, &S.Gs, S.mu, S.rp, S.split.n_u};
+        SchurPrecond<T> P(Vcycle<T>(&H, S.Ainv, S.nL, o), so);
+        P.template run<0>(S.r, S.z, S.partials, nullptr, st);
+        break;
+      }
       default: {
         VcycleOpts o{S.prm.npre, S.prm.npost, S.prm.relax};
         Vcycle<T> V(&H, S.Ainv, S.nL, o);
@@ -412,28 +446,24 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
   (void)hipGraphExecDestroy(ge);
   (void)hipGraphDestroy(g);
   check_tail(H, s);
-  if (which == 5 && S.prm.relax == AMG_CHEBYSHEV) {
-    *bytes = cheb_vcycle_bytes(S, H);
+  if (which == 5) {
+    *bytes = vcycle_bytes(S, H);
     return 1000.0 * ms / reps;
   }
-  if (which == 5) {
-    // Algorithmic bytes of one V-cycle with npre = npost = 1: per level
-    // 2 passes over A_l, one over P_l and R_l each, 11 vector passes of n_l
-    // and 2 of n_{l+1}, by step: pre-sweep + residual reads f and m, writes
-    // r; restriction reads r (writes f_c); prolongation reads z_c, m, f,
-    // writes y; post-sweep reads y (gathered), m, f, writes z.  On level 1 f
-    // and z are the Krylov loop's FP64 vectors: 3 reads of f and the write of
-    // z at 8 bytes, the other 7 passes at the hierarchy's value size.
-    // Dense coarse inverse + f_L, z_L.
-    double b = 0.0;
-    for (size_t l = 0; l < H.lev.size(); ++l) {
-      const DevLevel<T>& L = H.lev[l];
-      const double nl = L.n, ncl = L.nc;
-      b += 2.0 * double(L.A.nnz) * (sz + 4) + 2.0 * double(L.P.nnz) * (sz + 4);
-      b += 12.0 * (nl + 1) + 4.0 * (ncl + 1) + 2.0 * ncl * sz;
-      b += (l == 0) ? nl * (4.0 * 8.0 + 7.0 * sz) : 11.0 * nl * sz;
-    }
-    b += 8.0 * double(S.nL) * double(S.nL) + 2.0 * double(S.nL) * sz;
+  if (which == 6) {
+    // the whole system: p in, q out (p also the dot's second operand)
+    const double na = double(S.Afull.rows);
+    *bytes = double(S.Afull.nnz) * 12.0 + 4.0 * (na + 1) + 16.0 * na;
+    return 1000.0 * ms / reps;
+  }
+  if (which == 7) {
+    // r_p' = r_p - (D diag(M_u)) r_u: D's arrays, r_u gathered, r_p in, r_p' out;
+    // the pressure V-cycle; z_u = M_u (r_u - G z_p): G's arrays, z_p
+    // gathered, M_u and r_u in, z_u out.
+    const double nu = double(S.split.n_u), np = double(S.Dm.rows);
+    double b = double(S.Dm.nnz) * 12.0 + 4.0 * (np + 1) + 8.0 * nu + 16.0 * np;
+    b += vcycle_bytes(S, H);
+    b += double(S.Gs.nnz) * 12.0 + 4.0 * (nu + 1) + 8.0 * np + 24.0 * nu;
     *bytes = b;
     return 1000.0 * ms / reps;
   }
@@ -516,8 +546,9 @@ extern "C" {
 amg_status amg_time_kernel(amg_handle h, int32_t which, int32_t reps, void* hip_stream, double* avg_us,
                            double* bytes) {
   return guarded([&]() -> amg_status {
-    if (!h || !avg_us || !bytes || reps < 1 || which < 0 || which > 5) throw SetupError{-1, "bad argument"};
+    if (!h || !avg_us || !bytes || reps < 1 || which < 0 || which > 7) throw SetupError{-1, "bad argument"};
     if (!h->on_device) throw SetupError{-1, "handle was built by amg_setup_host: no device data"};
+    if (which >= 6 && !h->schur) throw SetupError{-1, "which = 6, 7 need a field-split handle"};
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     if (h->block) {
       if (which != 5) throw SetupError{-1, "block-value handles time the whole V-cycle only (which = 5)"};

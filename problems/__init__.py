@@ -30,4 +30,4 @@ from .blocks import (  # noqa: F401
     decoupled_diffusion3d,
     random_block_rhs,
 )
-from .stokes import stokes3d, stokes_rhs  # noqa: F401
+from .stokes import oseen_p1, oseen_rhs, stokes3d, stokes_rhs  # noqa: F401

@@ -40,7 +40,18 @@ def _problem(name):
         return problems.stokes3d(20, beta=0.0) + ({"coarse_enough": 500},)
     if name == "stokes14-perturbed":
         return _perturbed_stokes(14) + ({"coarse_enough": 500},)
+    # equal-order P1 tetrahedra with convection (nonsymmetric K) and
+    # stabilisation: the structure of the Navier-Stokes systems
+    if name == "oseen16":
+        return problems.oseen_p1(16) + ({"coarse_enough": 500},)
+    if name == "oseen24":
+        return problems.oseen_p1(24) + ({},)
     raise KeyError(name)
+
+
+def _rhs(name, A):
+    N = round((A.n // 4) ** (1 / 3))
+    return problems.oseen_rhs(N) if name.startswith("oseen") else problems.stokes_rhs(N)
 
 
 def _oracle_params(kw):
@@ -49,7 +60,8 @@ def _oracle_params(kw):
 
 
 APPLY_CASES = [("stokes7", {}), ("stokes16", {}), ("stokes24", {}), ("stokes20-unstabilised", {}),
-               ("stokes14-perturbed", {}), ("stokes16", {"relax": "jacobi"}), ("stokes16", {"relax": "chebyshev"})]
+               ("stokes14-perturbed", {}), ("stokes16", {"relax": "jacobi"}), ("stokes16", {"relax": "chebyshev"}),
+               ("oseen16", {}), ("oseen24", {})]
 
 
 @pytest.mark.parametrize("name,extra", APPLY_CASES, ids=[f"{c[0]}-{i}" for i, c in enumerate(APPLY_CASES)])
@@ -69,7 +81,7 @@ def test_split_apply_fp64_matches_oracle(name, extra):
     S.release()
 
 
-@pytest.mark.parametrize("name", ["stokes16", "stokes24", "stokes14-perturbed"])
+@pytest.mark.parametrize("name", ["stokes16", "stokes24", "stokes14-perturbed", "oseen24"])
 def test_split_apply_mixed_matches_fp32_oracle(name):
     A, n_u, kw = _problem(name)
     kw = {**kw, "solver": "bicgstab"}
@@ -98,6 +110,9 @@ SOLVE_CASES = [
     ("stokes7", {"solver": "bicgstab"}),
     ("stokes14-perturbed", {"solver": "bicgstab"}),
     ("stokes20-unstabilised", {"solver": "gmres"}),
+    ("oseen16", {"solver": "bicgstab"}),
+    ("oseen24", {"solver": "gmres"}),
+    ("oseen24", {"solver": "bicgstab", "precision": "mixed"}),
 ]
 
 
@@ -105,8 +120,7 @@ SOLVE_CASES = [
 def test_split_solve_matches_oracle(name, extra):
     A, n_u, kw = _problem(name)
     kw = {**kw, **extra}
-    N = round((A.n // 4) ** (1 / 3))
-    f = problems.stokes_rhs(N)
+    f = _rhs(name, A)
     S = amg.Solver(A, n_u=n_u, **kw)
     announce("schur solve", name, extra)
     x, info = S.solve(dev(f))
@@ -143,4 +157,35 @@ def test_split_refuses_cg_and_noalloc():
     S = amg.Solver(A, n_u=n_u, solver="gmres")
     with pytest.raises(amg.AmgError):
         S.vcycle_noalloc(dev(np.ones(A.n)))
+    S.release()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_oseen56(precision):
+    """The benchmark system (702,464 unknowns, 24.5M nonzeros) in the
+    benchmark's configuration: one preconditioner application against the
+    oracle's, and the whole solve against the oracle's solve."""
+    A, n_u = problems.oseen_p1(56)
+    f = problems.oseen_rhs(56)
+    mixed = precision == "mixed"
+    S = amg.Solver(A, n_u=n_u, solver="bicgstab", precision=precision)
+    ss = schur.setup(A.to_scipy(), n_u, oracle.Params(solver="bicgstab"))
+    assert S.nlevels == ss.h.nlevels
+    r = np.random.default_rng(9).standard_normal(A.n)
+    announce("oseen56 apply", precision)
+    z = host(S.vcycle(dev(r)))
+    zo = schur.precond(ss, mixed=mixed)(r)
+    e, m = rel_err(z, zo), max_rel(z, zo)
+    tol = mixed_vcycle_tol(S.nlevels, {}) if mixed else 1e-12
+    print(f"[oseen56 apply] {precision}: rel {e:.2e} max {m:.2e} bound {tol:.2e}", flush=True)
+    assert e <= tol and m <= 2 * tol
+    announce("oseen56 solve", precision)
+    x, info = S.solve(dev(f))
+    x = host(x)
+    xo, io, _ = schur.solve(A.to_scipy(), f, n_u, oracle.Params(solver="bicgstab"), mixed=mixed, ss=ss)
+    tr = true_rel_residual(A, x, f)
+    print(f"[oseen56 solve] {precision}: device iters {info['iters']} oracle {io.iters} true {tr:.2e}", flush=True)
+    assert info["status"] == 0 and tr <= 1e-8
+    assert abs(info["iters"] - io.iters) <= 1
+    assert rel_err(x, xo) <= 1e-6
     S.release()

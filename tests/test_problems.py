@@ -207,3 +207,36 @@ def test_stokes_structure(N):
     assert np.allclose(S.diagonal(), 6 * h * h / 12)
     f = stokes_rhs(N)
     assert f.shape == (4 * n,) and f[:n_u].min() == 1.0 and not f[n_u:].any()
+
+
+def test_oseen_p1_structure():
+    """P1 tetrahedra on the Kuhn mesh: every interior node couples to its 14
+    mesh neighbours; away from the boundary the rows of K sum to the lumped
+    nodal volume over dt (h^3 / dt: stiffness, convection and streamline
+    terms sum to zero), those of G_d and S to zero."""
+    from problems.stokes import oseen_p1, oseen_rhs
+
+    N = 6
+    A, n_u = oseen_p1(N)
+    n = N**3
+    h = 1.0 / (N + 1)
+    dt = 2.0 * h
+    M = A.to_scipy()
+    K, G, D, S = M[:n, :n], M[:n_u, n_u:], M[n_u:, :n_u], M[n_u:, n_u:]
+    assert abs(D + G.T).max() == 0
+    assert abs(K - K.T).max() > 0  # convection: nonsymmetric
+    assert M[:n, n:n_u].nnz == 0  # velocity components uncoupled
+    idx = np.arange(n)
+    c = np.stack([idx % N, (idx // N) % N, idx // (N * N)], axis=1)
+    deep = np.all((c >= 1) & (c <= N - 2), axis=1)
+    rl = np.diff(K.indptr)
+    assert np.all(rl[deep] == 15)
+    assert np.allclose(np.asarray(K.sum(axis=1)).ravel()[deep], h**3 / dt, rtol=1e-12)
+    for d in range(3):
+        Gd = G[d * n:(d + 1) * n]
+        assert np.allclose(np.asarray(Gd.sum(axis=1)).ravel()[deep], 0.0, atol=1e-14 * h * h)
+        assert Gd.diagonal().max() == 0  # no self coupling in the gradient
+    assert np.allclose(np.asarray(S.sum(axis=1)).ravel()[deep], 0.0, atol=1e-12 * S.diagonal().max())
+    assert np.all(M.diagonal()[n_u:] > 0)
+    f = oseen_rhs(N)
+    assert f.shape == (4 * n,) and not f[n_u:].any()
