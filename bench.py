@@ -12,6 +12,9 @@ Prints ONE JSON line.  Besides the solve time it reports the V-cycle's
 achieved bandwidth against MI355X's 8 TB/s HBM peak, the dominant kernel's
 roofline fraction (HIP-event timing of repeated launches on the solve
 stream, algorithmic bytes), and the oracle timed on the host as a baseline.
+The default line also carries a reduced served stream and two short legs:
+the Schur field split on the 56^3-node P1 Oseen system and the 4 x 4 block
+system of 96^3 nodes (5 timed solves each, FP64 and mixed).
 """
 
 from __future__ import annotations
@@ -461,6 +464,84 @@ SERVING_WORKLOAD = ("{count} diffusion systems n^3, n~U{{16..96}} (seed 6), k=ex
                     "Poisson arrivals (gaps seed 5)")
 
 
+def measure(name, steps, warmup, reps, no_mixed=False, fuse_coarse=False):
+    """Set up and time one workload in FP64 and mixed precision: (A, f_host,
+    results per precision, solutions per precision, nnz)."""
+    import numpy as np
+    import torch
+
+    import problems
+    from paper_1811_05704_amd import amg
+
+    N, rhs, kind, solver, relax = WORKLOADS[name]
+    n_u = None
+    if kind == "oseen":
+        A, n_u = problems.oseen_p1(N)
+        f_host = problems.oseen_rhs(N)
+    else:
+        A = workload_matrix(kind, N)
+        f_host = problems.rhs_uniform(A.n, 0) if rhs == "uniform" else problems.rhs_ones(A.n)
+    torch.cuda.set_device(0)
+    f = torch.tensor(f_host, device="cuda")
+    nnz = A.nnz if hasattr(A, "nnz") else A.nnzb * A.b * A.b
+    log(f"workload {name}: n={A.n} nnz={nnz}")
+
+    results = {}
+    xs = {}
+    precs = ["fp64"] if no_mixed else ["fp64", "mixed"]
+    for prec in precs:
+        log(f"setup {prec}")
+        S = amg.Solver(A, precision=prec, solver=solver, relax=relax, fuse_coarse=1 if fuse_coarse else 0,
+                       n_u=n_u)
+        levels = [S.level_info(l) for l in range(S.nlevels)]
+        fused_from, fused_grid = S.tail_info()
+        log(f"{prec}: levels {levels}")
+        x, info, times, wall = run_solves(S, f, steps, warmup, torch)
+        xs[prec] = x.cpu().numpy()
+        true_res = float(np.linalg.norm(f_host - A.to_scipy() @ xs[prec]) / np.linalg.norm(f_host))
+        log(f"{prec}: {info['iters']} iters, solve {np.mean(times) * 1e3:.2f} ms, true res {true_res:.2e}")
+        ktab = kernel_table(S, reps, relax, block=(kind == "block"), split=(kind == "oseen"))
+        vc = ktab.pop("vcycle")
+        pc = ktab.pop("split_precond", None)
+        results[prec] = {
+            "solve_s_mean": wall / steps,
+            "solve_s_p50": pct(times, 50),
+            "solve_s_p99": pct(times, 99),
+            "iters": info["iters"],
+            "true_rel_resid": true_res,
+            "setup_s": info["setup_s"],
+            "setup_profile_s": S.setup_profile(),
+            "op_complexity": info["op_complexity"],
+            "levels": [{"n": n, "nnz_A": a, "nnz_P": p} for n, a, p in levels],
+            "vcycle_us": vc["us"],
+            "vcycle_bytes": vc["bytes"],
+            "vcycle_GBps": vc["GBps"],
+            "vcycle_frac_of_peak": vc["frac"],
+            "fused_from_level": fused_from,
+            "fused_workgroups": fused_grid,
+            "kernels": ktab,
+        }
+        if pc is not None:
+            results[prec]["split_precond"] = pc
+        S.release()
+
+    return A, f_host, results, xs, nnz
+
+
+def leg_summary(name, steps, warmup, reps):
+    """A compact record of another workload for the default line."""
+    A, _, res, _, nnz = measure(name, steps, warmup, reps)
+    out = {"workload": name, "n": A.n, "nnz": nnz, "steps": steps, "warmup": warmup}
+    for prec, r in res.items():
+        out[prec] = {k: r[k] for k in ("solve_s_mean", "solve_s_p50", "solve_s_p99", "iters", "true_rel_resid",
+                                       "setup_s", "vcycle_us", "vcycle_GBps") if k in r}
+        if "split_precond" in r:
+            out[prec]["split_precond"] = r["split_precond"]
+        if r["kernels"]:
+            out[prec]["kernels"] = r["kernels"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -480,6 +561,9 @@ def main():
     ap.add_argument("--serving-closed-only", action="store_true")
     ap.add_argument("--serving-leg", type=int, default=300,
                     help="requests of the reduced served stream in the default line (0: none)")
+    ap.add_argument("--legs", default=None,
+                    help="comma-separated further workloads measured briefly (5 solves) for the same line "
+                         "(default: oseen56,block96 with the poisson150 workload, none otherwise; '' for none)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch a 1 GiB copy and a few launches of each hot kernel (run under "
                          "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
@@ -505,56 +589,8 @@ def main():
         return
     # the served stream's inputs come from a process pool: before any GPU use
     reqs = generate_requests(args.serving_leg) if args.serving_leg > 0 else None
-    n_u = None
-    if kind == "oseen":
-        A, n_u = problems.oseen_p1(N)
-        f_host = problems.oseen_rhs(N)
-    else:
-        A = workload_matrix(kind, N)
-        f_host = problems.rhs_uniform(A.n, 0) if rhs == "uniform" else problems.rhs_ones(A.n)
-    torch.cuda.set_device(0)
-    f = torch.tensor(f_host, device="cuda")
-    nnz = A.nnz if hasattr(A, "nnz") else A.nnzb * A.b * A.b
-    log(f"workload {args.workload}: n={A.n} nnz={nnz}")
-
-    results = {}
-    xs = {}
-    precs = ["fp64"] if args.no_mixed else ["fp64", "mixed"]
-    for prec in precs:
-        log(f"setup {prec}")
-        S = amg.Solver(A, precision=prec, solver=solver, relax=relax, fuse_coarse=1 if args.fuse_coarse else 0,
-                       n_u=n_u)
-        levels = [S.level_info(l) for l in range(S.nlevels)]
-        fused_from, fused_grid = S.tail_info()
-        log(f"{prec}: levels {levels}")
-        x, info, times, wall = run_solves(S, f, args.steps, args.warmup, torch)
-        xs[prec] = x.cpu().numpy()
-        true_res = float(np.linalg.norm(f_host - A.to_scipy() @ xs[prec]) / np.linalg.norm(f_host))
-        log(f"{prec}: {info['iters']} iters, solve {np.mean(times) * 1e3:.2f} ms, true res {true_res:.2e}")
-        ktab = kernel_table(S, args.reps, relax, block=(kind == "block"), split=(kind == "oseen"))
-        vc = ktab.pop("vcycle")
-        pc = ktab.pop("split_precond", None)
-        results[prec] = {
-            "solve_s_mean": wall / args.steps,
-            "solve_s_p50": pct(times, 50),
-            "solve_s_p99": pct(times, 99),
-            "iters": info["iters"],
-            "true_rel_resid": true_res,
-            "setup_s": info["setup_s"],
-            "setup_profile_s": S.setup_profile(),
-            "op_complexity": info["op_complexity"],
-            "levels": [{"n": n, "nnz_A": a, "nnz_P": p} for n, a, p in levels],
-            "vcycle_us": vc["us"],
-            "vcycle_bytes": vc["bytes"],
-            "vcycle_GBps": vc["GBps"],
-            "vcycle_frac_of_peak": vc["frac"],
-            "fused_from_level": fused_from,
-            "fused_workgroups": fused_grid,
-            "kernels": ktab,
-        }
-        if pc is not None:
-            results[prec]["split_precond"] = pc
-        S.release()
+    A, f_host, results, xs, nnz = measure(args.workload, args.steps, args.warmup, args.reps, args.no_mixed,
+                                          args.fuse_coarse)
 
     copy_gbps = copy_bandwidth(torch)
     log(f"device copy reference: {copy_gbps:.0f} GB/s")
@@ -616,6 +652,13 @@ def main():
         sv["workload"] = SERVING_WORKLOAD.format(count=args.serving_leg)
         line["serving"] = sv
     # the block and field-split oracles are sized for the parity tests
+    legs = args.legs if args.legs is not None else ("oseen56,block96" if args.workload == "poisson150" else "")
+    legs = [w for w in legs.split(",") if w]
+    if legs:
+        line["legs"] = {}
+        for w in legs:
+            log(f"leg {w}")
+            line["legs"][w] = leg_summary(w, 5, 1, 20)
     if not args.no_cpu_baseline and kind not in ("block", "oseen"):
         log("cpu baseline (oracle)")
         cb, errs = cpu_baseline(A, f_host, xs, solver, relax)
