@@ -68,7 +68,7 @@ def workload_matrix(kind, N):
     return problems.diffusion3d(N, g, velocity=vel)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_poisson150.json")
+TRAFFIC_FILES = {w: os.path.join(ROOT, "profiles", f"hbm_traffic_{w}.json") for w in ("poisson150", "oseen56")}
 # the kernels, their schedules and the V-cycle driver that picks their gathers and epilogues
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1811_05704_amd", "csrc", f)
                   for f in ("kernels.hpp", "device.hpp", "vcycle.hpp")]
@@ -84,11 +84,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec, kernel):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or None
-    when the kernel sources changed since the counters were taken."""
+def measured_traffic(workload, prec, kernel):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary of the
+    workload, or None when there is none or the kernel sources changed since
+    the counters were taken."""
+    if workload not in TRAFFIC_FILES:
+        return None
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(TRAFFIC_FILES[workload]) as fh:
             t = json.load(fh)
     except OSError:
         return None
@@ -161,22 +164,27 @@ def copy_bandwidth(torch, gib=2, reps=20):
     return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(A, f, x_gpu_by_prec, solver="cg", relax="spai0"):
+def cpu_baseline(A, f, x_gpu_by_prec, solver="cg", relax="spai0", n_u=None):
     """The oracle, single-threaded, on the host: one full FP64 solve at the
-    benchmark size (the oracle hierarchy is built first and not timed)."""
+    benchmark size (the oracle hierarchy is built first and not timed); with
+    n_u, the field-split oracle."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import oracle
+    from oracle import schur
 
     with threadpool_limits(limits=1):
         t = time.perf_counter()
         prm = oracle.Params(solver=solver, relax=relax)
-        h = oracle.setup(A, prm)
+        h = oracle.setup(A, prm) if n_u is None else schur.setup(A.to_scipy(), n_u, prm)
         t_setup = time.perf_counter() - t
         log(f"oracle setup {t_setup:.1f} s")
         t = time.perf_counter()
-        xo, io, _ = oracle.solve(A, f, prm, h=h)
+        if n_u is None:
+            xo, io, _ = oracle.solve(A, f, prm, h=h)
+        else:
+            xo, io, _ = schur.solve(A.to_scipy(), f, n_u, prm, ss=h)
         t_solve = time.perf_counter() - t
     errs = {p: float(np.linalg.norm(x - xo) / np.linalg.norm(xo)) for p, x in x_gpu_by_prec.items()}
     return {
@@ -184,8 +192,9 @@ def cpu_baseline(A, f, x_gpu_by_prec, solver="cg", relax="spai0"):
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"one full FP64 AMG-{KRYLOV_NAMES[solver]} solve of the same system (oracle hierarchy built first, "
-                  f"{t_setup:.1f} s, untimed); NumPy/SciPy pinned to 1 thread",
+        "sample": f"one full FP64 {'AMG' if n_u is None else 'Schur field-split'}-{KRYLOV_NAMES[solver]} solve of the "
+                  f"same system (oracle hierarchy built first, {t_setup:.1f} s, untimed); NumPy/SciPy pinned to 1 "
+                  f"thread",
         "iters": io.iters,
         "true_rel_resid": io.true_rel_resid,
         "setup_s": t_setup,
@@ -193,13 +202,15 @@ def cpu_baseline(A, f, x_gpu_by_prec, solver="cg", relax="spai0"):
     }, errs
 
 
-def pmc_probe(N, torch, amg, problems):
+def pmc_probe(N, torch, amg, problems, kind="poisson"):
     """Counter calibration and hot-kernel dispatches for rocprofv3 --pmc runs.
 
     A device-to-device copy of exactly 1 GiB (read 1 GiB, write 1 GiB) gives
     the scale between the counters and bytes; then each level-1 kernel and
     the V-cycle are launched through amg_time_kernel (reps launches after one
-    warm-up) in FP64 and mixed precision.
+    warm-up) in FP64 and mixed precision.  For the field split (kind
+    "oseen"): the SpMV with the whole system and the pressure hierarchy's
+    level-1 kernels.
     """
     torch.cuda.set_device(0)
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
@@ -207,11 +218,17 @@ def pmc_probe(N, torch, amg, problems):
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    A = problems.poisson3d(N)
+    n_u = None
+    if kind == "oseen":
+        A, n_u = problems.oseen_p1(N)
+        names = ("split_outer_spmv_dot", "pre_smooth_residual", "post_smooth_dot", "restrict", "prolong")
+    else:
+        A = problems.poisson3d(N)
+        names = amg.Solver.KERNELS[:6]
     out = {"copy_bytes": src.numel() * 8, "kernel_source_hash": kernel_source_hash()}
     for prec in ("fp64", "mixed"):
-        S = amg.Solver(A, precision=prec)
-        for k in S.KERNELS[:6]:
+        S = amg.Solver(A, precision=prec, n_u=n_u, solver="bicgstab" if n_u else "cg")
+        for k in names:
             us, by = S.time_kernel(k, reps=3)
             out[f"{prec}:{k}"] = {"us": us, "bytes": by}
         S.release()
@@ -585,7 +602,7 @@ def main():
 
     N, rhs, kind, solver, relax = WORKLOADS[args.workload]
     if args.pmc_probe:
-        pmc_probe(N, torch, amg, problems)
+        pmc_probe(N, torch, amg, problems, kind)
         return
     # the served stream's inputs come from a process pool: before any GPU use
     reqs = generate_requests(args.serving_leg) if args.serving_leg > 0 else None
@@ -636,7 +653,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": dom["frac"],
-            "traffic": measured_traffic("fp64", dom_name) if args.workload == "poisson150" else None,
+            "traffic": measured_traffic(args.workload, "fp64", dom_name),
         },
         "vcycle_GBps": base["vcycle_GBps"],
         "vcycle_frac_of_peak": base["vcycle_frac_of_peak"],
@@ -659,9 +676,10 @@ def main():
         for w in legs:
             log(f"leg {w}")
             line["legs"][w] = leg_summary(w, 5, 1, 20)
-    if not args.no_cpu_baseline and kind not in ("block", "oseen"):
+    # the block oracle is sized for the parity tests
+    if not args.no_cpu_baseline and kind != "block":
         log("cpu baseline (oracle)")
-        cb, errs = cpu_baseline(A, f_host, xs, solver, relax)
+        cb, errs = cpu_baseline(A, f_host, xs, solver, relax, n_u=3 * N**3 if kind == "oseen" else None)
         line["cpu_baseline"] = cb
         for p, e in errs.items():
             results[p]["err_vs_fp64_oracle"] = e

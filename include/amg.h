@@ -351,7 +351,8 @@ amg_status amg_csr_spmv(amg_matrix m, const void* x_dev, void* y_dev, void* hip_
  * block_bytes: LDS bytes of products per stream block (4096 for matrices
  * with less than 32 MiB of values; otherwise 8192 for FP64 matrices reduced
  * by one lane per row, else the smallest of 4096, 8192 and 16384 that holds
- * 256 / lanes_per_row rows of mean length), 0 for kind 1.  Any output pointer
+ * 256 / lanes_per_row rows of mean length, 512 / lanes_per_row with 16
+ * lanes per row), 0 for kind 1.  Any output pointer
  * may be NULL.
  */
 amg_status amg_csr_kernel_info(amg_matrix m, int32_t* kind, int32_t* lanes_per_row,

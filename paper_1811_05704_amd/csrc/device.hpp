@@ -149,19 +149,24 @@ Schedule make_schedule(const Csr& M, int force_kind = -1) {
   if (s.kind == 0) {
     s.lanes = stream_lanes(mean);
     // Block size: 4 KB for small matrices; otherwise the smallest of 4, 8 and
-    // 16 KB that holds one reduction pass (kBS / G rows of mean length), so
-    // few of the unrolled loads re-read the last entry (8 KB exists for G =
-    // 1 and 4; FP64 one-lane rows keep 8 KB, measured best).
-    const double pass = double(kBS / s.lanes) * mean;
+    // 16 KB that holds the rows of the reduction phase (kBS / G rows of mean
+    // length per pass; one pass, two for G = 16), so few of the unrolled
+    // loads re-read the last entry (8 KB exists for G = 1, 4 and 16; FP64
+    // one-lane rows keep 8 KB, measured best).  With one pass of 16 rows the
+    // 60-entry rows of a pressure Schur complement filled half of a 16 KB
+    // FP64 block; two passes of 16 fill it and were 2-6 % faster than one
+    // pass in 8 KB blocks.
+    const int npass = s.lanes == 16 ? 2 : 1;
+    const double pass = double(npass * kBS / s.lanes) * mean;
     if (M.nnz() * static_cast<int64_t>(sizeof(T)) < kStreamSmallMatrix) s.bclass = 1;
     else if (s.lanes == 1 && sizeof(T) == 8) s.bclass = 2;
     else if (pass <= stream_nnz<T, kStreamSmallBytes>()) s.bclass = 1;
-    else if (s.lanes <= 4 && pass <= stream_nnz<T, kStreamMidBytes>()) s.bclass = 2;
+    else if (s.lanes <= 16 && pass <= stream_nnz<T, kStreamMidBytes>()) s.bclass = 2;
     const int64_t cap = s.bclass == 1   ? stream_nnz<T, kStreamSmallBytes>()
                         : s.bclass == 2 ? stream_nnz<T, kStreamMidBytes>()
                                         : stream_nnz<T>();
-    // rows per block: at most one reduction pass of the workgroup (kBS / G)
-    const int64_t max_rows = std::min<int64_t>(kStreamMaxRows, kBS / s.lanes);
+    // rows per block: at most npass reduction passes of the workgroup
+    const int64_t max_rows = std::min<int64_t>(kStreamMaxRows, npass * kBS / s.lanes);
     s.blk.push_back(0);
     int64_t r = 0;
     while (r < rows) {
@@ -259,6 +264,7 @@ int launch_spmv(const DevCsr<T>& M, G g, E e, double* partials, const int* skip,
       case 18: csr_stream_kernel<4, NM, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
       case 64: csr_stream_kernel<16, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
       case 65: csr_stream_kernel<16, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      case 66: csr_stream_kernel<16, NM, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
       case 256: csr_stream_kernel<64, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
       default: csr_stream_kernel<64, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
     }

@@ -227,7 +227,7 @@ struct EpiSmooth {
 // memory latency (measured on the level matrices of the 150^3 hierarchy:
 // 15-40% faster below 32 MB).  Larger matrices take the smallest block that
 // holds one reduction pass (the schedule puts at most kBS / G rows in a
-// block), kStreamMidBytes (8 KB) or AMG_STREAM_BYTES.
+// block), kStreamMidBytes (8 KB; G = 1, 4, 16) or AMG_STREAM_BYTES.
 #ifndef AMG_STREAM_BYTES
 #define AMG_STREAM_BYTES 16384
 #endif
@@ -711,9 +711,9 @@ struct SpmvItem {
 // (lanes, block class) pairs of the stream schedule that the batched kernel
 // dispatches; the host checks every item against it before a launch.
 __host__ __device__ constexpr bool stream_dispatchable(int lanes, int bclass) {
-  return (lanes == 1 || lanes == 4) ? (bclass >= 0 && bclass <= 2)
-         : (lanes == 16 || lanes == 64) ? (bclass == 0 || bclass == 1)
-                                        : false;
+  return (lanes == 1 || lanes == 4 || lanes == 16) ? (bclass >= 0 && bclass <= 2)
+         : (lanes == 64)                            ? (bclass == 0 || bclass == 1)
+                                                    : false;
 }
 
 template <class T, class Gth, class E>
@@ -736,6 +736,7 @@ __global__ void __launch_bounds__(kBS) batched_spmv_kernel(const Batch<SpmvItem<
         case 18: stream_block<4, NM>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         case 64: stream_block<16, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         case 65: stream_block<16, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 66: stream_block<16, NM>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         case 256: stream_block<64, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
         default: stream_block<64, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
       }

@@ -139,6 +139,7 @@ __device__ __forceinline__ void tail_spmv(const TailMat<T>& M, const Gth& g, con
       case 18: stream_block<4, NM>(M.A, g, e, vb, nullptr, 0, prod); break;
       case 64: stream_block<16, NL>(M.A, g, e, vb, nullptr, 0, prod); break;
       case 65: stream_block<16, NS>(M.A, g, e, vb, nullptr, 0, prod); break;
+      case 66: stream_block<16, NM>(M.A, g, e, vb, nullptr, 0, prod); break;
       case 256: stream_block<64, NL>(M.A, g, e, vb, nullptr, 0, prod); break;
       default: stream_block<64, NS>(M.A, g, e, vb, nullptr, 0, prod); break;
     }

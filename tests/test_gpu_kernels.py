@@ -61,6 +61,7 @@ CASES = [
     # at least 32 MiB of values in both precisions: 16 KB stream blocks
     ("large_blocks_g1", 1400000, 1400000, lambda r: r.integers(1, 13, 1400000)),
     ("large_blocks_g4", 300000, 300000, lambda r: r.integers(20, 41, 300000)),
+    ("large_blocks_g16", 150000, 150000, lambda r: r.integers(50, 71, 150000)),  # FP32: 8 KB blocks
 ]
 
 
@@ -80,14 +81,14 @@ def test_spmv_matches_cpu(name, rows, cols, gen, precision):
         assert info["lanes"] == expect
         sz = 8 if precision == "fp64" else 4
         vbytes = int(rp[-1]) * sz
-        one_pass = (256 // expect) * mean  # entries of one reduction pass
+        one_pass = (2 if expect == 16 else 1) * (256 // expect) * mean  # entries of the reduction passes
         if vbytes < 32 << 20:
             assert info["block_bytes"] == 4096
         elif expect == 1 and precision == "fp64":
             assert info["block_bytes"] == 8192
         elif one_pass <= 4096 // sz:
             assert info["block_bytes"] == 4096
-        elif expect <= 4 and one_pass <= 8192 // sz:
+        elif expect <= 16 and one_pass <= 8192 // sz:
             assert info["block_bytes"] == 8192
         else:
             assert info["block_bytes"] == 16384
