@@ -217,6 +217,21 @@ amg_status amg_get_smoother_blocks(amg_handle h, int32_t level, double* blocks, 
 amg_status amg_setup_schur(int64_t n, const int64_t* row_ptr, const int32_t* col,
                            const double* val, int64_t n_u, const amg_params* p,
                            const amg_allocator* alloc, void* hip_stream, amg_handle* out);
+/*
+ * The same field split for a system in any order (for example interlaced,
+ * four unknowns per mesh node): pmask uint8[n] (host, caller-owned, read
+ * during the call) marks each pressure unknown with 1 and each velocity
+ * unknown with 0; anything else, or a mask without both fields, is
+ * AMG_ERR_INVALID_ARG.  The library renumbers the system velocity first
+ * (each field in the caller's order) and works in that order; amg_solve and
+ * amg_vcycle take and return vectors in the caller's order (amg_vcycle then
+ * uses two of the handle's work vectors, so it must not overlap a solve on
+ * the same handle).  The query functions describe the renumbered system's
+ * pressure hierarchy.
+ */
+amg_status amg_setup_schur_masked(int64_t n, const int64_t* row_ptr, const int32_t* col,
+                                  const double* val, const uint8_t* pmask, const amg_params* p,
+                                  const amg_allocator* alloc, void* hip_stream, amg_handle* out);
 /* The field split's setup on the host only (queries only, like amg_setup_host). */
 amg_status amg_setup_schur_host(int64_t n, const int64_t* row_ptr, const int32_t* col,
                                 const double* val, int64_t n_u, const amg_params* p,

@@ -90,6 +90,8 @@ def lib():
         "amg_setup_schur": (i32, [i64, P64, P32, PD, i64, C.POINTER(Params), C.POINTER(Allocator), vp,
                                   C.POINTER(vp)]),
         "amg_setup_schur_host": (i32, [i64, P64, P32, PD, i64, C.POINTER(Params), C.POINTER(vp)]),
+        "amg_setup_schur_masked": (i32, [i64, P64, P32, PD, C.POINTER(C.c_uint8), C.POINTER(Params),
+                                         C.POINTER(Allocator), vp, C.POINTER(vp)]),
         "amg_get_level_bsr": (i32, [vp, i32, i32, P64, P32, PD]),
         "amg_get_smoother_blocks": (i32, [vp, i32, PD, PD]),
         "amg_solve": (i32, [vp, vp, vp, vp, C.POINTER(Info)]),
@@ -130,7 +132,7 @@ def lib():
 def exported_symbols():
     return [
         "amg_params_default", "amg_setup", "amg_setup_host", "amg_setup_block", "amg_setup_block_host",
-        "amg_setup_schur", "amg_setup_schur_host",
+        "amg_setup_schur", "amg_setup_schur_host", "amg_setup_schur_masked",
         "amg_get_level_bsr", "amg_get_smoother_blocks", "amg_solve", "amg_release",
         "amg_last_error", "amg_vcycle", "amg_num_levels", "amg_level_info", "amg_get_aggregates",
         "amg_get_level_csr", "amg_get_smoother", "amg_level_kernel_info", "amg_csr_upload", "amg_csr_spmv",
@@ -333,10 +335,12 @@ class Solver(_Handle):
     arguments are :class:`Params` fields.  With ``torch_alloc`` (default) the
     library's device memory comes from PyTorch's caching allocator.  With
     ``n_u`` the Schur-complement field split (``amg_setup_schur``): A is the
-    whole velocity/pressure system, velocity unknowns first.
+    whole velocity/pressure system, velocity unknowns first; with ``pmask``
+    (one byte per unknown, 1 = pressure) the same split in any order
+    (``amg_setup_schur_masked``).
     """
 
-    def __init__(self, A, torch_alloc: bool = True, alloc_limit=None, n_u=None, **params):
+    def __init__(self, A, torch_alloc: bool = True, alloc_limit=None, n_u=None, pmask=None, **params):
         import torch
 
         if not torch.cuda.is_available():
@@ -377,7 +381,15 @@ class Solver(_Handle):
             self._alloc = Allocator(ALLOC_FN(_a), FREE_FN(_f), None)
             alloc_p = C.byref(self._alloc)
         h = C.c_void_p()
-        if n_u is not None:
+        if pmask is not None:
+            rp, c, v = _csr_arrays(A)
+            self._pmask = np.ascontiguousarray(pmask, dtype=np.uint8)
+            assert self._pmask.size == self.n
+            _check(lib().amg_setup_schur_masked(self.n, _ptr(rp, C.c_int64), _ptr(c, C.c_int32),
+                                                _ptr(v, C.c_double), _ptr(self._pmask, C.c_uint8),
+                                                C.byref(self.params), alloc_p, C.c_void_p(stream.cuda_stream),
+                                                C.byref(h)))
+        elif n_u is not None:
             rp, c, v = _csr_arrays(A)
             _check(lib().amg_setup_schur(self.n, _ptr(rp, C.c_int64), _ptr(c, C.c_int32), _ptr(v, C.c_double),
                                          int(n_u), C.byref(self.params), alloc_p, C.c_void_p(stream.cuda_stream),

@@ -47,6 +47,48 @@ Csr extract(const Csr& A, int64_t r0, int64_t r1, int64_t c0, int64_t c1, const 
 
 }  // namespace
 
+int64_t field_order(int64_t n, const uint8_t* pmask, std::vector<int32_t>* old_of_new) {
+  if (!pmask) throw SetupError{-1, "pmask must not be NULL"};
+  int64_t n_u = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (pmask[i] > 1) throw SetupError{-1, "pmask entries must be 0 (velocity) or 1 (pressure)"};
+    n_u += pmask[i] == 0;
+  }
+  if (n_u == 0 || n_u == n) throw SetupError{-1, "pmask must mark some but not all unknowns as pressure"};
+  old_of_new->resize(n);
+  int64_t u = 0, p = n_u;
+  for (int64_t i = 0; i < n; ++i) (*old_of_new)[pmask[i] ? p++ : u++] = static_cast<int32_t>(i);
+  return n_u;
+}
+
+Csr permute_symmetric(const Csr& A, const std::vector<int32_t>& old_of_new) {
+  const int64_t n = A.rows;
+  std::vector<int32_t> new_of_old(n);
+  for (int64_t j = 0; j < n; ++j) new_of_old[old_of_new[j]] = static_cast<int32_t>(j);
+  Csr B;
+  B.rows = B.cols = n;
+  B.ptr.assign(n + 1, 0);
+  for (int64_t j = 0; j < n; ++j) B.ptr[j + 1] = B.ptr[j] + (A.ptr[old_of_new[j] + 1] - A.ptr[old_of_new[j]]);
+  B.col.resize(B.nnz());
+  B.val.resize(B.nnz());
+  for_row_ranges(n, [&](int64_t b, int64_t e) {
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t j = b; j < e; ++j) {
+      const int64_t i = old_of_new[j];
+      row.clear();
+      for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) row.emplace_back(new_of_old[A.col[k]], A.val[k]);
+      std::sort(row.begin(), row.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+      int64_t o = B.ptr[j];
+      for (const auto& c : row) {
+        B.col[o] = c.first;
+        B.val[o] = c.second;
+        ++o;
+      }
+    }
+  });
+  return B;
+}
+
 Csr split_fields(Csr A, int64_t n_u, FieldSplit* out) {
   const int64_t n = A.rows;
   if (n_u <= 0 || n_u >= n) throw SetupError{-1, "velocity unknowns n_u must satisfy 0 < n_u < n"};

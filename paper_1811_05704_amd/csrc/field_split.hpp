@@ -9,6 +9,7 @@
 #pragma once
 
 #include <cstdint>
+#include <vector>
 
 #include "host_setup.hpp"
 
@@ -20,7 +21,21 @@ struct FieldSplit {
   Csr Dm;           // D diag(M_u): pressure rows, velocity columns
   Csr G;            // velocity rows, pressure columns numbered from 0
   hvec<double> mu;  // SPAI-0 diagonal of K: k_ii / sum_j k_ij^2 over K's columns
+  // The caller's index of each unknown of the velocity-first order (empty:
+  // the caller's order is velocity first).
+  std::vector<int32_t> old_of_new;
 };
+
+// Velocity-first order of a system whose pressure unknowns are marked by
+// pmask[i] = 1 (velocity 0; the fields in any order): old_of_new[j] is the
+// caller's index of unknown j of the new order (the velocity unknowns, then
+// the pressure unknowns, each in the caller's order).  Returns n_u; throws
+// SetupError unless every entry is 0 or 1 and both fields are present.
+int64_t field_order(int64_t n, const uint8_t* pmask, std::vector<int32_t>* old_of_new);
+
+// B = Q A Q^T with Q the permutation of old_of_new (row j of B is row
+// old_of_new[j] of A, columns renumbered and ascending).
+Csr permute_symmetric(const Csr& A, const std::vector<int32_t>& old_of_new);
 
 // Takes the whole system A (columns ascending within each row), fills *out
 // with it and the preconditioner's operators, and returns S_hat (columns

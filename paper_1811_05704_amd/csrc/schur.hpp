@@ -28,6 +28,20 @@ struct EpiSchurVelocity {
   __device__ __forceinline__ void operator()(int i, double s, double*) const { z[i] = m[i] * (f[i] - s); }
 };
 
+// dst[j] = src[idx[j]] and dst[idx[j]] = src[j]: vectors between the
+// caller's order and the velocity-first order (idx a permutation).
+static __global__ void __launch_bounds__(kVecBS) gather_kernel(int n, double* dst, const double* src,
+                                                               const int32_t* idx) {
+  const int stride = gridDim.x * kVecBS;
+  for (int j = blockIdx.x * kVecBS + threadIdx.x; j < n; j += stride) dst[j] = src[idx[j]];
+}
+
+static __global__ void __launch_bounds__(kVecBS) scatter_kernel(int n, double* dst, const double* src,
+                                                                const int32_t* idx) {
+  const int stride = gridDim.x * kVecBS;
+  for (int j = blockIdx.x * kVecBS + threadIdx.x; j < n; j += stride) dst[idx[j]] = src[j];
+}
+
 struct SchurOps {
   const DevCsr<double>* Dm = nullptr;  // D diag(M_u): pressure rows, velocity columns
   const DevCsr<double>* G = nullptr;   // velocity rows, pressure columns

@@ -37,9 +37,11 @@ const char* amg_last_error(void) { return g_last_error.c_str(); }
 
 // n_u > 0: a Schur-complement field split with n_u velocity unknowns; the
 // hierarchy is built for the approximate pressure Schur complement.
+// pmask (with n_u = -1): the field split with the pressure unknowns marked,
+// in any order; the system is renumbered velocity first.
 static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
                            const amg_params* p, bool device, const amg_allocator* alloc, void* stream,
-                           amg_handle* out, int64_t n_u = 0) {
+                           amg_handle* out, int64_t n_u = 0, const uint8_t* pmask = nullptr) {
   if (out) *out = nullptr;
   return guarded([&]() -> amg_status {
     if (!out) throw SetupError{-1, "out must not be NULL"};
@@ -98,7 +100,13 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
     validate_csr(n, row_ptr, col, val, /*require_diag=*/n_u == 0);
     Csr A = to_csr(n, row_ptr, col, val);
     if (n_u) {
+      std::vector<int32_t> order;
+      if (pmask) {
+        n_u = field_order(n, pmask, &order);
+        A = permute_symmetric(A, order);
+      }
       A = split_fields(std::move(A), n_u, &S->split);
+      S->split.old_of_new = std::move(order);
       S->schur = true;
     }
     // Data-parallel setup steps on the device (bit-identical to the host's);
@@ -225,6 +233,18 @@ amg_status amg_setup_schur(int64_t n, const int64_t* row_ptr, const int32_t* col
   return do_setup(n, row_ptr, col, val, p, true, alloc, hip_stream, out, n_u);
 }
 
+amg_status amg_setup_schur_masked(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+                                  const uint8_t* pmask, const amg_params* p, const amg_allocator* alloc,
+                                  void* hip_stream, amg_handle* out) {
+  if (out) *out = nullptr;
+  if (n <= 0 || !pmask) return set_error(AMG_ERR_INVALID_ARG, "null pmask or non-positive size");
+  return guarded([&]() -> amg_status {
+    std::vector<int32_t> order;
+    (void)field_order(n, pmask, &order);  // the mask's errors before any device work
+    return do_setup(n, row_ptr, col, val, p, true, alloc, hip_stream, out, -1, pmask);
+  });
+}
+
 amg_status amg_setup_schur_host(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
                                 int64_t n_u, const amg_params* p, amg_handle* out) {
   if (n_u <= 0 || n_u >= n) {
@@ -253,7 +273,16 @@ amg_status amg_vcycle(amg_handle h, const double* r_dev, double* z_dev, void* hi
       throw SetupError{-1, "r and z must not alias"};
     TraceRange range("amg V-cycle");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    with_vcycle(*h, [&](auto& V) { return V.template run<0>(r_dev, z_dev, h->partials, nullptr, s); });
+    if (h->perm) {  // the caller's order -> velocity first and back, through two work vectors
+      const int n = static_cast<int>(h->n);
+      gather_kernel<<<vec_blocks(n), kVecBS, 0, s>>>(n, h->tmp, r_dev, h->perm);
+      AMG_LAUNCHED();
+      with_vcycle(*h, [&](auto& V) { return V.template run<0>(h->tmp, h->q, h->partials, nullptr, s); });
+      scatter_kernel<<<vec_blocks(n), kVecBS, 0, s>>>(n, z_dev, h->q, h->perm);
+      AMG_LAUNCHED();
+    } else {
+      with_vcycle(*h, [&](auto& V) { return V.template run<0>(r_dev, z_dev, h->partials, nullptr, s); });
+    }
     AMG_HIP(hipStreamSynchronize(s));
     check_tail(h->h64, s);
     check_tail(h->h32, s);

@@ -89,6 +89,7 @@ struct amg_solver {
   amg::DevCsr<double> Afull, Dm, Gs;
   double* mu = nullptr;
   double* rp = nullptr;
+  int32_t* perm = nullptr;  // caller's index of each velocity-first unknown (NULL: same order)
 
   amg::KState* st = nullptr;
   amg::KState* st_host = nullptr;  // pinned mirror for polling
@@ -761,8 +762,15 @@ inline amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, h
   const double t0 = now_s();
   const int n = static_cast<int>(S.n);
   const size_t bytes = sizeof(double) * S.n;
-  AMG_HIP(hipMemcpyAsync(S.f, f_dev, bytes, hipMemcpyDeviceToDevice, s));
-  AMG_HIP(hipMemcpyAsync(S.x, u_dev, bytes, hipMemcpyDeviceToDevice, s));
+  if (S.perm) {  // the caller's order -> velocity first
+    gather_kernel<<<vec_blocks(n), kVecBS, 0, s>>>(n, S.f, f_dev, S.perm);
+    AMG_LAUNCHED();
+    gather_kernel<<<vec_blocks(n), kVecBS, 0, s>>>(n, S.x, u_dev, S.perm);
+    AMG_LAUNCHED();
+  } else {
+    AMG_HIP(hipMemcpyAsync(S.f, f_dev, bytes, hipMemcpyDeviceToDevice, s));
+    AMG_HIP(hipMemcpyAsync(S.x, u_dev, bytes, hipMemcpyDeviceToDevice, s));
+  }
   KState init{};
   init.tol = S.prm.tol;
   init.max_iter = S.prm.max_iter;
@@ -811,7 +819,12 @@ inline amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, h
     fill_kernel<double><<<vec_blocks(n), kVecBS, 0, s>>>(n, S.x, 0.0);
     AMG_LAUNCHED();
   }
-  AMG_HIP(hipMemcpyAsync(u_dev, S.x, bytes, hipMemcpyDeviceToDevice, s));
+  if (S.perm) {
+    scatter_kernel<<<vec_blocks(n), kVecBS, 0, s>>>(n, u_dev, S.x, S.perm);
+    AMG_LAUNCHED();
+  } else {
+    AMG_HIP(hipMemcpyAsync(u_dev, S.x, bytes, hipMemcpyDeviceToDevice, s));
+  }
   AMG_HIP(hipStreamSynchronize(s));
   check_tail(S.h64, s);
   check_tail(S.h32, s);
@@ -880,6 +893,7 @@ inline void drop_device_state(amg_solver& S) {
   S.gm = nullptr;
   S.Afull = S.Dm = S.Gs = DevCsr<double>{};
   S.mu = S.rp = nullptr;
+  S.perm = nullptr;
 }
 
 // `accel`: the setup steps' accelerator, whose device copies of the levels
@@ -914,6 +928,7 @@ inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t 
       S.Gs = upload_csr<double>(ar, S.split.G);
       S.mu = ar.upload(S.split.mu.data(), S.split.mu.size());
       S.rp = ar.get<double>(S.split.A.rows - S.split.n_u);
+      if (!S.split.old_of_new.empty()) S.perm = ar.upload(S.split.old_of_new.data(), S.split.old_of_new.size());
     }
   }
   clk.enter(kPhCoarse);

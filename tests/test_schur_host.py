@@ -116,3 +116,50 @@ def test_unstabilised_system_has_no_pressure_diagonal_and_is_accepted():
     # the plain setup refuses the same matrix (missing diagonals)
     with pytest.raises(amg.AmgError):
         amg.HostHierarchy(A)
+
+
+def interlaced(A, n_u):
+    """The system renumbered node by node (u_x, u_y, u_z, p of node k at
+    4k .. 4k+3) and its pressure mask; returns (CSR, pmask, new_of_old)."""
+    n = A.n // 4
+    old = np.arange(A.n)
+    d, k = old // n, old % n
+    new_of_old = 4 * k + d
+    Q = sp.csr_matrix((np.ones(A.n), (new_of_old, old)), shape=(A.n, A.n))
+    B = (Q @ A.to_scipy() @ Q.T).tocsr()
+    pmask = np.zeros(A.n, dtype=np.uint8)
+    pmask[3::4] = 1
+    return _csr(B), pmask, new_of_old
+
+
+def _setup_masked(A, pmask, **kw):
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(A.col, dtype=np.int32)
+    val = np.ascontiguousarray(A.val, dtype=np.float64)
+    m = np.ascontiguousarray(pmask, dtype=np.uint8)
+    p = amg.make_params(**kw)
+    h = C.c_void_p()
+    code = amg.lib().amg_setup_schur_masked(int(A.n), rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                            col.ctypes.data_as(C.POINTER(C.c_int32)),
+                                            val.ctypes.data_as(C.POINTER(C.c_double)),
+                                            m.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(p), None, None,
+                                            C.byref(h))
+    if h.value:
+        amg.lib().amg_release(h)
+    return code, h.value, amg.lib().amg_last_error().decode()
+
+
+def test_masked_setup_rejects_bad_masks_before_device_work():
+    A, n_u = problems.stokes3d(3)
+    B, pmask, _ = interlaced(A, n_u)
+    for bad in (np.zeros(A.n, np.uint8), np.ones(A.n, np.uint8), np.where(pmask == 1, 2, 0).astype(np.uint8)):
+        code, h, msg = _setup_masked(B, bad, solver="bicgstab")
+        assert code == -1 and h is None and "pmask" in msg
+
+
+def test_interlaced_system_is_the_permuted_one():
+    A, n_u = problems.stokes3d(3)
+    B, pmask, new_of_old = interlaced(A, n_u)
+    M, N = A.to_scipy().toarray(), B.to_scipy().toarray()
+    assert np.array_equal(N[np.ix_(new_of_old, new_of_old)], M)
+    assert np.array_equal(np.flatnonzero(pmask), np.sort(new_of_old[n_u:]))
