@@ -113,6 +113,9 @@ SOLVE_CASES = [
     ("oseen16", {"solver": "bicgstab"}),
     ("oseen24", {"solver": "gmres"}),
     ("oseen24", {"solver": "bicgstab", "precision": "mixed"}),
+    ("oseen16", {"solver": "gmres", "relax": "chebyshev"}),
+    ("stokes16", {"solver": "bicgstab", "npre": 2, "npost": 2}),
+    ("oseen16", {"solver": "bicgstab", "relax": "jacobi", "precision": "mixed"}),
 ]
 
 
@@ -236,3 +239,16 @@ def test_masked_split_on_interlaced_system(name, precision):
     assert abs(info["iters"] - io.iters) <= 1
     assert rel_err(x, xo) <= 1e-6
     S.release()
+
+
+def test_split_graph_and_direct_launch_identical():
+    A, n_u, kw = _problem("oseen16")
+    f = _rhs("oseen16", A)
+    out = []
+    for use_graph in (1, 0, 1):
+        S = amg.Solver(A, n_u=n_u, solver="bicgstab", use_graph=use_graph, **kw)
+        x, info = S.solve(dev(f))
+        out.append((host(x), info["iters"]))
+        S.release()
+    assert out[0][1] == out[1][1] == out[2][1]
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][0], out[2][0])
