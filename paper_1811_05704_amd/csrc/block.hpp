@@ -117,14 +117,36 @@ __device__ __forceinline__ void bsr_block(const BsrView<T>& A, const Gth& gather
   T s = T(0);
   if (i < A.rows) {
     const int b = A.ptr[i], e = A.ptr[i + 1];
-    for (int k = b + u; k < e; k += SUB) {
-      const int j = kB * A.col[k];
-      const T* v = A.val + static_cast<int64_t>(k) * kB2 + q * kB;
-      const T x0 = gather(j), x1 = gather(j + 1), x2 = gather(j + 2), x3 = gather(j + 3);
-      s = s + v[0] * x0;
-      s = s + v[1] * x1;
-      s = s + v[2] * x2;
-      s = s + v[3] * x3;
+    // FP32: the blocks of U iterations are loaded and gathered before they
+    // are summed (in the same order), the last block re-read past the row's
+    // end; this took the FP32 block V-cycle from 625 to 571 us at 96^3 nodes
+    // and made the FP64 one 1 % slower, which keeps one block at a time.
+    constexpr int U = sizeof(T) == 4 ? 4 : 1;
+    for (int k0 = b + u; k0 < e; k0 += U * SUB) {
+      int jj[U];
+      T vv[U][kB];
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        const int k = min(k0 + t * SUB, e - 1);
+        jj[t] = kB * A.col[k];
+        const T* v = A.val + static_cast<int64_t>(k) * kB2 + q * kB;
+#pragma unroll
+        for (int c = 0; c < kB; ++c) vv[t][c] = v[c];
+      }
+      T xx[U][kB];
+#pragma unroll
+      for (int t = 0; t < U; ++t)
+#pragma unroll
+        for (int c = 0; c < kB; ++c) xx[t][c] = gather(jj[t] + c);
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        if (k0 + t * SUB < e) {
+          s = s + vv[t][0] * xx[t][0];
+          s = s + vv[t][1] * xx[t][1];
+          s = s + vv[t][2] * xx[t][2];
+          s = s + vv[t][3] * xx[t][3];
+        }
+      }
     }
   }
   s = group_sum<SUB>(s);
