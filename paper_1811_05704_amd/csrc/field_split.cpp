@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace amg {
@@ -127,65 +129,77 @@ Csr split_fields(Csr A, int64_t n_u, FieldSplit* out) {
   const Csr Dk = extract(A, n_u, n, 0, n_u, kinv.data());  // D diag(K)^-1
   const Csr& G = out->G;
 
-  // S_hat row i = S row i - (D diag(K)^-1 G) row i; counted, then written.
+  // S_hat row i = S row i - (D diag(K)^-1 G) row i.  Each chunk of rows is
+  // computed once into the chunk's own arrays (dense accumulators over the
+  // pressure columns, left unset until a row first touches a column), then
+  // the chunks are copied into place after the row counts are summed.
   Csr Sh;
   Sh.rows = Sh.cols = np;
   Sh.ptr.assign(np + 1, 0);
-  auto row = [&](int64_t i, std::vector<double>& acc, std::vector<double>& sv, std::vector<int64_t>& mark,
-                 std::vector<int32_t>& cols, bool write) {
-    cols.clear();
-    for (int64_t k = Dk.ptr[i]; k < Dk.ptr[i + 1]; ++k) {
-      const int32_t v = Dk.col[k];
-      const double w = Dk.val[k];
-      for (int64_t q = G.ptr[v]; q < G.ptr[v + 1]; ++q) {
-        const int32_t j = G.col[q];
-        if (mark[j] != i) {
-          mark[j] = i;
+  struct Chunk {
+    int64_t b = 0;
+    hvec<int32_t> col;
+    hvec<double> val;
+  };
+  std::mutex mu;
+  std::vector<Chunk> chunks;
+  for_row_ranges(np, [&](int64_t b, int64_t e) {
+    Chunk c;
+    c.b = b;
+    hvec<double> acc(np), sv(np);
+    std::vector<int32_t> mark(np, -1);
+    std::vector<int32_t> cols;
+    for (int64_t i = b; i < e; ++i) {
+      const int32_t stamp = static_cast<int32_t>(i);
+      cols.clear();
+      for (int64_t k = Dk.ptr[i]; k < Dk.ptr[i + 1]; ++k) {
+        const int32_t v = Dk.col[k];
+        const double w = Dk.val[k];
+        for (int64_t q = G.ptr[v]; q < G.ptr[v + 1]; ++q) {
+          const int32_t j = G.col[q];
+          if (mark[j] != stamp) {
+            mark[j] = stamp;
+            acc[j] = 0.0;
+            sv[j] = 0.0;
+            cols.push_back(j);
+          }
+          acc[j] += w * G.val[q];
+        }
+      }
+      for (int64_t k = first_at_or_after(A, n_u + i, n_u); k < A.ptr[n_u + i + 1]; ++k) {
+        const int32_t j = static_cast<int32_t>(A.col[k] - n_u);
+        if (mark[j] != stamp) {
+          mark[j] = stamp;
           acc[j] = 0.0;
-          sv[j] = 0.0;
           cols.push_back(j);
         }
-        acc[j] += w * G.val[q];
+        sv[j] = A.val[k];
       }
+      std::sort(cols.begin(), cols.end());
+      int64_t cnt = 0;
+      for (int32_t j : cols) {
+        const double t = sv[j] - acc[j];
+        if (t == 0.0) continue;
+        c.col.push_back(j);
+        c.val.push_back(t);
+        ++cnt;
+      }
+      Sh.ptr[i + 1] = cnt;
     }
-    for (int64_t k = first_at_or_after(A, n_u + i, n_u); k < A.ptr[n_u + i + 1]; ++k) {
-      const int32_t j = static_cast<int32_t>(A.col[k] - n_u);
-      if (mark[j] != i) {
-        mark[j] = i;
-        acc[j] = 0.0;
-        cols.push_back(j);
-      }
-      sv[j] = A.val[k];
-    }
-    std::sort(cols.begin(), cols.end());
-    int64_t o = write ? Sh.ptr[i] : 0;
-    for (int32_t j : cols) {
-      const double s = sv[j] - acc[j];
-      if (s == 0.0) continue;
-      if (write) {
-        Sh.col[o] = j;
-        Sh.val[o] = s;
-      }
-      ++o;
-    }
-    return o;
-  };
-  for (int pass = 0; pass < 2; ++pass) {
-    for_row_ranges(np, [&](int64_t b, int64_t e) {
-      std::vector<double> acc(np), sv(np);
-      std::vector<int64_t> mark(np, -1);
-      std::vector<int32_t> cols;
-      for (int64_t i = b; i < e; ++i) {
-        const int64_t c = row(i, acc, sv, mark, cols, pass == 1);
-        if (pass == 0) Sh.ptr[i + 1] = c;
-      }
+    std::lock_guard<std::mutex> lk(mu);
+    chunks.push_back(std::move(c));
+  });
+  for (int64_t i = 0; i < np; ++i) Sh.ptr[i + 1] += Sh.ptr[i];
+  Sh.col.resize(Sh.nnz());
+  Sh.val.resize(Sh.nnz());
+  std::vector<std::thread> copiers;
+  for (const Chunk& c : chunks)
+    copiers.emplace_back([&Sh, &c] {
+      std::copy(c.col.begin(), c.col.end(), Sh.col.begin() + Sh.ptr[c.b]);
+      std::copy(c.val.begin(), c.val.end(), Sh.val.begin() + Sh.ptr[c.b]);
     });
-    if (pass == 0) {
-      for (int64_t i = 0; i < np; ++i) Sh.ptr[i + 1] += Sh.ptr[i];
-      Sh.col.resize(Sh.nnz());
-      Sh.val.resize(Sh.nnz());
-    }
-  }
+  for (auto& t : copiers) t.join();
+
   // the hierarchy is built for S_hat: every row needs a positive diagonal
   std::atomic<int64_t> bad_p{-1};
   for_row_ranges(np, [&](int64_t b, int64_t e) {
