@@ -1,9 +1,8 @@
 // gfx950 kernels of the AMG solve phase.
 //
-// The solve phase (section 2, "AMG solve", and section 3: "sparse
-// matrix-vector product or linear vector combinations") reduces to CSR
-// sparse matrix-vector products with fused element-wise epilogues, vector
-// updates and dot products.  Everything here is bandwidth bound (about 2
+// The solve phase (section 2, "AMG solve"; section 3 names the two backend
+// primitives it rests on) reduces to CSR sparse matrix-vector products with
+// fused element-wise epilogues, vector updates and dot products.  Everything here is bandwidth bound (about 2
 // flops per 12 bytes of matrix in FP64), so no matrix cores are used: the
 // kernels are built around coalesced streaming of the CSR arrays, gathers of
 // x that hit in L2, LDS-staged row sums and wave64 reductions.
