@@ -107,10 +107,16 @@ struct amg_solver {
 
   hipGraphExec_t iter_exec = nullptr;
   hipGraph_t iter_graph = nullptr;
+  // GMRES: one graph per group of check_every Arnoldi steps of a cycle, and
+  // one for the end of a cycle (with the next cycle's start)
+  std::vector<hipGraphExec_t> gm_execs;
+  std::vector<hipGraph_t> gm_graphs;
 
   ~amg_solver() {
     if (iter_exec) (void)hipGraphExecDestroy(iter_exec);
     if (iter_graph) (void)hipGraphDestroy(iter_graph);
+    for (auto e : gm_execs) (void)hipGraphExecDestroy(e);
+    for (auto g : gm_graphs) (void)hipGraphDestroy(g);
     if (st_host) (void)hipHostFree(st_host);
     if (gm_host) (void)hipHostFree(gm_host);
     arena.reset();
@@ -734,25 +740,61 @@ inline KState gm_poll(amg_solver& S, hipStream_t s, int32_t* stop) {
   return *S.st_host;
 }
 
-// The whole GMRES solve with direct launches; the host polls every
-// check_every Arnoldi steps and at the end of each cycle.  Returns the final
-// state and the number of cycles run.
+// Captures the GMRES graphs: group g holds Arnoldi steps [g ce, min(m, (g +
+// 1) ce)), the last graph the end of a cycle and the next one's start.
+inline void build_gm_graphs(amg_solver& S) {
+  if (!S.gm_execs.empty()) return;
+  const int m = S.prm.gmres_m, ce = S.prm.check_every;
+  const int groups = (m + ce - 1) / ce;
+  for (int g = 0; g <= groups; ++g) {
+    AMG_HIP(hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      if (g < groups) {
+        for (int j = g * ce; j < std::min(m, (g + 1) * ce); ++j) enqueue_gm_step(S, j, S.cap_stream);
+      } else {
+        enqueue_gm_cycle_end(S, S.cap_stream);
+      }
+    } catch (...) {
+      hipGraph_t gr;
+      (void)hipStreamEndCapture(S.cap_stream, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      throw;
+    }
+    hipGraph_t gr = nullptr;
+    AMG_HIP(hipStreamEndCapture(S.cap_stream, &gr));
+    S.gm_graphs.push_back(gr);
+    hipGraphExec_t ex = nullptr;
+    AMG_HIP(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+    S.gm_execs.push_back(ex);
+  }
+}
+
+// The whole GMRES solve; the host polls every check_every Arnoldi steps and
+// at the end of each cycle.  With use_graph each group of steps between
+// polls, and the end of a cycle, is one graph launch (the same kernels in
+// the same order as the direct launches).  Returns the final state and the
+// number of cycles run.
 inline KState run_gmres(amg_solver& S, hipStream_t s, int* cycles) {
   int32_t stop = 0;
   enqueue_gm_cycle_start(S, true, s);
   KState k = gm_poll(S, s, &stop);
   *cycles = 0;
-  const int m = S.prm.gmres_m;
+  const int m = S.prm.gmres_m, ce = S.prm.check_every;
+  const int groups = (m + ce - 1) / ce;
+  if (S.prm.use_graph) build_gm_graphs(S);
   while (k.done == kRunning) {
     ++*cycles;
-    for (int j = 0; j < m; ++j) {
-      enqueue_gm_step(S, j, s);
-      if ((j + 1) % S.prm.check_every == 0 || j == m - 1) {
-        k = gm_poll(S, s, &stop);
-        if (stop) break;
+    for (int g = 0; g < groups; ++g) {
+      if (S.prm.use_graph) {
+        AMG_HIP(hipGraphLaunch(S.gm_execs[g], s));
+      } else {
+        for (int j = g * ce; j < std::min(m, (g + 1) * ce); ++j) enqueue_gm_step(S, j, s);
       }
+      k = gm_poll(S, s, &stop);
+      if (stop) break;
     }
-    enqueue_gm_cycle_end(S, s);
+    if (S.prm.use_graph) AMG_HIP(hipGraphLaunch(S.gm_execs[groups], s));
+    else enqueue_gm_cycle_end(S, s);
     k = gm_poll(S, s, &stop);
   }
   return k;

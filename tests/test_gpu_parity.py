@@ -504,12 +504,13 @@ def test_singular_coarse_level_is_reported():
     assert e.value.code == -4
 
 
-def test_graph_and_direct_launch_identical_and_deterministic():
+@pytest.mark.parametrize("solver", ["cg", "gmres"])
+def test_graph_and_direct_launch_identical_and_deterministic(solver):
     A, _ = _problem("diffusion24")
     f = problems.rhs_ones(A.n)
     out = []
     for use_graph in (1, 0, 1):
-        S = amg.Solver(A, use_graph=use_graph)
+        S = amg.Solver(A, use_graph=use_graph, solver=solver)
         x, info = S.solve(dev(f))
         out.append((host(x), info["iters"]))
         S.release()
