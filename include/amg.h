@@ -372,13 +372,21 @@ amg_status amg_csr_spmv(amg_matrix m, const void* x_dev, void* y_dev, void* hip_
  */
 amg_status amg_csr_kernel_info(amg_matrix m, int32_t* kind, int32_t* lanes_per_row,
                                int32_t* blocks, int32_t* block_bytes);
+/*
+ * Bytes per column index the stream kernel reads for this matrix: 2 when
+ * every stream block of at most one LDS pass spans at most 65536 columns
+ * (2-byte offsets from a per-block int32 base, which solver handles use for
+ * their own stream matrices too), else 4; *bytes is 4 for kind 1.
+ */
+amg_status amg_csr_column_bytes(amg_matrix m, int32_t* bytes);
 void amg_csr_release(amg_matrix m);
 
 /*
  * Measurement: launch one hot kernel of the solve `reps` times back to back
  * on hip_stream between two HIP events and report the mean duration per
  * launch (microseconds) and the kernel's algorithmic HBM bytes per launch
- * (CSR arrays read once, int32 indices, each vector read or written once).
+ * (CSR arrays read once, int32 indices, each vector read or written once;
+ * a kernel that reads 2-byte column offsets moves fewer bytes than this).
  * which: 0 outer SpMV q = A p with p.q (FP64), 1 level-1 pre-sweep +
  * residual, 2 level-1 post-sweep (with r.z), 3 level-1 restriction,
  * 4 level-1 prolongation + correction, 5 one whole V-cycle (all levels,

@@ -107,6 +107,7 @@ def lib():
         "amg_csr_upload": (i32, [i64, i64, P64, P32, PD, i32, vp, C.POINTER(vp)]),
         "amg_csr_spmv": (i32, [vp, vp, vp, vp]),
         "amg_csr_kernel_info": (i32, [vp, P32, P32, P32, P32]),
+        "amg_csr_column_bytes": (i32, [vp, P32]),
         "amg_csr_release": (None, [vp]),
         "amg_time_kernel": (i32, [vp, i32, i32, vp, PD, PD]),
         "amg_tail_info": (i32, [vp, P32, P32]),
@@ -136,7 +137,7 @@ def exported_symbols():
         "amg_get_level_bsr", "amg_get_smoother_blocks", "amg_solve", "amg_release",
         "amg_last_error", "amg_vcycle", "amg_num_levels", "amg_level_info", "amg_get_aggregates",
         "amg_get_level_csr", "amg_get_smoother", "amg_level_kernel_info", "amg_csr_upload", "amg_csr_spmv",
-        "amg_csr_kernel_info", "amg_csr_release", "amg_time_kernel", "amg_tail_info", "amg_tail_set_wait",
+        "amg_csr_kernel_info", "amg_csr_column_bytes", "amg_csr_release", "amg_time_kernel", "amg_tail_info", "amg_tail_set_wait",
         "amg_setup_profile", "amg_vcycle_noalloc",
         "amg_server_create", "amg_server_submit", "amg_server_step", "amg_server_wait_ready", "amg_server_poll",
         "amg_server_fetch", "amg_server_destroy",
@@ -490,8 +491,10 @@ class DeviceMatrix:
     def kernel_info(self):
         k, l, b, nb = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().amg_csr_kernel_info(self._h, C.byref(k), C.byref(l), C.byref(b), C.byref(nb)))
+        cb = C.c_int32()
+        _check(lib().amg_csr_column_bytes(self._h, C.byref(cb)))
         return {"kind": ("stream", "vector")[k.value], "lanes": l.value, "blocks": b.value,
-                "block_bytes": nb.value}
+                "block_bytes": nb.value, "column_bytes": cb.value}
 
     def spmv(self, x, y=None):
         import torch

@@ -87,6 +87,8 @@ class DevArena {
   }
   size_t bytes() const { return bytes_; }
   hipStream_t stream() const { return stream_; }
+  // Stream matrices uploaded here also get 2-byte column offsets (attach_compact_cols).
+  bool compact_cols = false;
   // Stream that release() synchronises before freeing (the owner's compute stream).
   void set_stream(hipStream_t s) { stream_ = s; }
   void release() {
@@ -124,7 +126,9 @@ struct DevCsr {
   int bclass = 0;  // stream block size class: 0 = 16 KB, 1 = 4 KB, 2 = 8 KB
   int32_t nblocks = 0;
   int32_t* blk = nullptr;
-  CsrView<T> view() const { return CsrView<T>{ptr, col, val, blk, rows, nblocks}; }
+  uint16_t* col16 = nullptr;  // stream: 2-byte column offsets per block (NULL: col)
+  int32_t* cbase = nullptr;
+  CsrView<T> view() const { return CsrView<T>{ptr, col, val, blk, rows, nblocks, col16, cbase}; }
 };
 
 struct Schedule {
@@ -193,6 +197,39 @@ Schedule make_schedule(const Csr& M, int force_kind = -1) {
   return s;
 }
 
+// Entries per stream block of the matrix's block size class.
+template <class T>
+int stream_block_entries(int bclass) {
+  return bclass == 1 ? stream_nnz<T, kStreamSmallBytes>() : bclass == 2 ? stream_nnz<T, kStreamMidBytes>()
+                                                                         : stream_nnz<T>();
+}
+
+// With ar.compact_cols, gives a stream matrix 2-byte column offsets from each
+// block's smallest column (2 bytes per entry and 4 per block read instead
+// of 4 per entry) when every block of at most one LDS pass spans at most
+// 65536 columns; otherwise the matrix keeps reading its int32 columns.  The
+// same columns either way, so results do not change.  Waits for the check.
+template <class T>
+void attach_compact_cols(DevArena& ar, DevCsr<T>& d) {
+  if (!ar.compact_cols || d.kind != 0 || d.nnz == 0 || d.nblocks == 0) return;
+  const hipStream_t s = ar.stream();
+  int32_t* cbase = ar.get<int32_t>(d.nblocks);
+  uint16_t* c16 = ar.get<uint16_t>(d.nnz);
+  int32_t* bad = ar.get<int32_t>(1);
+  fill_kernel<int32_t><<<1, kVecBS, 0, s>>>(1, bad, 0);
+  AMG_LAUNCHED();
+  compact_cols_kernel<<<d.nblocks, kBS, 0, s>>>(d.ptr, d.col, d.blk, stream_block_entries<T>(d.bclass), cbase, c16,
+                                                bad);
+  AMG_LAUNCHED();
+  int32_t h = 1;
+  AMG_HIP(hipMemcpyAsync(&h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  if (h == 0) {
+    d.col16 = c16;
+    d.cbase = cbase;
+  }
+}
+
 template <class T>
 DevCsr<T> upload_csr(DevArena& ar, const Csr& M, int force_kind = -1) {
   DevCsr<T> d;
@@ -219,6 +256,7 @@ DevCsr<T> upload_csr(DevArena& ar, const Csr& M, int force_kind = -1) {
   if (s.kind == 0) d.blk = ar.upload(s.blk.data(), s.blk.size());
   // upload uses pageable host buffers: finish before they go out of scope
   AMG_HIP(hipStreamSynchronize(ar.stream()));
+  attach_compact_cols(ar, d);
   return d;
 }
 
@@ -243,6 +281,7 @@ DevCsr<T> upload_values_like(DevArena& ar, const DevCsr<U>& like, const Csr& M) 
   d.bclass = s.bclass;
   d.nblocks = s.nblocks;
   if (s.kind == 0) d.blk = ar.upload(s.blk.data(), s.blk.size());
+  attach_compact_cols(ar, d);
   return d;
 }
 
@@ -255,19 +294,24 @@ int launch_spmv(const DevCsr<T>& M, G g, E e, double* partials, const int* skip,
     constexpr int NS = kStreamSmallBytes, NM = kStreamMidBytes, NL = AMG_STREAM_BYTES;
     const CsrView<T> A = M.view();
     const int n = M.nblocks;
-    switch (M.lanes * 4 + M.bclass) {
-      case 4: csr_stream_kernel<1, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 5: csr_stream_kernel<1, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 6: csr_stream_kernel<1, NM, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 16: csr_stream_kernel<4, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 17: csr_stream_kernel<4, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 18: csr_stream_kernel<4, NM, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 64: csr_stream_kernel<16, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 65: csr_stream_kernel<16, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 66: csr_stream_kernel<16, NM, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      case 256: csr_stream_kernel<64, NL, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-      default: csr_stream_kernel<64, NS, T, G, E><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
-    }
+    auto go = [&](auto c16) {
+      constexpr int C = decltype(c16)::value;
+      switch (M.lanes * 4 + M.bclass) {
+        case 4: csr_stream_kernel<1, NL, T, G, E, C><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+        case 5: csr_stream_kernel<1, NS, T, G, E, C><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+        case 6: csr_stream_kernel<1, NM, T, G, E, C><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+        case 16: csr_stream_kernel<4, NL, T, G, E, C><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+        case 17: csr_stream_kernel<4, NS, T, G, E, C><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+        case 18: csr_stream_kernel<4, NM, T, G, E, C><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+        case 64: csr_stream_kernel<16, NL, T, G, E, C><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+        case 65: csr_stream_kernel<16, NS, T, G, E, C><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+        case 66: csr_stream_kernel<16, NM, T, G, E, C><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+        case 256: csr_stream_kernel<64, NL, T, G, E, C><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+        default: csr_stream_kernel<64, NS, T, G, E, C><<<n, kBS, 0, s>>>(A, g, e, partials, skip); break;
+      }
+    };
+    if (M.col16) go(std::integral_constant<int, 1>{});
+    else go(std::integral_constant<int, 0>{});
   } else {
     csr_vector_kernel<64, T, G, E><<<M.nblocks, kBS, 0, s>>>(M.view(), g, e, partials, skip);
   }

@@ -92,6 +92,10 @@ struct CsrView {
   const int32_t* blk;  // stream variant: first row of each block, nblocks + 1
   int32_t rows;
   int32_t nblocks;
+  // Stream variant, optional: column of entry e = cbase[block] + col16[e]
+  // for every block that fits in one LDS pass (NULL: read col).
+  const uint16_t* col16;
+  const int32_t* cbase;
 };
 
 // x-gathers ---------------------------------------------------------------
@@ -249,7 +253,9 @@ constexpr int kStreamMaxRows = 1024;  // rows per stream block
 // row's products (strided, then a butterfly) and apply the epilogue.  The
 // block's dot-product partials go to partials[k * nparts + vb].  `prod` is the
 // caller's LDS buffer of at least stream_nnz<T, NB>() + kBS entries.
-template <int G, int NB, class T, class Gth, class E>
+// C16: the matrix's 2-byte column offsets are read (the caller checked that
+// A.col16 is set); -1: either, decided at run time.
+template <int G, int NB, class T, class Gth, class E, int C16 = -1>
 __device__ __forceinline__ void stream_block(const CsrView<T>& A, const Gth& gather, const E& epi, int vb,
                                              double* partials, int nparts, T* prod) {
   constexpr int NNZ = stream_nnz<T, NB>();
@@ -267,11 +273,21 @@ __device__ __forceinline__ void stream_block(const CsrView<T>& A, const Gth& gat
       // their product in the spare slots.
       int c[PER];
       T v[PER];
+      if (C16 == 1 || (C16 < 0 && A.col16)) {  // 2-byte offsets from the block's smallest column
+        const int base = A.cbase[vb];
 #pragma unroll
-      for (int k = 0; k < PER; ++k) {
-        const int e = min(e0 + k * kBS + tid, e1 - 1);
-        c[k] = __builtin_nontemporal_load(A.col + e);
-        v[k] = __builtin_nontemporal_load(A.val + e);
+        for (int k = 0; k < PER; ++k) {
+          const int e = min(e0 + k * kBS + tid, e1 - 1);
+          c[k] = base + static_cast<int>(__builtin_nontemporal_load(A.col16 + e));
+          v[k] = __builtin_nontemporal_load(A.val + e);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int e = min(e0 + k * kBS + tid, e1 - 1);
+          c[k] = __builtin_nontemporal_load(A.col + e);
+          v[k] = __builtin_nontemporal_load(A.val + e);
+        }
       }
       T x[PER];
 #pragma unroll
@@ -307,12 +323,57 @@ __device__ __forceinline__ void stream_block(const CsrView<T>& A, const Gth& gat
   if constexpr (E::K > 0) block_partials<E::K, kBS>(d, partials, nparts, vb);
 }
 
-template <int G, int NB, class T, class Gth, class E>
+// Column offsets of the stream schedule's blocks: cbase[vb] = the smallest
+// column of block vb and col16[e] = col[e] - cbase[vb] for blocks of at
+// most cap entries (longer single rows keep reading col; cbase 0); *bad = 1
+// if a block spans more than 65536 columns.  One workgroup per block.
+static __global__ void __launch_bounds__(kBS) compact_cols_kernel(const int32_t* ptr, const int32_t* col,
+                                                                  const int32_t* blk, int cap, int32_t* cbase,
+                                                                  uint16_t* col16, int32_t* bad) {
+  __shared__ int wlo[kBS / 64], whi[kBS / 64];
+  const int vb = blockIdx.x, tid = threadIdx.x;
+  const int e0 = ptr[blk[vb]], e1 = ptr[blk[vb + 1]];
+  if (e1 - e0 > cap || e1 == e0) {
+    if (tid == 0) cbase[vb] = 0;
+    return;
+  }
+  int lo = 0x7fffffff, hi = -1;
+  for (int e = e0 + tid; e < e1; e += kBS) {
+    lo = min(lo, col[e]);
+    hi = max(hi, col[e]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = min(lo, __shfl_xor(lo, off, 64));
+    hi = max(hi, __shfl_xor(hi, off, 64));
+  }
+  if ((tid & 63) == 0) {
+    wlo[tid >> 6] = lo;
+    whi[tid >> 6] = hi;
+  }
+  __syncthreads();
+  lo = wlo[0];
+  hi = whi[0];
+#pragma unroll
+  for (int w = 1; w < kBS / 64; ++w) {
+    lo = min(lo, wlo[w]);
+    hi = max(hi, whi[w]);
+  }
+  if (hi - lo > 65535) {
+    if (tid == 0) *bad = 1;
+    return;
+  }
+  if (tid == 0) cbase[vb] = lo;
+  for (int e = e0 + tid; e < e1; e += kBS) col16[e] = static_cast<uint16_t>(col[e] - lo);
+}
+
+template <int G, int NB, class T, class Gth, class E, int C16>
 static __global__ void __launch_bounds__(kBS) csr_stream_kernel(CsrView<T> A, Gth gather, E epi,
                                                          double* partials, const int* skip) {
   if (skip && *skip) return;
   __shared__ T prod[stream_nnz<T, NB>() + kBS];  // the last kBS slots take surplus lanes' products
-  stream_block<G, NB>(A, gather, epi, xcd_remap(blockIdx.x, gridDim.x), partials, gridDim.x, prod);
+  stream_block<G, NB, T, Gth, E, C16>(A, gather, epi, xcd_remap(blockIdx.x, gridDim.x), partials, gridDim.x,
+                                      prod);
 }
 
 // Vector variant: L lanes per row, kBS / L rows per workgroup.  Block vb
@@ -727,17 +788,17 @@ __global__ void __launch_bounds__(kBS) batched_spmv_kernel(const Batch<SpmvItem<
       constexpr int NS = kStreamSmallBytes, NM = kStreamMidBytes, NL = AMG_STREAM_BYTES;
       if (it.kind == 1) vector_block<64>(it.A, it.g, it.e, vb, it.partials, nb);
       else switch (it.lanes * 4 + it.bclass) {
-        case 4: stream_block<1, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 5: stream_block<1, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 6: stream_block<1, NM>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 16: stream_block<4, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 17: stream_block<4, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 18: stream_block<4, NM>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 64: stream_block<16, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 65: stream_block<16, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 66: stream_block<16, NM>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        case 256: stream_block<64, NL>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
-        default: stream_block<64, NS>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 4: stream_block<1, NL, T, Gth, E, 0>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 5: stream_block<1, NS, T, Gth, E, 0>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 6: stream_block<1, NM, T, Gth, E, 0>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 16: stream_block<4, NL, T, Gth, E, 0>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 17: stream_block<4, NS, T, Gth, E, 0>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 18: stream_block<4, NM, T, Gth, E, 0>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 64: stream_block<16, NL, T, Gth, E, 0>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 65: stream_block<16, NS, T, Gth, E, 0>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 66: stream_block<16, NM, T, Gth, E, 0>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        case 256: stream_block<64, NL, T, Gth, E, 0>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
+        default: stream_block<64, NS, T, Gth, E, 0>(it.A, it.g, it.e, vb, it.partials, nb, prod); break;
       }
     }
     __syncthreads();

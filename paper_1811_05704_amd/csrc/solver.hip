@@ -116,6 +116,9 @@ static amg_status do_setup(int64_t n, const int64_t* row_ptr, const int32_t* col
     if (device) {
       clk.enter(kPhUpload);
       S->arena = std::make_unique<DevArena>(alloc, static_cast<hipStream_t>(stream));
+      // (its column offsets are added in device_setup: the kernel that forms
+      // them would load the solve's code object here, before the side
+      // thread does so during aggregation)
       S->A0 = upload_csr<double>(*S->arena, A);
       DeviceCsrRef fine;
       fine.rows = S->A0.rows;
@@ -332,6 +335,15 @@ namespace {
 // one post-sweep of k steps: k passes over A_l for each sweep, one over P_l
 // and R_l, and each vector read or written once per kernel (level 1: f and z
 // FP64); dense coarse inverse + f, z.
+// Algorithmic bytes of one pass over a CSR matrix's entries: its values and
+// int32 column indices (row pointers are counted by the callers).  A stream
+// matrix may be read through 2-byte column offsets instead, which lowers the
+// traffic of the launch, not this count of the product's bytes.
+template <class T>
+double csr_entry_bytes(const DevCsr<T>& M) {
+  return double(M.nnz) * (sizeof(T) + 4.0);
+}
+
 template <class T>
 double cheb_vcycle_bytes(const amg_solver& S, const DevHierarchy<T>& H) {
   const double sz = sizeof(T);
@@ -342,9 +354,9 @@ double cheb_vcycle_bytes(const amg_solver& S, const DevHierarchy<T>& H) {
     const int k = L.cheb.degree;
     const double n = L.n, nc = L.nc;
     const double szf = (l == 0) ? 8.0 : sz;
-    const double passA = double(L.A.nnz) * (sz + 4) + 4.0 * (n + 1);
+    const double passA = csr_entry_bytes(L.A) + 4.0 * (n + 1);
     b += 2.0 * k * passA;                                          // pre and post sweeps
-    b += double(L.P.nnz) * (sz + 4) * 2.0 + 4.0 * (n + 1) + 4.0 * (nc + 1);  // P and R
+    b += csr_entry_bytes(L.P) + csr_entry_bytes(L.R) + 4.0 * (n + 1) + 4.0 * (nc + 1);  // P and R
     // pre-sweep from zero, residual kept
     if (l == 0) b += n * (sz + szf);                               // m, f
     else b += n * sz * ((k == 1) ? 2.0 : 3.0);                     // d0, f (, m)
@@ -383,7 +395,8 @@ double vcycle_bytes(const amg_solver& S, const DevHierarchy<T>& H) {
   for (size_t l = 0; l < H.lev.size(); ++l) {
     const DevLevel<T>& L = H.lev[l];
     const double nl = L.n, ncl = L.nc;
-    b += 2.0 * double(L.A.nnz) * (sz + 4) + 2.0 * double(L.P.nnz) * (sz + 4);
+    b += csr_entry_bytes(L.A) + csr_entry_bytes(l == 0 && L.As.val ? L.As : L.A) + csr_entry_bytes(L.P) +
+         csr_entry_bytes(L.R);
     b += 12.0 * (nl + 1) + 4.0 * (ncl + 1) + 2.0 * ncl * sz;
     b += (l == 0) ? nl * (4.0 * 8.0 + 7.0 * sz) : 11.0 * nl * sz;
   }
@@ -396,7 +409,7 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
                           double* bytes) {
   if (H.lev.empty()) throw SetupError{-1, "single-level hierarchy: no level-1 kernels to time"};
   DevLevel<T>& lv = H.lev[0];
-  const double n = lv.n, nc = lv.nc, zA = double(lv.A.nnz), zP = double(lv.P.nnz);
+  const double n = lv.n, nc = lv.nc;
   const double sz = sizeof(T);
   T* fnext = H.lev.size() > 1 ? H.lev[1].f : H.fL;
   const T* zc = H.lev.size() > 1 ? H.lev[1].z : H.zL;
@@ -482,7 +495,7 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
   if (which == 6) {
     // the whole system: p in, q out (p also the dot's second operand)
     const double na = double(S.Afull.rows);
-    *bytes = double(S.Afull.nnz) * 12.0 + 4.0 * (na + 1) + 16.0 * na;
+    *bytes = csr_entry_bytes(S.Afull) + 4.0 * (na + 1) + 16.0 * na;
     return 1000.0 * ms / reps;
   }
   if (which == 7) {
@@ -490,19 +503,23 @@ double time_level0_kernel(amg_solver& S, DevHierarchy<T>& H, int which, int reps
     // the pressure V-cycle; z_u = M_u (r_u - G z_p): G's arrays, z_p
     // gathered, M_u and r_u in, z_u out.
     const double nu = double(S.split.n_u), np = double(S.Dm.rows);
-    double b = double(S.Dm.nnz) * 12.0 + 4.0 * (np + 1) + 8.0 * nu + 16.0 * np;
+    double b = csr_entry_bytes(S.Dm) + 4.0 * (np + 1) + 8.0 * nu + 16.0 * np;
     b += vcycle_bytes(S, H);
-    b += double(S.Gs.nnz) * 12.0 + 4.0 * (nu + 1) + 8.0 * np + 24.0 * nu;
+    b += csr_entry_bytes(S.Gs) + 4.0 * (nu + 1) + 8.0 * np + 24.0 * nu;
     *bytes = b;
     return 1000.0 * ms / reps;
   }
   const double idx = 4.0;
   switch (which) {
-    case 0: *bytes = zA * (8 + idx) + idx * (n + 1) + 16 * n; break;                    // p in, q out
-    case 1: *bytes = zA * (sz + idx) + idx * (n + 1) + n * 8 + 2 * n * sz; break;       // f, m (folded into A diag(m)) in; r out
-    case 2: *bytes = zA * (sz + idx) + idx * (n + 1) + n * sz * 2 + n * 8 * 2; break;   // y, m, f in; z out
-    case 3: *bytes = zP * (sz + idx) + idx * (nc + 1) + n * sz + nc * sz; break;        // r in; f_c out
-    default: *bytes = zP * (sz + idx) + idx * (n + 1) + nc * sz + n * 8 + 2 * n * sz; break;  // z_c, f, m in; y out
+    case 0: *bytes = csr_entry_bytes(S.A0) + idx * (n + 1) + 16 * n; break;  // p in, q out
+    case 1:  // f, m (folded into A diag(m)) in; r out
+      *bytes = csr_entry_bytes(lv.As.val ? lv.As : lv.A) + idx * (n + 1) + n * 8 + 2 * n * sz;
+      break;
+    case 2: *bytes = csr_entry_bytes(lv.A) + idx * (n + 1) + n * sz * 2 + n * 8 * 2; break;  // y, m, f in; z out
+    case 3: *bytes = csr_entry_bytes(lv.R) + idx * (nc + 1) + n * sz + nc * sz; break;       // r in; f_c out
+    default:  // z_c, f, m in; y out
+      *bytes = csr_entry_bytes(lv.P) + idx * (n + 1) + nc * sz + n * 8 + 2 * n * sz;
+      break;
   }
   return 1000.0 * ms / reps;
 }
@@ -742,6 +759,7 @@ amg_status amg_csr_upload(int64_t rows, int64_t cols, const int64_t* row_ptr, co
     M.val.assign(val, val + row_ptr[rows]);
     auto m = std::make_unique<amg_matrix_s>();
     m->arena = std::make_unique<DevArena>(nullptr, static_cast<hipStream_t>(hip_stream));
+    m->arena->compact_cols = true;
     m->precision = precision;
     if (precision == AMG_FP64) m->d64 = upload_csr<double>(*m->arena, M);
     else m->d32 = upload_csr<float>(*m->arena, M);
@@ -777,6 +795,15 @@ amg_status amg_csr_kernel_info(amg_matrix m, int32_t* kind, int32_t* lanes, int3
       const int bc = f64 ? m->d64.bclass : m->d32.bclass;
       *block_bytes = k != 0 ? 0 : bc == 1 ? kStreamSmallBytes : bc == 2 ? kStreamMidBytes : AMG_STREAM_BYTES;
     }
+    return AMG_OK;
+  });
+}
+
+amg_status amg_csr_column_bytes(amg_matrix m, int32_t* bytes) {
+  return guarded([&]() -> amg_status {
+    if (!m || !bytes) throw SetupError{-1, "NULL argument"};
+    const bool c16 = m->precision == AMG_FP64 ? m->d64.col16 != nullptr : m->d32.col16 != nullptr;
+    *bytes = c16 ? 2 : 4;
     return AMG_OK;
   });
 }

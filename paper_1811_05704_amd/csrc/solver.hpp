@@ -378,6 +378,7 @@ DevCsr<T> device_copy_csr(DevArena& ar, const DeviceCsrRef& src, const Csr& M) {
   d.bclass = sc.bclass;
   d.nblocks = sc.nblocks;
   if (sc.kind == 0) d.blk = ar.upload(sc.blk.data(), sc.blk.size());
+  attach_compact_cols(ar, d);
   return d;
 }
 
@@ -427,6 +428,7 @@ inline void upload_levels(amg_solver& S, DevHierarchy<T>& H, const SetupAccel* a
         d.A.bclass = sc.bclass;
         d.A.nblocks = sc.nblocks;
         d.A.blk = sc.kind == 0 ? ar.upload(sc.blk.data(), sc.blk.size()) : nullptr;
+        attach_compact_cols(ar, d.A);
       }
     } else {
       d.A = (dev && ref.A.val) ? device_copy_csr<T>(ar, ref.A, hl.A) : upload_csr<T>(ar, hl.A);
@@ -946,6 +948,8 @@ inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t 
   if (!S.arena) S.arena = std::make_unique<DevArena>(alloc, s);
   if (opts.standalone) AMG_HIP(hipStreamCreateWithFlags(&S.cap_stream, hipStreamNonBlocking));
   DevArena& ar = *S.arena;
+  // served solves keep int32 columns (their footprint is planned before placement)
+  ar.compact_cols = opts.standalone;
   // the coarsest operator in scalar form; upload_levels sizes f_L, z_L by nL
   const Csr AL = S.block ? bsr_to_csr(S.bhost.levels.back().A) : S.host.levels.back().A;
   S.nL = static_cast<int32_t>(AL.rows);
@@ -961,6 +965,7 @@ inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t 
     const HostLevel& fine = S.host.levels[0];
     S.n = fine.A.rows;
     if (!S.A0.val) S.A0 = upload_csr<double>(ar, fine.A);  // unless uploaded before the setup steps
+    else if (!S.A0.col16) attach_compact_cols(ar, S.A0);
     if (S.prm.precision == AMG_MIXED) upload_levels<float>(S, S.h32, accel);
     else upload_levels<double>(S, S.h64, accel);
     if (S.schur) {

@@ -92,6 +92,11 @@ def test_spmv_matches_cpu(name, rows, cols, gen, precision):
             assert info["block_bytes"] == 8192
         else:
             assert info["block_bytes"] == 16384
+    # 2-byte column offsets unless a stream block spans more than 65536 columns
+    if info["kind"] == "stream" and cols <= 65536:
+        assert info["column_bytes"] == 2
+    if info["kind"] == "vector" or name.startswith("large_blocks"):  # random columns over > 65536: int32
+        assert info["column_bytes"] == 4
     # worst case grows with the row length (per-lane partial sums + a tree)
     tol = 5e-14 if precision == "fp64" else 2e-5
     err = np.abs(y - yr)
@@ -119,6 +124,7 @@ def test_spmv_full_size_poisson150_sampled_rows():
     A = problems.poisson3d(150)
     M = amg.DeviceMatrix(A.n, A.n, A.row_ptr, A.col, A.val, precision="fp64")
     assert M.kernel_info()["kind"] == "stream"
+    assert M.kernel_info()["column_bytes"] == 2  # a block of rows spans at most 2 N^2 + 1 columns
     x = np.random.default_rng(9).random(A.n)
     announce("spmv poisson 150^3 full size")
     y = M.spmv(torch.tensor(x, device="cuda")).cpu().numpy()
