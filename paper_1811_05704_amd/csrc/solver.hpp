@@ -666,7 +666,7 @@ inline void build_graph(amg_solver& S) {
   try {
     for (int it = 0; it < S.prm.check_every; ++it) enqueue_iteration(S, S.cap_stream);
   } catch (...) {
-    hipGraph_t g;
+    hipGraph_t g = nullptr;
     (void)hipStreamEndCapture(S.cap_stream, &g);
     if (g) (void)hipGraphDestroy(g);
     throw;
@@ -748,27 +748,41 @@ inline void build_gm_graphs(amg_solver& S) {
   if (!S.gm_execs.empty()) return;
   const int m = S.prm.gmres_m, ce = S.prm.check_every;
   const int groups = (m + ce - 1) / ce;
-  for (int g = 0; g <= groups; ++g) {
-    AMG_HIP(hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal));
-    try {
-      if (g < groups) {
-        for (int j = g * ce; j < std::min(m, (g + 1) * ce); ++j) enqueue_gm_step(S, j, S.cap_stream);
-      } else {
-        enqueue_gm_cycle_end(S, S.cap_stream);
+  // built into local lists and kept only when every graph was made
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> execs;
+  auto drop = [&] {
+    for (auto e : execs) (void)hipGraphExecDestroy(e);
+    for (auto g : graphs) (void)hipGraphDestroy(g);
+  };
+  try {
+    for (int g = 0; g <= groups; ++g) {
+      AMG_HIP(hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        if (g < groups) {
+          for (int j = g * ce; j < std::min(m, (g + 1) * ce); ++j) enqueue_gm_step(S, j, S.cap_stream);
+        } else {
+          enqueue_gm_cycle_end(S, S.cap_stream);
+        }
+      } catch (...) {
+        hipGraph_t gr = nullptr;
+        (void)hipStreamEndCapture(S.cap_stream, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
       }
-    } catch (...) {
-      hipGraph_t gr;
-      (void)hipStreamEndCapture(S.cap_stream, &gr);
-      if (gr) (void)hipGraphDestroy(gr);
-      throw;
+      hipGraph_t gr = nullptr;
+      AMG_HIP(hipStreamEndCapture(S.cap_stream, &gr));
+      graphs.push_back(gr);
+      hipGraphExec_t ex = nullptr;
+      AMG_HIP(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+      execs.push_back(ex);
     }
-    hipGraph_t gr = nullptr;
-    AMG_HIP(hipStreamEndCapture(S.cap_stream, &gr));
-    S.gm_graphs.push_back(gr);
-    hipGraphExec_t ex = nullptr;
-    AMG_HIP(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
-    S.gm_execs.push_back(ex);
+  } catch (...) {
+    drop();
+    throw;
   }
+  S.gm_graphs = std::move(graphs);
+  S.gm_execs = std::move(execs);
 }
 
 // The whole GMRES solve; the host polls every check_every Arnoldi steps and
@@ -938,6 +952,15 @@ inline void drop_device_state(amg_solver& S) {
   S.Afull = S.Dm = S.Gs = DevCsr<double>{};
   S.mu = S.rp = nullptr;
   S.perm = nullptr;
+  // captured graphs hold pointers into the released memory
+  if (S.iter_exec) (void)hipGraphExecDestroy(S.iter_exec);
+  if (S.iter_graph) (void)hipGraphDestroy(S.iter_graph);
+  S.iter_exec = nullptr;
+  S.iter_graph = nullptr;
+  for (auto e : S.gm_execs) (void)hipGraphExecDestroy(e);
+  for (auto g : S.gm_graphs) (void)hipGraphDestroy(g);
+  S.gm_execs.clear();
+  S.gm_graphs.clear();
 }
 
 // `accel`: the setup steps' accelerator, whose device copies of the levels
