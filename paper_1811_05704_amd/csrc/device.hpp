@@ -260,31 +260,6 @@ DevCsr<T> upload_csr(DevArena& ar, const Csr& M, int force_kind = -1) {
   return d;
 }
 
-// The same matrix in another value type, sharing the row pointers and column
-// indices of an uploaded copy (same pattern, so only the values and the
-// schedule, which depends on the value size, are stored again).
-template <class T, class U>
-DevCsr<T> upload_values_like(DevArena& ar, const DevCsr<U>& like, const Csr& M) {
-  DevCsr<T> d;
-  d.rows = static_cast<int32_t>(M.rows);
-  d.cols = static_cast<int32_t>(M.cols);
-  d.nnz = M.nnz();
-  d.ptr = like.ptr;
-  d.col = like.col;
-  const size_t nz = M.col.size();
-  std::vector<T> v(nz);
-  for (size_t k = 0; k < nz; ++k) v[k] = static_cast<T>(M.val[k]);  // FP32: round to nearest
-  d.val = ar.upload(v.data(), nz);
-  Schedule s = make_schedule<T>(M, -1);
-  d.kind = s.kind;
-  d.lanes = s.lanes;
-  d.bclass = s.bclass;
-  d.nblocks = s.nblocks;
-  if (s.kind == 0) d.blk = ar.upload(s.blk.data(), s.blk.size());
-  attach_compact_cols(ar, d);
-  return d;
-}
-
 // Launch y-epilogue SpMV with the matrix's schedule; returns the grid size
 // (= number of partials written when E::K > 0).
 template <class T, class G, class E>
