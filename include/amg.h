@@ -164,8 +164,8 @@ amg_status amg_setup_host(int64_t n, const int64_t* row_ptr, const int32_t* col,
  * Frobenius norms, aggregation over nodes, identity tentative blocks,
  * block-diagonal filtered matrix and damping, block Galerkin products, and
  * block SPAI-0 (the block-diagonal minimiser of ||I - M A||_F) or block
- * Jacobi smoothing, the post-sweep applying M^T.  Supported: solver AMG_CG or
- * AMG_BICGSTAB, relax AMG_SPAI0 or AMG_JACOBI, npre = npost = 1, precision
+ * Jacobi smoothing, the post-sweep applying M^T.  Supported: solver AMG_CG,
+ * AMG_BICGSTAB or AMG_GMRES, relax AMG_SPAI0 or AMG_JACOBI, npre = npost = 1, precision
  * AMG_FP64 or AMG_MIXED; anything else is AMG_ERR_INVALID_ARG.
  * coarse_enough counts unknowns (4 nb).  Errors as for amg_setup; a singular
  * diagonal block gives AMG_ERR_ZERO_DIAG.  amg_level_info then reports block

@@ -400,8 +400,9 @@ def vcycle_fp32(h: BlockHierarchy, f: np.ndarray) -> np.ndarray:
 
 def solve(A: Bsr, f: np.ndarray, params: sa_amg.Params | None = None, mixed: bool = False,
           h: BlockHierarchy | None = None):
-    """AMG-preconditioned CG or BiCGStab on the scalar form of A; the Krylov
-    methods are the scalar oracle's, one block V-cycle per preconditioning step."""
+    """AMG-preconditioned CG, BiCGStab or flexible GMRES on the scalar form of
+    A; the Krylov methods are the scalar oracle's, one block V-cycle per
+    preconditioning step."""
     prm = params or sa_amg.Params()
     if h is None:
         h = setup(A, prm)
@@ -414,6 +415,8 @@ def solve(A: Bsr, f: np.ndarray, params: sa_amg.Params | None = None, mixed: boo
         x, info = sa_amg.pcg(As, f, precond, prm.tol, prm.max_iter)
     elif prm.solver == "bicgstab":
         x, info = sa_amg.bicgstab(As, f, precond, prm.tol, prm.max_iter)
+    elif prm.solver == "gmres":
+        x, info = sa_amg.gmres(As, f, precond, m=prm.gmres_m, tol=prm.tol, max_iter=prm.max_iter)
     else:
-        raise ValueError("block values support cg and bicgstab")
+        raise ValueError("block values support cg, bicgstab and gmres")
     return x, info, h

@@ -158,8 +158,8 @@ inline void check_params(const amg_params& p) {
 // Settings the block path implements: CG or BiCGStab, SPAI-0 or Jacobi
 // blocks, one pre- and one post-sweep.
 inline void check_block_params(const amg_params& p) {
-  if (p.solver != AMG_CG && p.solver != AMG_BICGSTAB)
-    throw SetupError{-1, "block values: solver must be AMG_CG or AMG_BICGSTAB"};
+  if (p.solver != AMG_CG && p.solver != AMG_BICGSTAB && p.solver != AMG_GMRES)
+    throw SetupError{-1, "block values: solver must be AMG_CG, AMG_BICGSTAB or AMG_GMRES"};
   if (p.relax != AMG_SPAI0 && p.relax != AMG_JACOBI)
     throw SetupError{-1, "block values: relax must be AMG_SPAI0 or AMG_JACOBI"};
   if (p.npre != 1 || p.npost != 1) throw SetupError{-1, "block values: npre and npost must be 1"};
@@ -686,8 +686,8 @@ inline KState poll(amg_solver& S, hipStream_t s) {
 // r = f - A x and the opening of a cycle (first: the initial residual).
 inline void enqueue_gm_cycle_start(amg_solver& S, bool first, hipStream_t s) {
   const int n = static_cast<int>(S.n);
-  int nb = launch_spmv(krylov_op(S), GatherX<double, double>{S.x}, EpiResidNorms{S.r, S.f}, S.partials,
-                       first ? nullptr : skip_of(S), s);
+  int nb = outer_spmv(S, GatherX<double, double>{S.x}, EpiResidNorms{S.r, S.f}, S.partials,
+                      first ? nullptr : skip_of(S), s);
   gm_start_state_kernel<<<1, kFinBS, 0, s>>>(S.partials, nb, S.st, S.gm, first ? 1 : 0);
   AMG_LAUNCHED();
   gm_first_vector_kernel<<<vec_blocks(n), kVecBS, 0, s>>>(n, S.gmV, S.r, S.gm);
@@ -704,7 +704,7 @@ inline void enqueue_gm_step(amg_solver& S, int j, hipStream_t s) {
   double* w = S.q;
   const int* stop = &S.gm->stop;
   with_vcycle(S, [&](auto& V) { return V.template run<0>(vj, zj, S.partials, stop, s); });
-  launch_spmv(krylov_op(S), GatherX<double, double>{zj}, EpiStore<double, double>{w}, nullptr, stop, s);
+  outer_spmv(S, GatherX<double, double>{zj}, EpiStore<double, double>{w}, nullptr, stop, s);
   const int nb = S.gm_nb;
   for (int pass = 0; pass < 2; ++pass) {
     gm_dots_kernel<<<dim3(nb, j + 1), kVecBS, 0, s>>>(n, S.gmV, ld, w, S.gm_partials, S.gm);
@@ -844,8 +844,7 @@ inline amg_status run_solve(amg_solver& S, const double* f_dev, double* u_dev, h
     k = run_gmres(S, s, &cycles);
     restarts = std::max(cycles - 1, 0);
     if (k.done != kZeroRhs) {
-      int nb = launch_spmv(krylov_op(S), GatherX<double, double>{S.x}, EpiResidNorms{S.tmp, S.f}, S.partials,
-                           nullptr, s);
+      int nb = outer_spmv(S, GatherX<double, double>{S.x}, EpiResidNorms{S.tmp, S.f}, S.partials, nullptr, s);
       fin(S, 2, nb, kFinTrue, s);
       k = poll(S, s);
     }

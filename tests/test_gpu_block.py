@@ -52,6 +52,10 @@ def _case(name):
         g = problems.gaussian_field(16, 1.0, 8.0, 2)
         return (problems.coupled_diffusion3d(16, g, velocity=(50.0, 25.0, 12.5)),
                 {"relax": "jacobi", "solver": "bicgstab", "coarse_enough": 400})
+    if name == "convection16-gmres":
+        g = problems.gaussian_field(16, 1.0, 8.0, 2)
+        return (problems.coupled_diffusion3d(16, g, velocity=(50.0, 25.0, 12.5)),
+                {"relax": "jacobi", "solver": "gmres", "coarse_enough": 400})
     if name == "decoupled16":
         return problems.decoupled_diffusion3d(16, problems.gaussian_field(16, 1.0, 8.0, 3)), {"coarse_enough": 400}
     if name == "coupled32":
@@ -105,7 +109,8 @@ def test_block_vcycle_mixed_matches_fp32_oracle(name):
 
 SOLVE_CASES = [("coupled12", "fp64"), ("coupled16-3lev", "fp64"), ("coupled16-3lev", "mixed"),
                ("coupled20-jacobi", "fp64"), ("convection16", "fp64"), ("convection16", "mixed"),
-               ("coupled32", "fp64"), ("coupled32", "mixed")]
+               ("coupled32", "fp64"), ("coupled32", "mixed"),
+               ("convection16-gmres", "fp64"), ("convection16-gmres", "mixed")]
 
 
 @pytest.mark.parametrize("name,precision", SOLVE_CASES)
