@@ -165,8 +165,11 @@ amg_status amg_setup_host(int64_t n, const int64_t* row_ptr, const int32_t* col,
  * block-diagonal filtered matrix and damping, block Galerkin products, and
  * block SPAI-0 (the block-diagonal minimiser of ||I - M A||_F) or block
  * Jacobi smoothing, the post-sweep applying M^T.  Supported: solver AMG_CG,
- * AMG_BICGSTAB or AMG_GMRES, relax AMG_SPAI0 or AMG_JACOBI, npre = npost = 1, precision
- * AMG_FP64 or AMG_MIXED; anything else is AMG_ERR_INVALID_ARG.
+ * AMG_BICGSTAB or AMG_GMRES, relax AMG_SPAI0 or AMG_JACOBI, npre and npost in
+ * [0, 16] (one each runs fused kernels; other counts run one product per
+ * sweep), precision AMG_FP64 or AMG_MIXED; anything else is
+ * AMG_ERR_INVALID_ARG.  amg_time_kernel (which = 5) reports block bytes for
+ * npre = npost = 1 only and refuses other counts.
  * coarse_enough counts unknowns (4 nb).  Errors as for amg_setup; a singular
  * diagonal block gives AMG_ERR_ZERO_DIAG.  amg_level_info then reports block
  * rows and stored blocks; amg_get_level_csr, amg_get_smoother and the

@@ -1,7 +1,7 @@
 // Block-value hierarchy on the device and its V-cycle (section 2, "AMG
 // solve", with the 4 x 4 value type of section 3).
 //
-// Per level l < L (zero initial guess, one pre- and one post-sweep of the
+// Per level l < L (zero initial guess; with one pre- and one post-sweep of the
 // block smoother M; post-sweeps apply M^T, the adjoint of the pre-sweep):
 //   r_l     = f_l - A_l (M_l f_l)     level 1: (A_1 M_1) f_1 with the block
 //                                      products A_ij M_j formed once at setup
@@ -9,6 +9,9 @@
 //   ... z_L = A_L^-1 f_L (dense inverse of the scalar coarse matrix, FP64) ...
 //   y_l     = M_l f_l + P_l z_{l+1}    prolongation + correction
 //   z_l     = y_l + M_l^T (f_l - A_l y_l)   post-sweep (level 1 of PCG: r . z)
+// Other sweep counts (0 .. 16 each) take an unfused form: the pre-sweeps
+// z <- z + M (f - A z) from z = M f stored in a ping-pong pair, the residual
+// of the last, and as many post-sweeps, the last writing the level's output.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -97,6 +100,46 @@ struct DevBlockLevel {
   T* r = nullptr;
   T* y = nullptr;
   T* z = nullptr;             // levels > 1: output
+  T* zp[2] = {nullptr, nullptr};  // pre-sweep iterates (sweep counts other than 1 / 1)
+  T* t = nullptr;                 // post-sweep ping-pong partner (npost > 1)
+};
+
+// Level 1 first pre-sweep from zero, z = M f, one thread per scalar row
+// (4 x 4 row times 4-vector in column order, as the restriction's M f).
+template <class T, class TF>
+static __global__ void __launch_bounds__(kVecBS) bscale_kernel(int n, T* z, const T* M, const TF* f,
+                                                               const int* skip) {
+  if (skip && *skip) return;
+  const int stride = gridDim.x * kVecBS;
+  for (int k = blockIdx.x * kVecBS + threadIdx.x; k < n; k += stride) {
+    const int i = k / kB, q = k % kB;
+    const T* m = M + static_cast<int64_t>(i) * kB2 + q * kB;
+    const TF* fi = f + kB * i;
+    T v = m[0] * static_cast<T>(fi[0]);
+    v = v + m[1] * static_cast<T>(fi[1]);
+    v = v + m[2] * static_cast<T>(fi[2]);
+    v = v + m[3] * static_cast<T>(fi[3]);
+    z[k] = v;
+  }
+}
+
+// One more pre-sweep: out = z + M (f - A z), the row of M_i in column order.
+template <class T, class TF>
+struct EpiBPre {
+  static constexpr int K = 0;
+  T* out;
+  const T* z;
+  const T* M;
+  const TF* f;
+  __device__ __forceinline__ void operator()(int i, int q, const T* s4, double*) const {
+    const T* m = M + static_cast<int64_t>(i) * kB2 + q * kB;
+    const TF* fi = f + kB * i;
+    T v = m[0] * (static_cast<T>(fi[0]) - s4[0]);
+    v = v + m[1] * (static_cast<T>(fi[1]) - s4[1]);
+    v = v + m[2] * (static_cast<T>(fi[2]) - s4[2]);
+    v = v + m[3] * (static_cast<T>(fi[3]) - s4[3]);
+    out[kB * i + q] = z[kB * i + q] + v;
+  }
 };
 
 template <class T>
@@ -109,7 +152,8 @@ struct DevBlockHierarchy {
 template <class T>
 class BlockVcycle {
  public:
-  BlockVcycle(DevBlockHierarchy<T>* h, const double* Ainv, int32_t nL) : h_(h), Ainv_(Ainv), nL_(nL) {}
+  BlockVcycle(DevBlockHierarchy<T>* h, const double* Ainv, int32_t nL, int npre = 1, int npost = 1)
+      : h_(h), Ainv_(Ainv), nL_(nL), npre_(npre), npost_(npost) {}
 
   // z0 = V(f0); f0, z0 double[4 nb].  With DOT, writes the partials of
   // f0 . z0 and returns their count.
@@ -127,6 +171,7 @@ class BlockVcycle {
       }
       return 0;
     }
+    if (npre_ != 1 || npost_ != 1) return run_sweeps<DOT>(f0, z0, partials, skip, s);
     for (int l = 0; l < L - 1; ++l) {
       DevBlockLevel<T>& lv = h_->lev[l];
       DevBlockLevel<T>* next = (l + 1 < L - 1) ? &h_->lev[l + 1] : nullptr;
@@ -160,16 +205,107 @@ class BlockVcycle {
   }
 
  private:
+  // The buffer holding level l's last pre-sweep (null with no pre-sweep):
+  // the first is M f (level 1: bscale_kernel; deeper levels: written by the
+  // restriction into mf), then each further sweep goes to the other of zp.
+  T* pre_result(const DevBlockLevel<T>& lv, int l) const {
+    if (npre_ == 0) return nullptr;
+    T* cur = (l == 0) ? lv.zp[0] : lv.mf;
+    for (int k = 1; k < npre_; ++k) cur = (cur == lv.zp[0]) ? lv.zp[1] : lv.zp[0];
+    return cur;
+  }
+
+  template <class TF>
+  void down_sweeps(DevBlockLevel<T>& lv, int l, const TF* f, DevBlockLevel<T>* next, const int* skip,
+                   hipStream_t s) {
+    auto restrict_from = [&](auto gather) {
+      if (next && npre_ > 0)
+        launch_bsr(lv.R, gather, EpiBRestrict<T>{next->f, next->mf, next->M}, nullptr, skip, s);
+      else
+        launch_bsr(lv.R, gather, PerRow<EpiStore<T, T>>{{next ? next->f : h_->fL}}, nullptr, skip, s);
+    };
+    if (npre_ == 0) {
+      restrict_from(GatherX<T, TF>{f});
+      return;
+    }
+    T* cur = lv.mf;
+    if (l == 0) {
+      const int n = kB * lv.nb;
+      bscale_kernel<T, TF><<<vec_blocks(n), kVecBS, 0, s>>>(n, lv.zp[0], lv.M, f, skip);
+      AMG_LAUNCHED();
+      cur = lv.zp[0];
+    }
+    for (int k = 1; k < npre_; ++k) {
+      T* dst = (cur == lv.zp[0]) ? lv.zp[1] : lv.zp[0];
+      launch_bsr(lv.A, GatherX<T, T>{cur}, EpiBPre<T, TF>{dst, cur, lv.M, f}, nullptr, skip, s);
+      cur = dst;
+    }
+    launch_bsr(lv.A, GatherX<T, T>{cur}, PerRow<EpiResid<T, TF>>{{lv.r, f}}, nullptr, skip, s);
+    restrict_from(GatherX<T, T>{lv.r});
+  }
+
+  template <class TF, class TZ, int DOT>
+  int up_sweeps(DevBlockLevel<T>& lv, int l, const TF* f, const T* zc, TZ* zout, double* partials,
+                const int* skip, hipStream_t s) {
+    if (npre_ == 0)
+      launch_bsr(lv.P, GatherX<T, T>{zc}, PerRow<EpiProlong<T, T, 0>>{{lv.y, nullptr, nullptr, nullptr}}, nullptr,
+                 skip, s);
+    else
+      launch_bsr(lv.P, GatherX<T, T>{zc}, PerRow<EpiProlong<T, T, 2>>{{lv.y, nullptr, nullptr, pre_result(lv, l)}},
+                 nullptr, skip, s);
+    if (npost_ == 0) {
+      const int n = kB * lv.nb, nb = vec_blocks(n);
+      copy_dot_kernel<T, TF, TZ, DOT><<<nb, kVecBS, 0, s>>>(n, zout, lv.y, f, partials, skip);
+      AMG_LAUNCHED();
+      return DOT ? nb : 0;
+    }
+    T* cur = lv.y;
+    T* other = lv.t;
+    int nparts = 0;
+    for (int k = 0; k < npost_; ++k) {
+      if (k == npost_ - 1) {
+        nparts = launch_bsr(lv.A, GatherX<T, T>{cur}, EpiBSmooth<T, TF, TZ, DOT>{zout, cur, lv.M, f}, partials,
+                            skip, s);
+      } else {
+        launch_bsr(lv.A, GatherX<T, T>{cur}, EpiBSmooth<T, TF, T, 0>{other, cur, lv.M, f}, nullptr, skip, s);
+        std::swap(cur, other);
+      }
+    }
+    return DOT ? nparts : 0;
+  }
+
+  template <int DOT>
+  int run_sweeps(const double* f0, double* z0, double* partials, const int* skip, hipStream_t s) {
+    const int L = static_cast<int>(h_->lev.size()) + 1;
+    for (int l = 0; l < L - 1; ++l) {
+      DevBlockLevel<T>& lv = h_->lev[l];
+      DevBlockLevel<T>* next = (l + 1 < L - 1) ? &h_->lev[l + 1] : nullptr;
+      if (l == 0) down_sweeps<double>(lv, l, f0, next, skip, s);
+      else down_sweeps<T>(lv, l, lv.f, next, skip, s);
+    }
+    coarse_gemv_kernel<T, T><<<nL_, kBS, 0, s>>>(nL_, Ainv_, h_->fL, h_->zL, skip);
+    AMG_LAUNCHED();
+    int nparts = 0;
+    for (int l = L - 2; l >= 0; --l) {
+      DevBlockLevel<T>& lv = h_->lev[l];
+      const T* zc = (l + 1 < L - 1) ? h_->lev[l + 1].z : h_->zL;
+      if (l == 0) nparts = up_sweeps<double, double, DOT>(lv, l, f0, zc, z0, partials, skip, s);
+      else up_sweeps<T, T, 0>(lv, l, lv.f, zc, lv.z, partials, skip, s);
+    }
+    return DOT ? nparts : 0;
+  }
+
   DevBlockHierarchy<T>* h_;
   const double* Ainv_;
   int32_t nL_;
+  int npre_, npost_;
 };
 
 // Level matrices, smoother blocks and vectors of a block hierarchy.  The
 // FP64 fine operator B0 (the Krylov loop's) shares its pattern with level 1.
 template <class T>
 inline void upload_block_levels(DevArena& ar, const BlockHierarchy& H, const DevBsr<double>& B0,
-                                DevBlockHierarchy<T>& D) {
+                                DevBlockHierarchy<T>& D, int npre = 1, int npost = 1) {
   const int L = static_cast<int>(H.levels.size());
   for (int l = 0; l < L - 1; ++l) {
     const BlockLevel& hl = H.levels[l];
@@ -214,6 +350,11 @@ inline void upload_block_levels(DevArena& ar, const BlockHierarchy& H, const Dev
     }
     d.r = ar.get<T>(n);
     d.y = ar.get<T>(n);
+    if ((npre != 1 || npost != 1) && npre > 0) {
+      d.zp[0] = ar.get<T>(n);
+      d.zp[1] = ar.get<T>(n);
+    }
+    if (npost > 1) d.t = ar.get<T>(n);
     D.lev.push_back(d);
   }
   const int64_t nL = int64_t(kB) * H.levels.back().A.rows;

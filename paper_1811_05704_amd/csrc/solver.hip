@@ -542,7 +542,7 @@ double time_block_vcycle(amg_solver& S, DevBlockHierarchy<T>& H, int reps, hipSt
   hipGraphExec_t ge = nullptr;
   AMG_HIP(hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal));
   try {
-    BlockVcycle<T> V(&H, S.Ainv, S.nL);
+    BlockVcycle<T> V(&H, S.Ainv, S.nL, S.prm.npre, S.prm.npost);
     for (int k = 0; k < reps; ++k) V.template run<0>(S.r, S.z, S.partials, nullptr, S.cap_stream);
   } catch (...) {
     (void)hipStreamEndCapture(S.cap_stream, &g);
@@ -598,6 +598,8 @@ amg_status amg_time_kernel(amg_handle h, int32_t which, int32_t reps, void* hip_
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     if (h->block) {
       if (which != 5) throw SetupError{-1, "block-value handles time the whole V-cycle only (which = 5)"};
+      if (h->prm.npre != 1 || h->prm.npost != 1)
+        throw SetupError{-1, "block V-cycle timing counts bytes for npre = npost = 1 only"};
       if (h->prm.precision == AMG_MIXED) *avg_us = time_block_vcycle<float>(*h, h->bh32, reps, s, bytes);
       else *avg_us = time_block_vcycle<double>(*h, h->bh64, reps, s, bytes);
       return AMG_OK;

@@ -156,13 +156,12 @@ inline void check_params(const amg_params& p) {
 }
 
 // Settings the block path implements: CG or BiCGStab, SPAI-0 or Jacobi
-// blocks, one pre- and one post-sweep.
+// blocks, 0 .. 16 pre- and post-sweeps (checked with the scalar settings).
 inline void check_block_params(const amg_params& p) {
   if (p.solver != AMG_CG && p.solver != AMG_BICGSTAB && p.solver != AMG_GMRES)
     throw SetupError{-1, "block values: solver must be AMG_CG, AMG_BICGSTAB or AMG_GMRES"};
   if (p.relax != AMG_SPAI0 && p.relax != AMG_JACOBI)
     throw SetupError{-1, "block values: relax must be AMG_SPAI0 or AMG_JACOBI"};
-  if (p.npre != 1 || p.npost != 1) throw SetupError{-1, "block values: npre and npost must be 1"};
 }
 
 inline Csr to_csr(int64_t n, const int64_t* ptr, const int32_t* col, const double* val) {
@@ -563,10 +562,10 @@ inline auto with_vcycle(amg_solver& S, F fn) {
   }
   if (S.block) {
     if (S.prm.precision == AMG_MIXED) {
-      BlockVcycle<float> V(&S.bh32, S.Ainv, S.nL);
+      BlockVcycle<float> V(&S.bh32, S.Ainv, S.nL, S.prm.npre, S.prm.npost);
       return fn(V);
     }
-    BlockVcycle<double> V(&S.bh64, S.Ainv, S.nL);
+    BlockVcycle<double> V(&S.bh64, S.Ainv, S.nL, S.prm.npre, S.prm.npost);
     return fn(V);
   }
   if (S.prm.precision == AMG_MIXED) {
@@ -981,8 +980,8 @@ inline void device_setup(amg_solver& S, const amg_allocator* alloc, hipStream_t 
     const Bsr& fine = S.bhost.levels[0].A;
     S.n = int64_t(kB) * fine.rows;
     S.B0 = upload_bsr<double>(ar, fine);
-    if (S.prm.precision == AMG_MIXED) upload_block_levels<float>(ar, S.bhost, S.B0, S.bh32);
-    else upload_block_levels<double>(ar, S.bhost, S.B0, S.bh64);
+    if (S.prm.precision == AMG_MIXED) upload_block_levels<float>(ar, S.bhost, S.B0, S.bh32, S.prm.npre, S.prm.npost);
+    else upload_block_levels<double>(ar, S.bhost, S.B0, S.bh64, S.prm.npre, S.prm.npost);
   } else {
     const HostLevel& fine = S.host.levels[0];
     S.n = fine.A.rows;

@@ -56,6 +56,15 @@ def _case(name):
         g = problems.gaussian_field(16, 1.0, 8.0, 2)
         return (problems.coupled_diffusion3d(16, g, velocity=(50.0, 25.0, 12.5)),
                 {"relax": "jacobi", "solver": "gmres", "coarse_enough": 400})
+    if name.startswith("coupled16-sweeps"):
+        # sweep counts other than one pre- and one post-sweep (the unfused form)
+        npre, npost = int(name[-2]), int(name[-1])
+        return (problems.coupled_diffusion3d(16, problems.gaussian_field(16, 1.0, 8.0, 2)),
+                {"coarse_enough": 400, "npre": npre, "npost": npost, "solver": "bicgstab"})
+    if name == "convection16-sweeps21":
+        g = problems.gaussian_field(16, 1.0, 8.0, 2)
+        return (problems.coupled_diffusion3d(16, g, velocity=(50.0, 25.0, 12.5)),
+                {"relax": "jacobi", "solver": "gmres", "coarse_enough": 400, "npre": 2, "npost": 1})
     if name == "decoupled16":
         return problems.decoupled_diffusion3d(16, problems.gaussian_field(16, 1.0, 8.0, 3)), {"coarse_enough": 400}
     if name == "coupled32":
@@ -64,10 +73,13 @@ def _case(name):
 
 
 def _oracle_params(kw):
-    return sa.Params(**{k: v for k, v in kw.items() if k in ("relax", "solver", "coarse_enough")})
+    return sa.Params(**{k: v for k, v in kw.items() if k in ("relax", "solver", "coarse_enough", "npre", "npost")})
 
 
-VCYCLE_CASES = ["coupled12", "coupled16-3lev", "coupled20-jacobi", "convection16", "decoupled16", "coupled32"]
+SWEEP_CASES = ["coupled16-sweeps22", "coupled16-sweeps03", "coupled16-sweeps10", "coupled16-sweeps32",
+               "convection16-sweeps21"]
+VCYCLE_CASES = ["coupled12", "coupled16-3lev", "coupled20-jacobi", "convection16", "decoupled16",
+                "coupled32"] + SWEEP_CASES
 
 
 @pytest.mark.parametrize("name", VCYCLE_CASES)
@@ -95,11 +107,12 @@ def test_block_vcycle_mixed_matches_fp32_oracle(name):
     r = np.random.default_rng(42).standard_normal(B.n)
     z = host(S.vcycle(dev(r)))
     z32, z64 = ba.vcycle_fp32(h, r), ba.vcycle(h, r)
-    # FP32 rounding bound: p = 4 products per level (pre-sweep, restriction,
-    # prolongation, post-sweep), each rounding to a few u; a 4 x 4 smoother
-    # block adds a 4-term product per row (counted as one more product)
+    # FP32 rounding bound: per level one product per sweep, the restriction
+    # and the prolongation, each rounding to a few u; a 4 x 4 smoother block
+    # adds a 4-term product per row to each sweep (counted as one more
+    # product): 2 (npre + npost) + 2 products, 6 with one sweep each
     u = 2.0 ** -24
-    tol = 2.0 * 6 * S.nlevels * u
+    tol = 2.0 * (2 * (kw.get("npre", 1) + kw.get("npost", 1)) + 2) * S.nlevels * u
     e32, m32, e64 = rel_err(z, z32), max_rel(z, z32), rel_err(z, z64)
     print(f"[block vcycle mixed] {name}: vs FP32 oracle rel {e32:.2e} max {m32:.2e}; vs FP64 oracle {e64:.2e}; "
           f"bound {tol:.2e}", flush=True)
@@ -110,7 +123,9 @@ def test_block_vcycle_mixed_matches_fp32_oracle(name):
 SOLVE_CASES = [("coupled12", "fp64"), ("coupled16-3lev", "fp64"), ("coupled16-3lev", "mixed"),
                ("coupled20-jacobi", "fp64"), ("convection16", "fp64"), ("convection16", "mixed"),
                ("coupled32", "fp64"), ("coupled32", "mixed"),
-               ("convection16-gmres", "fp64"), ("convection16-gmres", "mixed")]
+               ("convection16-gmres", "fp64"), ("convection16-gmres", "mixed"),
+               ("coupled16-sweeps22", "fp64"), ("coupled16-sweeps03", "mixed"), ("coupled16-sweeps32", "mixed"),
+               ("convection16-sweeps21", "fp64"), ("convection16-sweeps21", "mixed")]
 
 
 @pytest.mark.parametrize("name,precision", SOLVE_CASES)
@@ -159,6 +174,12 @@ def test_block_vcycle_timing_reports_bytes():
     assert us > 0 and by > 0
     with pytest.raises(amg.AmgError):
         S.time_kernel("restrict", reps=2)
+    S.release()
+    # the byte count covers one pre- and one post-sweep only
+    B, kw = _case("coupled16-sweeps22")
+    S = amg.Solver(B, **kw)
+    with pytest.raises(amg.AmgError):
+        S.time_kernel("vcycle", reps=2)
     S.release()
 
 
