@@ -120,18 +120,19 @@ def test_block_size_one_is_the_scalar_method(case):
     assert np.linalg.norm(zs - zb) <= 1e-12 * np.linalg.norm(zs)
 
 
-def test_decoupled_fields_are_four_scalar_amgs():
+@pytest.mark.parametrize("npre,npost", [(1, 1), (2, 3), (0, 2), (3, 0)])
+def test_decoupled_fields_are_four_scalar_amgs(npre, npost):
     N = 12
     g = problems.gaussian_field(N, 1.0, 8.0, 3)
     L = problems.diffusion3d(N, g)
     B = problems.decoupled_diffusion3d(N, g)
     c = np.diag(problems.blocks.DECOUPLED)
-    hb = ba.setup(_bsr(B), sa.Params(coarse_enough=4 * 60))
+    hb = ba.setup(_bsr(B), sa.Params(coarse_enough=4 * 60, npre=npre, npost=npost))
     f = np.random.default_rng(5).standard_normal(B.n)
     zb = ba.vcycle(hb, f)
     for k in range(4):
         Ak = problems.CSR(L.n, L.row_ptr, L.col, c[k] * L.val)
-        hs = sa.setup(Ak, sa.Params(coarse_enough=60))
+        hs = sa.setup(Ak, sa.Params(coarse_enough=60, npre=npre, npost=npost))
         assert hs.nlevels == hb.nlevels >= 3
         for ls, lb in zip(hs.levels[:-1], hb.levels[:-1]):
             assert np.array_equal(ls.agg, lb.agg)
@@ -232,10 +233,12 @@ def test_two_grid_closed_form_without_sweeps():
     assert np.linalg.norm(ba.vcycle(h, r) - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("relax", ["spai0", "jacobi"])
-def test_vcycle_operator_symmetric_spd_linear(relax):
+@pytest.mark.parametrize("relax,sweeps", [("spai0", 1), ("jacobi", 1), ("spai0", 2), ("jacobi", 3)])
+def test_vcycle_operator_symmetric_spd_linear(relax, sweeps):
+    # equal pre- and post-sweep counts, the post-sweeps applying M^T: the
+    # V-cycle is a symmetric positive definite linear operator
     A = _coupled(5)
-    h = ba.setup(A, sa.Params(coarse_enough=24, relax=relax))
+    h = ba.setup(A, sa.Params(coarse_enough=24, relax=relax, npre=sweeps, npost=sweeps))
     assert h.nlevels >= 3
     n = A.nb * 4
     Bm = np.column_stack([ba.vcycle(h, e) for e in np.eye(n)])
