@@ -301,12 +301,14 @@ def _pins_fail():
         test_block_inverse_matches_dense_inverse,
         test_block_product_spgemm_and_transpose_match_dense,
         lambda: test_block_size_one_is_the_scalar_method(0),
-        test_decoupled_fields_are_four_scalar_amgs,
+        lambda: test_decoupled_fields_are_four_scalar_amgs(1, 1),
+        lambda: test_decoupled_fields_are_four_scalar_amgs(2, 3),
         test_block_spai0_is_the_least_squares_minimiser,
         test_galerkin_is_dense_ptap_and_spd,
         test_prolongator_is_one_damped_block_jacobi_step_on_the_tentative_basis,
         test_two_grid_closed_form_without_sweeps,
-        lambda: test_vcycle_operator_symmetric_spd_linear("spai0"),
+        lambda: test_vcycle_operator_symmetric_spd_linear("spai0", 1),
+        lambda: test_vcycle_operator_symmetric_spd_linear("spai0", 2),
         test_field_permutation_permutes_the_vcycle,
         lambda: test_whole_block_solve_vs_dense("cg-spai0"),
     ]
